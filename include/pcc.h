@@ -1,0 +1,231 @@
+/*
+ * pcc.h -- C ABI of the MI355X (gfx950) library for cluster-preserving
+ * correction of lossy-compressed particle data.
+ *
+ * The method is that of "Preserving Clusters in Error-Bounded Lossy
+ * Compression of Scientific Particle Data" (Ren, Di, Heitmann, Cappello,
+ * Guo).  Its problem statement (Alg. 1: original positions P, base-compressed
+ * positions P^(0), error bound xi, linking length b, bit depth m, learning
+ * rate alpha, iteration cap T_max, loss tolerance eps_L and mode in; the
+ * compressed edit stream out) is the shape of pcc_correct.  The library adds
+ * the friends-of-friends labels of P (Sec. 2.4), a batched entry point for
+ * many independent snapshots, and a decoder (Sec. 3.3, "Reconstruction of
+ * the edited data").
+ *
+ * Conventions
+ *   - Every call returns a pcc_status; negative values are errors, the
+ *     message of the last error of the calling thread is pcc_last_error().
+ *   - Positions are structure-of-arrays float32 (x, y, z), n entries each.
+ *     pcc_particles.memspace says whether the pointers are host memory or
+ *     device memory of the context's GPU.  The library only reads them and
+ *     does not keep them after the call returns.
+ *   - Outputs are caller-allocated; the library allocates none.  Labels are
+ *     written to memory of the same memspace as the original particles.
+ *   - Work is queued on the HIP stream passed as `hip_stream` (NULL = the
+ *     default stream); a call returns when its results are complete.
+ *   - A context is bound to one device and is not thread-safe: calls that
+ *     share a context must not overlap.
+ */
+#ifndef PCC_H
+#define PCC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PCC_VERSION 1
+
+typedef int32_t pcc_status;
+enum {
+  PCC_OK = 0,
+  PCC_NOT_CONVERGED = 1,      /* warning: T_max reached with violations left;
+                                 the outputs are valid and inside the box */
+  PCC_E_INVALID_ARG = -1,     /* b <= 0, xi < 0, NaN/Inf input, m not in
+                                 {8,16,32}, n < 0, periodic side < 3 (b +
+                                 2 sqrt(3) xi), n >= 2^31, NULL pointers */
+  PCC_E_OUT_OF_MEMORY = -2,
+  PCC_E_DEVICE = -3,          /* a HIP runtime call failed */
+  PCC_E_BUFFER_TOO_SMALL = -4,/* stream_cap too small; *stream_len = need */
+  PCC_E_INPUT_BOUND = -5,     /* some |x_hat - x| > xi (Sec. 3.1 assumes
+                                 the base compressor honours the bound) */
+  PCC_E_UNSUPPORTED = -6,
+  PCC_E_CANCELLED = -7
+};
+
+/* constraint-selection modes, Sec. 3.2 */
+enum { PCC_MODE_VP = 0, PCC_MODE_SC = 1, PCC_MODE_HF = 2 };
+/* optimiser: Adam (Sec. 4.2) or the plain step printed in Alg. 1 */
+enum { PCC_OPT_ADAM = 0, PCC_OPT_SGD = 1 };
+/* safety margins, Sec. 3.3: SAFE also covers float32 rounding of the
+   decoded coordinates; PAPER uses xi(1 - 2^-m) and 2 sqrt(3) eps_q */
+enum { PCC_MARGIN_SAFE = 0, PCC_MARGIN_PAPER = 1 };
+enum { PCC_MEM_HOST = 0, PCC_MEM_DEVICE = 1 };
+
+typedef struct pcc_context pcc_context;
+
+/* Borrowed view of n particles, float32 structure of arrays. */
+typedef struct {
+  const float *x, *y, *z;
+  int64_t n;
+  int32_t memspace;  /* PCC_MEM_HOST or PCC_MEM_DEVICE */
+  int32_t reserved;
+} pcc_particles;
+
+/* Alg. 1 inputs; pcc_params_init fills the defaults. */
+typedef struct {
+  double b;              /* linking length, > 0 */
+  double xi;             /* absolute pointwise error bound, >= 0 */
+  int32_t mode;          /* PCC_MODE_*, default HF */
+  int32_t m_bits;        /* bit depth of quantised edits: 8, 16 (default), 32 */
+  int32_t optimizer;     /* PCC_OPT_*, default Adam */
+  int32_t margin_policy; /* PCC_MARGIN_*, default SAFE */
+  double lr;             /* alpha, default 1e-3 */
+  double beta1, beta2;   /* Adam, default 0.9, 0.999 */
+  double adam_eps;       /* Adam epsilon, default 1e-8 */
+  int64_t max_iters;     /* T_max; <= 0 selects the safety cap 100000 */
+  double loss_tol;       /* eps_L; 0 (default) stops when no selected pair is
+                            violated, > 0 stops when the tightened loss of
+                            Eq. 3 is <= loss_tol */
+  double box[3];         /* periodic side per axis; 0 = open axis (default) */
+} pcc_params;
+
+/* Caller-allocated outputs of one correction. */
+typedef struct {
+  int32_t *labels;       /* [n] FoF labels of the originals (smallest member
+                            index), memspace of the originals; may be NULL */
+  uint8_t *stream;       /* host buffer for the edit stream; may be NULL
+                            together with stream_cap = 0 */
+  size_t stream_cap;
+  size_t *stream_len;    /* host; set to the stream size (or the size needed) */
+  double *debug_xyz;     /* host [3][n] planar float64 coordinates before
+                            quantisation (the reconstruction for particles
+                            that were not edited); may be NULL */
+} pcc_outputs;
+
+#define PCC_NSTAGES 10
+/* stage timings, milliseconds of device time measured with HIP events:
+   0 input scan, 1 cell build, 2 pair pass (classify + components),
+   3 labels, 4 constraint selection, 5 editable set and CSR, 6 PGD,
+   7 device encoding, 8 host lossless stage, 9 total wall time */
+#define PCC_NKERNELS 8
+/* device time of the main kernels, summed over their launches, filled only
+   when kernel timing is on (pcc_context_set): 0 pair classify/hook pass,
+   1 pair count pass, 2 pair write pass, 3 PGD step, 4 PGD finalize,
+   5 cell-key sort, 6 pair and incidence sorts, 7 spanning-forest rounds */
+typedef struct {
+  int64_t n_pairs;       /* pairs with d <= b + 2 sqrt(3) xi */
+  int64_t n_safe, n_pb, n_pc;
+  int64_t n_active, n_editable, n_flagged;
+  int64_t iters;         /* gradient steps taken */
+  double loss0, loss_final;
+  int64_t viol0, viol_final;
+  int64_t bytes_flags, bytes_codes, bytes_stream;
+  double t_stage_ms[PCC_NSTAGES];
+  double kernel_ms[PCC_NKERNELS];
+  int64_t kernel_launches[PCC_NKERNELS];
+} pcc_stats;
+
+typedef struct {
+  pcc_particles orig;
+  pcc_particles recon;
+  pcc_params params;
+  pcc_outputs out;
+} pcc_job;
+
+typedef struct {
+  pcc_status status;
+  int32_t reserved;
+  pcc_stats stats;
+} pcc_job_result;
+
+int pcc_version(void);
+const char *pcc_status_string(pcc_status s);
+/* Thread-local message of the last error on this thread ("" if none). */
+const char *pcc_last_error(void);
+
+pcc_status pcc_context_create(int device, pcc_context **out);
+pcc_status pcc_context_destroy(pcc_context *ctx);
+
+/*
+ * Context options.
+ *   PCC_CTX_KERNEL_TIMING  0/1: bracket the main kernels with HIP events and
+ *                          report their device time in pcc_stats.kernel_ms;
+ *                          the PGD iterations are then launched one by one
+ *                          instead of as a captured graph.  Default 0.
+ *   PCC_CTX_GRAPH_ITERS    PGD iterations per captured graph launch (1..64,
+ *                          default 8); one small readback follows each launch.
+ */
+enum { PCC_CTX_KERNEL_TIMING = 1, PCC_CTX_GRAPH_ITERS = 2 };
+pcc_status pcc_context_set(pcc_context *ctx, int32_t key, int64_t value);
+
+void pcc_params_init(pcc_params *p);
+
+/* Upper bound of the edit stream size for n particles. */
+size_t pcc_stream_bound(int64_t n, const pcc_params *p);
+
+/*
+ * The correction pass of Alg. 1 on one snapshot: cell build, pair search and
+ * classification (Sec. 3.1), FoF and safe components (Sec. 2.4, 3.2),
+ * constraint selection (Sec. 3.2), PGD with Adam and box projection
+ * (Alg. 1, Eq. 2-3), edit encoding (flags, m-bit edits, Huffman + ZSTD).
+ * orig and recon must have the same n and memspace.  stats may be NULL.
+ * Returns PCC_OK, PCC_NOT_CONVERGED or an error.
+ */
+pcc_status pcc_correct(pcc_context *ctx, const pcc_particles *orig,
+                       const pcc_particles *recon, const pcc_params *params,
+                       pcc_outputs *out, pcc_stats *stats, void *hip_stream);
+
+/*
+ * Many independent snapshots in one pass: every stage is one launch over all
+ * jobs, the PGD iterations of all jobs run together and a job that has
+ * converged is masked out.  Each job's results equal those of pcc_correct on
+ * that job alone.  results[k].status holds each job's status; the return
+ * value is PCC_OK unless a job failed (then the first job error).
+ */
+pcc_status pcc_correct_batch(pcc_context *ctx, const pcc_job *jobs, int32_t njobs,
+                             pcc_job_result *results, void *hip_stream);
+
+/*
+ * Decode an edit stream and apply it to the reconstruction (Sec. 3.3):
+ * out = float32(x_hat + edit) for flagged particles, x_hat bit-exactly for
+ * the others.  recon and out are host arrays of n entries each.
+ */
+pcc_status pcc_decode(const uint8_t *stream, size_t len, const pcc_particles *recon,
+                      float *out_x, float *out_y, float *out_z);
+
+/*
+ * Friends-of-friends labels (Sec. 2.4) of a point set at linking length b:
+ * labels[k] is the smallest index in k's cluster.  box as in pcc_params.
+ * labels has the memspace of pts.
+ */
+pcc_status pcc_fof_labels(pcc_context *ctx, const pcc_particles *pts, double b,
+                          const double box[3], int32_t *labels, void *hip_stream);
+
+/*
+ * Test hook: copy an intermediate result of job `job` of the last
+ * pcc_correct / pcc_correct_batch call on this context into host memory.
+ * Pair lists use particle indices of the job with i < j, unsorted.
+ *   PCC_DBG_ACTIVE_I / _J   uint32 [n_active]  active pairs
+ *   PCC_DBG_ACTIVE_TYPE     uint8  [n_active]  2 = potentially broken,
+ *                                              3 = potentially created
+ *   PCC_DBG_SAFE_LABELS     int32  [n]         safe-component labels
+ *   PCC_DBG_EDITABLE        uint32 [n_editable] editable particles, unsorted
+ * *count receives the element count; nothing is copied if cap < count.
+ */
+enum {
+  PCC_DBG_ACTIVE_I = 1,
+  PCC_DBG_ACTIVE_J = 2,
+  PCC_DBG_ACTIVE_TYPE = 3,
+  PCC_DBG_SAFE_LABELS = 4,
+  PCC_DBG_EDITABLE = 5
+};
+pcc_status pcc_debug_fetch(pcc_context *ctx, int32_t job, int32_t what, void *host_dst,
+                           int64_t cap, int64_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,312 @@
+"""ctypes binding of libpcc.so (include/pcc.h): argument marshalling only.
+
+Device arrays are torch tensors on the GPU (torch supplies device memory and
+the current HIP stream); host arrays are numpy.  Every computation happens in
+the library; when it is missing, loading fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpcc.so")
+
+OK, NOT_CONVERGED = 0, 1
+MODES = {"vp": 0, "sc": 1, "hf": 2}
+MEM_HOST, MEM_DEVICE = 0, 1
+NSTAGES = 10
+NKERNELS = 8
+KERNEL_NAMES = ("pair_classify", "pair_count", "pair_write", "pgd_step", "pgd_finalize",
+                "cell_sort", "pair_csr_sort", "forest")
+STAGE_NAMES = ("input_scan", "cell_build", "pair_pass", "labels", "selection", "csr", "pgd",
+               "encode_device", "lossless_host", "total_wall")
+
+
+class PccError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("pcc status %d: %s" % (status, msg))
+        self.status = status
+
+
+class Particles(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("n", C.c_int64),
+                ("memspace", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [("b", C.c_double), ("xi", C.c_double), ("mode", C.c_int32),
+                ("m_bits", C.c_int32), ("optimizer", C.c_int32), ("margin_policy", C.c_int32),
+                ("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("adam_eps", C.c_double), ("max_iters", C.c_int64), ("loss_tol", C.c_double),
+                ("box", C.c_double * 3)]
+
+
+class Outputs(C.Structure):
+    _fields_ = [("labels", C.c_void_p), ("stream", C.c_void_p), ("stream_cap", C.c_size_t),
+                ("stream_len", C.POINTER(C.c_size_t)), ("debug_xyz", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_pairs", C.c_int64), ("n_safe", C.c_int64), ("n_pb", C.c_int64),
+                ("n_pc", C.c_int64), ("n_active", C.c_int64), ("n_editable", C.c_int64),
+                ("n_flagged", C.c_int64), ("iters", C.c_int64), ("loss0", C.c_double),
+                ("loss_final", C.c_double), ("viol0", C.c_int64), ("viol_final", C.c_int64),
+                ("bytes_flags", C.c_int64), ("bytes_codes", C.c_int64),
+                ("bytes_stream", C.c_int64), ("t_stage_ms", C.c_double * NSTAGES),
+                ("kernel_ms", C.c_double * NKERNELS), ("kernel_launches", C.c_int64 * NKERNELS)]
+
+
+class Job(C.Structure):
+    _fields_ = [("orig", Particles), ("recon", Particles), ("params", Params), ("out", Outputs)]
+
+
+class JobResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("reserved", C.c_int32), ("stats", Stats)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libpcc.so (built by __graft_entry__.build or build_lib.py)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libpcc.so is not built (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        L.pcc_version.restype = C.c_int
+        L.pcc_status_string.restype = C.c_char_p
+        L.pcc_status_string.argtypes = [C.c_int32]
+        L.pcc_last_error.restype = C.c_char_p
+        L.pcc_context_create.argtypes = [C.c_int, C.POINTER(C.c_void_p)]
+        L.pcc_context_destroy.argtypes = [C.c_void_p]
+        L.pcc_params_init.argtypes = [C.POINTER(Params)]
+        L.pcc_params_init.restype = None
+        L.pcc_stream_bound.argtypes = [C.c_int64, C.POINTER(Params)]
+        L.pcc_stream_bound.restype = C.c_size_t
+        L.pcc_correct.argtypes = [C.c_void_p, C.POINTER(Particles), C.POINTER(Particles),
+                                  C.POINTER(Params), C.POINTER(Outputs), C.POINTER(Stats),
+                                  C.c_void_p]
+        L.pcc_correct_batch.argtypes = [C.c_void_p, C.POINTER(Job), C.c_int32,
+                                        C.POINTER(JobResult), C.c_void_p]
+        L.pcc_decode.argtypes = [C.c_void_p, C.c_size_t, C.POINTER(Particles), C.c_void_p,
+                                 C.c_void_p, C.c_void_p]
+        L.pcc_fof_labels.argtypes = [C.c_void_p, C.POINTER(Particles), C.c_double,
+                                     C.POINTER(C.c_double), C.c_void_p, C.c_void_p]
+        L.pcc_context_set.argtypes = [C.c_void_p, C.c_int32, C.c_int64]
+        L.pcc_debug_fetch.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int64,
+                                      C.POINTER(C.c_int64)]
+        for name in ("pcc_context_create", "pcc_context_destroy", "pcc_correct",
+                     "pcc_correct_batch", "pcc_decode", "pcc_fof_labels", "pcc_debug_fetch",
+                     "pcc_context_set"):
+            getattr(L, name).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _check(status: int) -> int:
+    if status < 0:
+        raise PccError(status, lib().pcc_last_error().decode() or
+                       lib().pcc_status_string(status).decode())
+    return status
+
+
+def stats_dict(s: Stats) -> Dict:
+    d = {k: getattr(s, k) for k, _ in Stats._fields_
+         if k not in ("t_stage_ms", "kernel_ms", "kernel_launches")}
+    d["t_stage_ms"] = {STAGE_NAMES[k]: s.t_stage_ms[k] for k in range(NSTAGES)}
+    d["kernel_ms"] = {KERNEL_NAMES[k]: s.kernel_ms[k] for k in range(NKERNELS)}
+    d["kernel_launches"] = {KERNEL_NAMES[k]: s.kernel_launches[k] for k in range(NKERNELS)}
+    return d
+
+
+def make_params(b: float, xi: float, mode="hf", box=None, m_bits=16, optimizer="adam",
+                lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8, max_iters=0, loss_tol=0.0,
+                margin="safe") -> Params:
+    p = Params()
+    lib().pcc_params_init(C.byref(p))
+    p.b, p.xi = float(b), float(xi)
+    p.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+    p.m_bits = int(m_bits)
+    p.optimizer = {"adam": 0, "sgd": 1}[optimizer]
+    p.margin_policy = {"safe": 0, "paper": 1}[margin]
+    p.lr, p.beta1, p.beta2, p.adam_eps = float(lr), float(beta1), float(beta2), float(adam_eps)
+    p.max_iters = int(max_iters)
+    p.loss_tol = float(loss_tol)
+    for k, v in enumerate(box or (0.0, 0.0, 0.0)):
+        p.box[k] = float(v)
+    return p
+
+
+def _view(a) -> Tuple[Particles, object]:
+    """Particles view of a (3, N) float32 array: torch GPU tensor or numpy."""
+    try:
+        import torch
+        if isinstance(a, torch.Tensor):
+            if a.dtype != torch.float32 or a.dim() != 2 or a.shape[0] != 3:
+                raise ValueError("expected a (3, N) float32 tensor")
+            a = a.contiguous()
+            mem = MEM_DEVICE if a.is_cuda else MEM_HOST
+            base, st = a.data_ptr(), a.stride(0) * a.element_size()
+            return Particles(base, base + st, base + 2 * st, a.shape[1], mem, 0), a
+    except ImportError:
+        pass
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if a.ndim != 2 or a.shape[0] != 3:
+        raise ValueError("expected a (3, N) float32 array")
+    base, st = a.ctypes.data, a.strides[0]
+    return Particles(base, base + st, base + 2 * st, a.shape[1], MEM_HOST, 0), a
+
+
+def _stream_handle(on_device: bool):
+    if not on_device:
+        return None
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """A library context bound to one GPU."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        _check(lib().pcc_context_create(int(device), C.byref(h)))
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pcc_context_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_option(self, key: str, value: int):
+        code = {"kernel_timing": 1, "graph_iters": 2}[key]
+        _check(lib().pcc_context_set(self._h, code, int(value)))
+
+    # ------------------------------------------------------------------
+    def correct(self, orig, recon, b: float, xi: float, mode="hf", box=None, labels=True,
+                debug_xyz=False, stream_cap: Optional[int] = None, **opts):
+        """Alg. 1 on one snapshot.  Returns (stream bytes, labels, stats);
+        labels live where `orig` lives; stats['status'] is 0 or 1."""
+        po, ko = _view(orig)
+        pr, kr = _view(recon)
+        n = po.n
+        params = make_params(b, xi, mode=mode, box=box, **opts)
+        cap = int(stream_cap) if stream_cap is not None else lib().pcc_stream_bound(n, C.byref(params))
+        sbuf = np.zeros(max(cap, 1), dtype=np.uint8)
+        slen = C.c_size_t(0)
+        lab = None
+        lab_ptr = None
+        if labels:
+            if po.memspace == MEM_DEVICE:
+                import torch
+                lab = torch.empty(max(n, 1), dtype=torch.int32, device=ko.device)
+                lab_ptr = lab.data_ptr()
+            else:
+                lab = np.zeros(max(n, 1), dtype=np.int32)
+                lab_ptr = lab.ctypes.data
+        dbg = np.zeros((3, max(n, 1)), dtype=np.float64) if debug_xyz else None
+        out = Outputs(lab_ptr, sbuf.ctypes.data, cap, C.pointer(slen),
+                      dbg.ctypes.data if dbg is not None else None)
+        st = Stats()
+        status = lib().pcc_correct(self._h, C.byref(po), C.byref(pr), C.byref(params),
+                                   C.byref(out), C.byref(st),
+                                   _stream_handle(po.memspace == MEM_DEVICE))
+        _check(status)
+        stats = stats_dict(st)
+        stats["status"] = status
+        res_lab = lab[:n] if lab is not None else None
+        if dbg is not None:
+            stats["debug_xyz"] = dbg[:, :n]
+        return bytes(sbuf[: slen.value]), res_lab, stats
+
+    def correct_batch(self, jobs: Sequence[Dict]):
+        """jobs: dicts with orig, recon, b, xi and optional mode, box, opts.
+        Returns a list of (status, stream bytes, labels, stats)."""
+        cj = (Job * len(jobs))()
+        keep, bufs = [], []
+        on_dev = False
+        for k, jd in enumerate(jobs):
+            po, ko = _view(jd["orig"])
+            pr, kr = _view(jd["recon"])
+            on_dev |= po.memspace == MEM_DEVICE
+            opts = dict(jd.get("opts", {}))
+            params = make_params(jd["b"], jd["xi"], mode=jd.get("mode", "hf"), box=jd.get("box"),
+                                 **opts)
+            cap = lib().pcc_stream_bound(po.n, C.byref(params))
+            sbuf = np.zeros(max(cap, 1), dtype=np.uint8)
+            slen = C.c_size_t(0)
+            if po.memspace == MEM_DEVICE:
+                import torch
+                lab = torch.empty(max(po.n, 1), dtype=torch.int32, device=ko.device)
+                lptr = lab.data_ptr()
+            else:
+                lab = np.zeros(max(po.n, 1), dtype=np.int32)
+                lptr = lab.ctypes.data
+            dbg = np.zeros((3, max(po.n, 1)), dtype=np.float64) if jd.get("debug_xyz") else None
+            cj[k].orig, cj[k].recon, cj[k].params = po, pr, params
+            cj[k].out = Outputs(lptr, sbuf.ctypes.data, cap, C.pointer(slen),
+                                dbg.ctypes.data if dbg is not None else None)
+            keep.append((ko, kr))
+            bufs.append((sbuf, slen, lab, dbg, po.n))
+        res = (JobResult * len(jobs))()
+        lib().pcc_correct_batch(self._h, cj, len(jobs), res, _stream_handle(on_dev))
+        out = []
+        for k, (sbuf, slen, lab, dbg, n) in enumerate(bufs):
+            st = stats_dict(res[k].stats)
+            st["status"] = res[k].status
+            if dbg is not None:
+                st["debug_xyz"] = dbg[:, :n]
+            out.append((res[k].status, bytes(sbuf[: slen.value]), lab[:n], st))
+        return out
+
+    def fof_labels(self, pts, b: float, box=None):
+        p, keep = _view(pts)
+        n = p.n
+        if p.memspace == MEM_DEVICE:
+            import torch
+            lab = torch.empty(max(n, 1), dtype=torch.int32, device=keep.device)
+            ptr = lab.data_ptr()
+        else:
+            lab = np.zeros(max(n, 1), dtype=np.int32)
+            ptr = lab.ctypes.data
+        bx = (C.c_double * 3)(*[float(v) for v in (box or (0.0, 0.0, 0.0))])
+        _check(lib().pcc_fof_labels(self._h, C.byref(p), float(b), bx, C.c_void_p(ptr),
+                                    _stream_handle(p.memspace == MEM_DEVICE)))
+        return lab[:n]
+
+    def debug_fetch(self, job: int, what: str):
+        code = {"active_i": 1, "active_j": 2, "active_type": 3, "safe_labels": 4,
+                "editable": 5}[what]
+        dtype = {1: np.uint32, 2: np.uint32, 3: np.uint8, 4: np.int32, 5: np.uint32}[code]
+        cnt = C.c_int64(0)
+        _check(lib().pcc_debug_fetch(self._h, int(job), code, None, 0, C.byref(cnt)))
+        buf = np.zeros(max(cnt.value, 1), dtype=dtype)
+        _check(lib().pcc_debug_fetch(self._h, int(job), code, buf.ctypes.data, cnt.value,
+                                     C.byref(cnt)))
+        return buf[: cnt.value]
+
+
+def decode(stream: bytes, recon: np.ndarray) -> np.ndarray:
+    """Apply an edit stream to a host (3, N) float32 reconstruction."""
+    pr, kr = _view(np.asarray(recon, dtype=np.float32))
+    n = pr.n
+    out = np.zeros((3, max(n, 1)), dtype=np.float32)
+    buf = np.frombuffer(stream, dtype=np.uint8).copy()
+    _check(lib().pcc_decode(buf.ctypes.data, len(buf), C.byref(pr), out[0].ctypes.data,
+                            out[1].ctypes.data, out[2].ctypes.data))
+    return out[:, :n]
+
+
+def version() -> int:
+    return lib().pcc_version()

@@ -1,0 +1,329 @@
+// C ABI of include/pcc.h: argument checks, context management, error
+// reporting; every entry point catches all exceptions at this boundary.
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "host.hpp"
+
+struct pcc_context {
+  pcc::Context c;
+};
+
+namespace {
+thread_local std::string g_err;
+
+pcc_status fail(pcc_status s, const std::string &m) {
+  g_err = m;
+  return s;
+}
+
+template <typename F>
+pcc_status guarded(F &&f) {
+  try {
+    g_err.clear();
+    return f();
+  } catch (const pcc::Error &e) {
+    return fail(e.status, e.what());
+  } catch (const std::bad_alloc &) {
+    return fail(PCC_E_OUT_OF_MEMORY, "host allocation failed");
+  } catch (const std::exception &e) {
+    return fail(PCC_E_DEVICE, e.what());
+  }
+}
+
+hipStream_t pick(pcc_context *ctx, void *s) {
+  return s ? (hipStream_t)s : ctx->c.own;
+}
+}  // namespace
+
+extern "C" {
+
+int pcc_version(void) { return PCC_VERSION; }
+
+const char *pcc_status_string(pcc_status s) {
+  switch (s) {
+    case PCC_OK: return "ok";
+    case PCC_NOT_CONVERGED: return "not converged (iteration cap reached)";
+    case PCC_E_INVALID_ARG: return "invalid argument";
+    case PCC_E_OUT_OF_MEMORY: return "out of memory";
+    case PCC_E_DEVICE: return "device error";
+    case PCC_E_BUFFER_TOO_SMALL: return "buffer too small";
+    case PCC_E_INPUT_BOUND: return "reconstruction outside the error bound";
+    case PCC_E_UNSUPPORTED: return "unsupported";
+    case PCC_E_CANCELLED: return "cancelled";
+    default: return "unknown status";
+  }
+}
+
+const char *pcc_last_error(void) { return g_err.c_str(); }
+
+pcc_status pcc_context_set(pcc_context *ctx, int32_t key, int64_t value) {
+  if (!ctx) return fail(PCC_E_INVALID_ARG, "NULL context");
+  if (key == PCC_CTX_KERNEL_TIMING) {
+    if (value != 0 && value != 1) return fail(PCC_E_INVALID_ARG, "kernel timing is 0 or 1");
+    ctx->c.kt.on = value != 0;
+    return PCC_OK;
+  }
+  if (key == PCC_CTX_GRAPH_ITERS) {
+    if (value < 1 || value > 64) return fail(PCC_E_INVALID_ARG, "graph iterations lie in 1..64");
+    ctx->c.graph_iters = (int)value;
+    return PCC_OK;
+  }
+  return fail(PCC_E_INVALID_ARG, "unknown context option");
+}
+
+void pcc_params_init(pcc_params *p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->mode = PCC_MODE_HF;
+  p->m_bits = 16;
+  p->optimizer = PCC_OPT_ADAM;
+  p->margin_policy = PCC_MARGIN_SAFE;
+  p->lr = 1e-3;
+  p->beta1 = 0.9;
+  p->beta2 = 0.999;
+  p->adam_eps = 1e-8;
+  p->max_iters = 0;
+  p->loss_tol = 0.0;
+}
+
+size_t pcc_stream_bound(int64_t n, const pcc_params *p) {
+  return pcc::stream_bound(n, p ? p->m_bits : 16);
+}
+
+pcc_status pcc_context_create(int device, pcc_context **out) {
+  if (!out) return fail(PCC_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  return guarded([&]() -> pcc_status {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count == 0)
+      return fail(PCC_E_DEVICE, "no HIP device is visible");
+    if (device < 0 || device >= count) return fail(PCC_E_INVALID_ARG, "device index out of range");
+    PCC_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    PCC_HIP(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+      return fail(PCC_E_UNSUPPORTED, std::string("built for gfx950, device is ") + prop.gcnArchName);
+    auto *c = new pcc_context;
+    c->c.device = device;
+    if (hipStreamCreate(&c->c.own) != hipSuccess) {
+      delete c;
+      return fail(PCC_E_DEVICE, "hipStreamCreate failed");
+    }
+    *out = c;
+    return PCC_OK;
+  });
+}
+
+pcc_status pcc_context_destroy(pcc_context *ctx) {
+  if (!ctx) return PCC_OK;
+  hipSetDevice(ctx->c.device);
+  hipDeviceSynchronize();
+  ctx->c.arena.release();
+  for (auto &t : ctx->c.bc) hipFree(t.dev);
+  for (auto &e : ctx->c.ev)
+    if (e) hipEventDestroy(e);
+  if (ctx->c.pinned) hipHostFree(ctx->c.pinned);
+  if (ctx->c.own) hipStreamDestroy(ctx->c.own);
+  delete ctx;
+  return PCC_OK;
+}
+
+pcc_status pcc_correct(pcc_context *ctx, const pcc_particles *orig, const pcc_particles *recon,
+                       const pcc_params *params, pcc_outputs *out, pcc_stats *stats,
+                       void *hip_stream) {
+  if (!ctx || !orig || !recon || !params || !out)
+    return fail(PCC_E_INVALID_ARG, "NULL argument");
+  return guarded([&]() -> pcc_status {
+    pcc_job job;
+    job.orig = *orig;
+    job.recon = *recon;
+    job.params = *params;
+    job.out = *out;
+    pcc_job_result r;
+    std::memset(&r, 0, sizeof r);
+    pcc::run_batch(ctx->c, &job, 1, &r, pick(ctx, hip_stream), false);
+    if (stats) *stats = r.stats;
+    if (r.status < 0 && g_err.empty()) g_err = pcc_status_string(r.status);
+    return r.status;
+  });
+}
+
+pcc_status pcc_correct_batch(pcc_context *ctx, const pcc_job *jobs, int32_t njobs,
+                             pcc_job_result *results, void *hip_stream) {
+  if (!ctx || njobs < 0 || (njobs > 0 && (!jobs || !results)))
+    return fail(PCC_E_INVALID_ARG, "NULL argument");
+  return guarded([&]() -> pcc_status {
+    if (njobs == 0) return PCC_OK;
+    return pcc::run_batch(ctx->c, jobs, njobs, results, pick(ctx, hip_stream), false);
+  });
+}
+
+pcc_status pcc_decode(const uint8_t *stream, size_t len, const pcc_particles *recon, float *ox,
+                      float *oy, float *oz) {
+  if (!stream || !recon) return fail(PCC_E_INVALID_ARG, "NULL argument");
+  if (recon->memspace != PCC_MEM_HOST) return fail(PCC_E_UNSUPPORTED, "decode takes host arrays");
+  if (recon->n > 0 && (!recon->x || !recon->y || !recon->z || !ox || !oy || !oz))
+    return fail(PCC_E_INVALID_ARG, "NULL coordinate pointer");
+  return guarded([&]() -> pcc_status {
+    std::string err;
+    pcc_status s = pcc::decode_stream(stream, len, recon->n, recon->x, recon->y, recon->z, ox, oy,
+                                      oz, err);
+    if (s != PCC_OK) g_err = err;
+    return s;
+  });
+}
+
+pcc_status pcc_fof_labels(pcc_context *ctx, const pcc_particles *pts, double b,
+                          const double box[3], int32_t *labels, void *hip_stream) {
+  if (!ctx || !pts || !labels) return fail(PCC_E_INVALID_ARG, "NULL argument");
+  return guarded([&]() -> pcc_status {
+    pcc_job job;
+    std::memset(&job, 0, sizeof job);
+    job.orig = *pts;
+    job.recon = *pts;
+    pcc_params_init(&job.params);
+    job.params.b = b;
+    job.params.xi = 0.0;
+    if (box)
+      for (int a = 0; a < 3; ++a) job.params.box[a] = box[a];
+    job.out.labels = labels;
+    pcc_job_result r;
+    std::memset(&r, 0, sizeof r);
+    pcc::run_batch(ctx->c, &job, 1, &r, pick(ctx, hip_stream), true);
+    if (r.status < 0 && g_err.empty()) g_err = pcc_status_string(r.status);
+    return r.status < 0 ? r.status : PCC_OK;
+  });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// test hook
+// ---------------------------------------------------------------------------
+namespace pcc {
+namespace {
+__global__ void k_dbg_pairs(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t, size_t na,
+                            const float4 *pos, const int64_t *p_off, int njobs, int32_t *job,
+                            uint32_t *lo, uint32_t *hi, uint8_t *t) {
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < na;
+       p += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t i = __float_as_uint(pos[a_i[p]].w), j = __float_as_uint(pos[a_j[p]].w);
+    job[p] = job_of(p_off, njobs, (int64_t)a_i[p]);
+    lo[p] = i < j ? i : j;
+    hi[p] = i < j ? j : i;
+    t[p] = a_t[p];
+  }
+}
+__global__ void k_dbg_safe(const uint32_t *root, const float4 *pos, size_t n, int32_t *lab_sorted_root) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (size_t)gridDim.x * blockDim.x)
+    atomicMin(lab_sorted_root + root[k], (int32_t)__float_as_uint(pos[k].w));
+}
+__global__ void k_dbg_safe2(const uint32_t *root, const float4 *pos, const int64_t *p_off, int njobs,
+                            size_t n, const int32_t *minid, int32_t *out) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (size_t)gridDim.x * blockDim.x) {
+    const int j = job_of(p_off, njobs, (int64_t)k);
+    out[p_off[j] + __float_as_uint(pos[k].w)] = minid[root[k]];
+  }
+}
+__global__ void k_dbg_e(const uint32_t *e_list, size_t ne, const float4 *pos, const int64_t *p_off,
+                        int njobs, int32_t *job, uint32_t *id) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne;
+       e += (size_t)gridDim.x * blockDim.x) {
+    job[e] = job_of(p_off, njobs, (int64_t)e_list[e]);
+    id[e] = __float_as_uint(pos[e_list[e]].w);
+  }
+}
+}  // namespace
+}  // namespace pcc
+
+extern "C" pcc_status pcc_debug_fetch(pcc_context *ctx, int32_t job, int32_t what, void *host_dst,
+                                      int64_t cap, int64_t *count) {
+  if (!ctx || !count) return fail(PCC_E_INVALID_ARG, "NULL argument");
+  return guarded([&]() -> pcc_status {
+    using namespace pcc;
+    LastCall &L = ctx->c.last;
+    if (!L.valid) return fail(PCC_E_INVALID_ARG, "no retained call");
+    int q = -1;
+    for (int k = 0; k < (int)L.job_index.size(); ++k)
+      if (L.job_index[k] == job) q = k;
+    if (q < 0) return fail(PCC_E_INVALID_ARG, "job was not part of the last call");
+    hipStream_t s = ctx->c.own;
+    PCC_HIP(hipSetDevice(ctx->c.device));
+    Arena scratch;
+    int64_t *d_poff = scratch.get<int64_t>(L.p_off.size());
+    PCC_HIP(hipMemcpyAsync(d_poff, L.p_off.data(), L.p_off.size() * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s));
+    const int64_t n_job = L.p_off[q + 1] - L.p_off[q];
+    if (what == PCC_DBG_SAFE_LABELS) {
+      *count = n_job;
+      if (cap < n_job || !host_dst) return PCC_OK;
+      int32_t *minid = scratch.get<int32_t>(L.n ? L.n : 1), *out = scratch.get<int32_t>(L.n ? L.n : 1);
+      fill_u32((uint32_t *)minid, 0x7fffffffu, L.n, s);
+      k_dbg_safe<<<blocks_for(L.n, 256, 65536), 256, 0, s>>>(L.safe_root, L.pos, L.n, minid);
+      k_dbg_safe2<<<blocks_for(L.n, 256, 65536), 256, 0, s>>>(L.safe_root, L.pos, d_poff, L.njobs,
+                                                               L.n, minid, out);
+      PCC_HIP(hipMemcpyAsync(host_dst, out + L.p_off[q], n_job * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s));
+      PCC_HIP(hipStreamSynchronize(s));
+      return PCC_OK;
+    }
+    if (what == PCC_DBG_EDITABLE) {
+      const size_t ne = L.ne ? L.ne : 1;
+      int32_t *jb = scratch.get<int32_t>(ne);
+      uint32_t *id = scratch.get<uint32_t>(ne);
+      if (L.ne)
+        k_dbg_e<<<blocks_for(L.ne, 256, 65536), 256, 0, s>>>(L.e_list, L.ne, L.pos, d_poff, L.njobs,
+                                                            jb, id);
+      std::vector<int32_t> hj(L.ne);
+      std::vector<uint32_t> hid(L.ne);
+      if (L.ne) {
+        PCC_HIP(hipMemcpyAsync(hj.data(), jb, L.ne * 4, hipMemcpyDeviceToHost, s));
+        PCC_HIP(hipMemcpyAsync(hid.data(), id, L.ne * 4, hipMemcpyDeviceToHost, s));
+      }
+      PCC_HIP(hipStreamSynchronize(s));
+      std::vector<uint32_t> sel;
+      for (size_t e = 0; e < L.ne; ++e)
+        if (hj[e] == q) sel.push_back(hid[e]);
+      *count = (int64_t)sel.size();
+      if (host_dst && cap >= *count) std::memcpy(host_dst, sel.data(), sel.size() * 4);
+      return PCC_OK;
+    }
+    if (what == PCC_DBG_ACTIVE_I || what == PCC_DBG_ACTIVE_J || what == PCC_DBG_ACTIVE_TYPE) {
+      const size_t na = L.na ? L.na : 1;
+      int32_t *jb = scratch.get<int32_t>(na);
+      uint32_t *lo = scratch.get<uint32_t>(na), *hi = scratch.get<uint32_t>(na);
+      uint8_t *t = scratch.get<uint8_t>(na);
+      if (L.na)
+        k_dbg_pairs<<<blocks_for(L.na, 256, 65536), 256, 0, s>>>(L.a_i, L.a_j, L.a_t, L.na, L.pos,
+                                                                 d_poff, L.njobs, jb, lo, hi, t);
+      std::vector<int32_t> hj(L.na);
+      std::vector<uint32_t> hl(L.na), hh(L.na);
+      std::vector<uint8_t> ht(L.na);
+      if (L.na) {
+        PCC_HIP(hipMemcpyAsync(hj.data(), jb, L.na * 4, hipMemcpyDeviceToHost, s));
+        PCC_HIP(hipMemcpyAsync(hl.data(), lo, L.na * 4, hipMemcpyDeviceToHost, s));
+        PCC_HIP(hipMemcpyAsync(hh.data(), hi, L.na * 4, hipMemcpyDeviceToHost, s));
+        PCC_HIP(hipMemcpyAsync(ht.data(), t, L.na, hipMemcpyDeviceToHost, s));
+      }
+      PCC_HIP(hipStreamSynchronize(s));
+      int64_t c = 0;
+      for (size_t p = 0; p < L.na; ++p) c += hj[p] == q;
+      *count = c;
+      if (!host_dst || cap < c) return PCC_OK;
+      int64_t w = 0;
+      for (size_t p = 0; p < L.na; ++p) {
+        if (hj[p] != q) continue;
+        if (what == PCC_DBG_ACTIVE_I) ((uint32_t *)host_dst)[w] = hl[p];
+        if (what == PCC_DBG_ACTIVE_J) ((uint32_t *)host_dst)[w] = hh[p];
+        if (what == PCC_DBG_ACTIVE_TYPE) ((uint8_t *)host_dst)[w] = ht[p];
+        ++w;
+      }
+      return PCC_OK;
+    }
+    return fail(PCC_E_INVALID_ARG, "unknown debug item");
+  });
+}

@@ -1,0 +1,248 @@
+// Cell build (Sec. 2.4.1 cell linking; Sec. 3.3 cell side >= b + 2 sqrt(3) xi):
+// input scan, cell keys of the original positions, gather of the sorted
+// structure of arrays, unique cells by boundary detection and the forward
+// half-shell of 13 neighbour cells.
+#include "kernels.hpp"
+
+#include <cfloat>
+
+namespace pcc {
+
+template <typename T>
+__device__ inline T wave_reduce_min(T v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v = fminf(v, __shfl_xor(v, d, kWave));
+  return v;
+}
+template <typename T>
+__device__ inline T wave_reduce_max(T v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, kWave));
+  return v;
+}
+__device__ inline uint32_t wave_reduce_add(uint32_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
+// One block per tile of one job: extent of the originals, largest magnitude,
+// and the count of values that are not finite or break |x_hat - x| <= xi.
+__global__ void __launch_bounds__(256)
+k_scan_inputs(const Tile *tiles, Soa3 o, Soa3 r, const double *xi_job, ScanPart *parts) {
+  __shared__ float smn[3][4], smx[3][4], sab[4];
+  __shared__ uint32_t sbb[4], sbv[4];
+  const Tile t = tiles[blockIdx.x];
+  const double xi = xi_job[t.job];
+  float mn[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, mx[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
+  float ab = 0.f;
+  uint32_t bb = 0, bv = 0;
+  for (int64_t g = t.start + threadIdx.x; g < t.end; g += blockDim.x) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float xv = o.a[a][g], rv = r.a[a][g];
+      if (!isfinite(xv) || !isfinite(rv)) {
+        bv++;
+        continue;
+      }
+      mn[a] = fminf(mn[a], xv);
+      mx[a] = fmaxf(mx[a], xv);
+      ab = fmaxf(ab, fmaxf(fabsf(xv), fabsf(rv)));
+      if (fabs((double)rv - (double)xv) > xi) bb++;
+    }
+  }
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    mn[a] = wave_reduce_min(mn[a]);
+    mx[a] = wave_reduce_max(mx[a]);
+  }
+  ab = wave_reduce_max(ab);
+  bb = wave_reduce_add(bb);
+  bv = wave_reduce_add(bv);
+  if (lane == 0) {
+    for (int a = 0; a < 3; ++a) {
+      smn[a][w] = mn[a];
+      smx[a][w] = mx[a];
+    }
+    sab[w] = ab;
+    sbb[w] = bb;
+    sbv[w] = bv;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ScanPart p;
+    for (int a = 0; a < 3; ++a) {
+      p.mn[a] = fminf(fminf(smn[a][0], smn[a][1]), fminf(smn[a][2], smn[a][3]));
+      p.mx[a] = fmaxf(fmaxf(smx[a][0], smx[a][1]), fmaxf(smx[a][2], smx[a][3]));
+    }
+    p.maxabs = fmaxf(fmaxf(sab[0], sab[1]), fmaxf(sab[2], sab[3]));
+    p.bad_bound = sbb[0] + sbb[1] + sbb[2] + sbb[3];
+    p.bad_value = sbv[0] + sbv[1] + sbv[2] + sbv[3];
+    p.job = (uint32_t)t.job;
+    parts[blockIdx.x] = p;
+  }
+}
+
+void launch_scan_inputs(const Tile *tiles, int ntiles, Soa3 o, Soa3 r, const double *xi_job,
+                        ScanPart *parts, hipStream_t s) {
+  if (ntiles) k_scan_inputs<<<ntiles, 256, 0, s>>>(tiles, o, r, xi_job, parts);
+}
+
+// cell coordinate along one axis of the job's grid
+__device__ inline int64_t cell_coord(double x, double origin, double inv_w, int nc, bool periodic) {
+  if (nc <= 1) return 0;
+  int64_t c = (int64_t)floor((x - origin) * inv_w);
+  if (periodic) {
+    c %= nc;
+    if (c < 0) c += nc;
+  } else {
+    if (c < 0) c = 0;
+    if (c >= nc) c = nc - 1;
+  }
+  return c;
+}
+
+__global__ void k_cell_keys(const JobDev *jobs, const int64_t *p_off, int njobs, Soa3 o, size_t n,
+                            uint32_t *keys, uint32_t *vals) {
+  for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
+       g += (size_t)gridDim.x * blockDim.x) {
+    const int j = job_of(p_off, njobs, (int64_t)g);
+    const JobDev &J = jobs[j];
+    int64_t c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      c[a] = cell_coord((double)o.a[a][g], J.origin[a], J.inv_w[a], J.nc[a], (J.periodic >> a) & 1);
+    keys[g] = J.cell_base + (uint32_t)((c[2] * J.nc[1] + c[1]) * J.nc[0] + c[0]);
+    vals[g] = (uint32_t)g;
+  }
+}
+
+void launch_cell_keys(const JobDev *jobs, const int64_t *p_off, int njobs, Soa3 o, size_t n,
+                      uint32_t *keys, uint32_t *vals, hipStream_t s) {
+  if (n) k_cell_keys<<<blocks_for(n, 256, 65536), 256, 0, s>>>(jobs, p_off, njobs, o, n, keys, vals);
+}
+
+// sorted structure of arrays: xyz and the job-local original index in w
+__global__ void k_gather(const uint32_t *perm, const int64_t *p_off, int njobs, Soa3 o, Soa3 r,
+                         size_t n, float4 *pos, float4 *rec, uint32_t *inv_perm) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t g = perm[k];
+    const int j = job_of(p_off, njobs, (int64_t)g);
+    const uint32_t lid = (uint32_t)((int64_t)g - p_off[j]);
+    pos[k] = make_float4(o.a[0][g], o.a[1][g], o.a[2][g], __uint_as_float(lid));
+    rec[k] = make_float4(r.a[0][g], r.a[1][g], r.a[2][g], 0.f);
+    inv_perm[g] = (uint32_t)k;
+  }
+}
+
+void launch_gather(const uint32_t *perm, const int64_t *p_off, int njobs, Soa3 o, Soa3 r, size_t n,
+                   float4 *pos, float4 *rec, uint32_t *inv_perm, hipStream_t s) {
+  if (n)
+    k_gather<<<blocks_for(n, 256, 65536), 256, 0, s>>>(perm, p_off, njobs, o, r, n, pos, rec,
+                                                       inv_perm);
+}
+
+__global__ void k_cell_flags(const uint32_t *keys, size_t n, uint8_t *flag) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (size_t)gridDim.x * blockDim.x)
+    flag[k] = (k == 0 || keys[k] != keys[k - 1]) ? 1 : 0;
+}
+
+__global__ void k_cell_starts(const uint32_t *keys, const uint8_t *flag, const uint32_t *cid,
+                              size_t n, uint32_t *cell_of, uint32_t *cell_start, uint32_t *cell_key,
+                              const uint32_t *n_cells) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t c = cid[k] + flag[k] - 1u;
+    cell_of[k] = c;
+    if (flag[k]) {
+      cell_start[c] = (uint32_t)k;
+      cell_key[c] = keys[k];
+    }
+    if (k == n - 1) cell_start[*n_cells] = (uint32_t)n;
+  }
+}
+
+void build_cells(const uint32_t *keys, size_t n, uint32_t *cell_of, uint32_t *cell_start,
+                 uint32_t *cell_key, uint32_t *n_cells, Arena &ar, hipStream_t s) {
+  if (n == 0) {
+    PCC_HIP(hipMemsetAsync(n_cells, 0, sizeof(uint32_t), s));
+    PCC_HIP(hipMemsetAsync(cell_start, 0, sizeof(uint32_t), s));
+    return;
+  }
+  uint8_t *flag = ar.get<uint8_t>(n);
+  uint32_t *cid = ar.get<uint32_t>(n);
+  const int nb = blocks_for(n, 256, 65536);
+  k_cell_flags<<<nb, 256, 0, s>>>(keys, n, flag);
+  scan_u8_u32(flag, cid, n, n_cells, ar, s);
+  k_cell_starts<<<nb, 256, 0, s>>>(keys, flag, cid, n, cell_of, cell_start, cell_key, n_cells);
+}
+
+// the 13 offsets (dx, dy, dz) that come after (0, 0, 0) in z-major order
+__constant__ int8_t kFwd[13][3] = {{1, 0, 0},  {-1, 1, 0}, {0, 1, 0},  {1, 1, 0},  {-1, -1, 1},
+                                   {0, -1, 1}, {1, -1, 1}, {-1, 0, 1}, {0, 0, 1},  {1, 0, 1},
+                                   {-1, 1, 1}, {0, 1, 1},  {1, 1, 1}};
+
+__global__ void k_neighbors(const JobDev *jobs, const uint32_t *cell_base, int njobs,
+                            const uint32_t *cell_key, const uint32_t *n_cells, int32_t *nbr) {
+  const uint32_t U = *n_cells;
+  for (size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x; u < U;
+       u += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t key = cell_key[u];
+    // job whose key range holds this cell
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (cell_base[mid] <= key)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const JobDev &J = jobs[lo];
+    const uint32_t local = key - J.cell_base;
+    const int64_t c[3] = {(int64_t)(local % (uint32_t)J.nc[0]),
+                          (int64_t)((local / (uint32_t)J.nc[0]) % (uint32_t)J.nc[1]),
+                          (int64_t)(local / ((uint32_t)J.nc[0] * (uint32_t)J.nc[1]))};
+    for (int s = 0; s < 13; ++s) {
+      int64_t q[3];
+      bool ok = true;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        q[a] = c[a] + kFwd[s][a];
+        const int nc = J.nc[a];
+        if (q[a] < 0 || q[a] >= nc) {
+          if (((J.periodic >> a) & 1) && nc >= 3)
+            q[a] = (q[a] + nc) % nc;
+          else
+            ok = false;
+        }
+      }
+      int32_t found = -1;
+      if (ok) {
+        const uint32_t want = J.cell_base + (uint32_t)((q[2] * J.nc[1] + q[1]) * J.nc[0] + q[0]);
+        uint32_t a = 0, b = U;
+        while (a < b) {
+          uint32_t m = (a + b) >> 1;
+          if (cell_key[m] < want)
+            a = m + 1;
+          else
+            b = m;
+        }
+        if (a < U && cell_key[a] == want) found = (int32_t)a;
+      }
+      nbr[u * 13 + s] = found;
+    }
+  }
+}
+
+void launch_neighbors(const JobDev *jobs, const uint32_t *cell_base, int njobs,
+                      const uint32_t *cell_key, const uint32_t *n_cells, size_t max_cells,
+                      int32_t *nbr, hipStream_t s) {
+  if (max_cells)
+    k_neighbors<<<blocks_for(max_cells, 256, 65536), 256, 0, s>>>(jobs, cell_base, njobs, cell_key,
+                                                                  n_cells, nbr);
+}
+
+}  // namespace pcc

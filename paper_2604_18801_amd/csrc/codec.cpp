@@ -1,0 +1,331 @@
+// Host half of the edit stream (Sec. 3.3: Huffman coding followed by ZSTD):
+// length-limited canonical Huffman tables from the device histograms, ZSTD
+// through the system runtime library (opened with dlopen; the stream is
+// stored uncompressed when it is missing), stream assembly and decoding.
+//
+// Byte layout (little-endian):
+//   header, 64 bytes: u32 magic 0x45434350 | u16 version 1 | u8 m | u8 flags
+//     (bit 0: payload is one ZSTD frame, bit 1: Huffman-coded symbols)
+//     | u64 n | u64 flagged | f64 step | f64 offset | u64 raw payload bytes
+//     | u64 stored payload bytes | u32 symbol bits (8 or 16) | u32 0
+//   payload: ceil(n/8) flag bytes (particle k at bit k mod 8 of byte k / 8),
+//     then for flagged > 0: u32 K | K u32 symbols | K u8 code lengths |
+//     u64 bit count | the bits.  Symbols run x plane, y plane, z plane, each
+//     over the flagged particles in increasing index; m = 32 codes are a low
+//     then a high 16-bit symbol.  Canonical codes in (length, symbol) order,
+//     most significant bit first; stream bit q is bit q mod 8 of byte q / 8.
+//   decoding: edit = code * step - offset; x' = float32(x_hat + edit).
+#include <dlfcn.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <queue>
+#include <thread>
+
+#include "host.hpp"
+
+namespace pcc {
+
+namespace {
+constexpr uint32_t kMagic = 0x45434350u;
+constexpr int kMaxLen = 24;
+constexpr size_t kHeader = 64;
+
+struct Zstd {
+  bool ok = false;
+  size_t (*bound)(size_t) = nullptr;
+  size_t (*compress)(void *, size_t, const void *, size_t, int) = nullptr;
+  size_t (*decompress)(void *, size_t, const void *, size_t) = nullptr;
+  unsigned (*is_error)(size_t) = nullptr;
+  void *(*create_cctx)() = nullptr;
+  size_t (*free_cctx)(void *) = nullptr;
+  size_t (*set_param)(void *, int, int) = nullptr;
+  size_t (*compress2)(void *, void *, size_t, const void *, size_t) = nullptr;
+};
+
+Zstd &zstd() {
+  static Zstd z;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    void *h = dlopen("libzstd.so.1", RTLD_NOW | RTLD_LOCAL);
+    if (!h) return;
+    z.bound = (size_t(*)(size_t))dlsym(h, "ZSTD_compressBound");
+    z.compress = (size_t(*)(void *, size_t, const void *, size_t, int))dlsym(h, "ZSTD_compress");
+    z.decompress = (size_t(*)(void *, size_t, const void *, size_t))dlsym(h, "ZSTD_decompress");
+    z.is_error = (unsigned (*)(size_t))dlsym(h, "ZSTD_isError");
+    z.create_cctx = (void *(*)())dlsym(h, "ZSTD_createCCtx");
+    z.free_cctx = (size_t(*)(void *))dlsym(h, "ZSTD_freeCCtx");
+    z.set_param = (size_t(*)(void *, int, int))dlsym(h, "ZSTD_CCtx_setParameter");
+    z.compress2 = (size_t(*)(void *, void *, size_t, const void *, size_t))dlsym(h, "ZSTD_compress2");
+    z.ok = z.bound && z.compress && z.decompress && z.is_error;
+  });
+  return z;
+}
+
+// public parameter numbers of ZSTD_CCtx_setParameter
+constexpr int kZstdLevel = 100;
+constexpr int kZstdWorkers = 400;
+
+template <typename T>
+void put(std::vector<uint8_t> &b, size_t at, T v) {
+  std::memcpy(b.data() + at, &v, sizeof v);
+}
+template <typename T>
+T get(const uint8_t *p) {
+  T v;
+  std::memcpy(&v, p, sizeof v);
+  return v;
+}
+
+uint32_t reverse_bits(uint32_t c, int len) {
+  uint32_t r = 0;
+  for (int k = 0; k < len; ++k) r |= ((c >> k) & 1u) << (len - 1 - k);
+  return r;
+}
+}  // namespace
+
+bool zstd_available() { return zstd().ok; }
+
+bool zstd_compress(const uint8_t *src, size_t len, std::vector<uint8_t> &dst, int level) {
+  Zstd &z = zstd();
+  if (!z.ok || len == 0) return false;
+  dst.resize(z.bound(len));
+  size_t got;
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  if (len >= ((size_t)4 << 20) && z.create_cctx && z.set_param && z.compress2 && hw > 1) {
+    void *cc = z.create_cctx();
+    z.set_param(cc, kZstdLevel, level);
+    z.set_param(cc, kZstdWorkers, (int)std::min(16u, hw));
+    got = z.compress2(cc, dst.data(), dst.size(), src, len);
+    z.free_cctx(cc);
+  } else {
+    got = z.compress(dst.data(), dst.size(), src, len, level);
+  }
+  if (z.is_error(got)) return false;
+  dst.resize(got);
+  return true;
+}
+
+bool zstd_decompress(const uint8_t *src, size_t len, uint8_t *dst, size_t raw_len) {
+  Zstd &z = zstd();
+  if (!z.ok) return false;
+  size_t got = z.decompress(dst, raw_len, src, len);
+  return !z.is_error(got) && got == raw_len;
+}
+
+// Huffman code lengths by repeatedly merging the two lightest trees (binary
+// heap, ties broken by node number); if a code would exceed 24 bits the
+// counts are halved and the tree is rebuilt.
+void huffman_build(const uint32_t *hist, int alphabet, HuffTable &out) {
+  out.syms.clear();
+  out.lens.clear();
+  out.table.assign(65536, 0);
+  std::vector<uint64_t> w;
+  for (int s = 0; s < alphabet; ++s)
+    if (hist[s]) {
+      out.syms.push_back((uint32_t)s);
+      w.push_back(hist[s]);
+    }
+  const size_t k = out.syms.size();
+  if (k == 0) return;
+  std::vector<uint8_t> len(k, 1);
+  if (k > 1) {
+    for (;;) {
+      using Item = std::pair<uint64_t, uint32_t>;
+      std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
+      std::vector<uint32_t> parent(2 * k - 1, 0);
+      for (size_t i = 0; i < k; ++i) heap.push({w[i], (uint32_t)i});
+      uint32_t next = (uint32_t)k;
+      while (heap.size() > 1) {
+        Item a = heap.top();
+        heap.pop();
+        Item b = heap.top();
+        heap.pop();
+        parent[a.second] = next;
+        parent[b.second] = next;
+        heap.push({a.first + b.first, next});
+        ++next;
+      }
+      std::vector<int> depth(2 * k - 1, 0);
+      int deepest = 0;
+      for (int id = (int)(2 * k - 3); id >= 0; --id) {
+        depth[id] = depth[parent[id]] + 1;
+        if (id < (int)k) deepest = std::max(deepest, depth[id]);
+      }
+      if (deepest <= kMaxLen) {
+        for (size_t i = 0; i < k; ++i) len[i] = (uint8_t)depth[i];
+        break;
+      }
+      for (auto &x : w) x = (x + 1) / 2;
+    }
+  }
+  std::vector<uint32_t> order(k);
+  for (size_t i = 0; i < k; ++i) order[i] = (uint32_t)i;
+  std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+    return len[a] != len[b] ? len[a] < len[b] : out.syms[a] < out.syms[b];
+  });
+  std::vector<uint32_t> syms(k);
+  std::vector<uint8_t> lens(k);
+  uint32_t code = 0;
+  for (size_t r = 0; r < k; ++r) {
+    const uint32_t i = order[r];
+    if (r > 0) code = (code + 1) << (len[i] - lens[r - 1]);
+    syms[r] = out.syms[i];
+    lens[r] = len[i];
+    out.table[syms[r]] = reverse_bits(code, len[i]) | ((uint32_t)len[i] << 24);
+  }
+  out.syms.swap(syms);
+  out.lens.swap(lens);
+}
+
+size_t stream_bound(int64_t n, int m_bits) {
+  if (n < 0) n = 0;
+  const size_t per = m_bits == 32 ? 2 : 1;
+  const size_t raw = ((size_t)n + 7) / 8 + 4 + 5 * 65536 + 8 + ((size_t)n * 3 * per * kMaxLen + 7) / 8;
+  return kHeader + raw + raw / 128 + 4096;
+}
+
+void assemble_stream(int64_t n, int m_bits, int64_t nflagged, double qstep, double qoffset,
+                     const uint8_t *flags, size_t nflag_bytes, const HuffTable *ht,
+                     const uint32_t *words, uint64_t nbits, std::vector<uint8_t> &out,
+                     size_t *payload_raw) {
+  std::vector<uint8_t> pay;
+  const size_t nb = ((size_t)n + 7) / 8;
+  const bool huff = nflagged > 0 && ht && !ht->syms.empty();
+  size_t raw = nb;
+  if (huff) raw += 4 + 5 * ht->syms.size() + 8 + (size_t)((nbits + 7) / 8);
+  pay.assign(raw, 0);
+  if (nb) std::memcpy(pay.data(), flags, std::min(nb, nflag_bytes));
+  if (huff) {
+    size_t at = nb;
+    put<uint32_t>(pay, at, (uint32_t)ht->syms.size());
+    at += 4;
+    for (uint32_t sy : ht->syms) {
+      put<uint32_t>(pay, at, sy);
+      at += 4;
+    }
+    for (uint8_t l : ht->lens) pay[at++] = l;
+    put<uint64_t>(pay, at, nbits);
+    at += 8;
+    std::memcpy(pay.data() + at, words, (size_t)((nbits + 7) / 8));
+  }
+  *payload_raw = raw;
+  std::vector<uint8_t> z;
+  const bool zok = zstd_compress(pay.data(), pay.size(), z, 3);
+  const std::vector<uint8_t> &stored = zok ? z : pay;
+  out.assign(kHeader + stored.size(), 0);
+  put<uint32_t>(out, 0, kMagic);
+  put<uint16_t>(out, 4, 1);
+  out[6] = (uint8_t)m_bits;
+  out[7] = (uint8_t)((zok ? 1 : 0) | (huff ? 2 : 0));
+  put<uint64_t>(out, 8, (uint64_t)n);
+  put<uint64_t>(out, 16, (uint64_t)nflagged);
+  put<double>(out, 24, qstep);
+  put<double>(out, 32, qoffset);
+  put<uint64_t>(out, 40, (uint64_t)raw);
+  put<uint64_t>(out, 48, (uint64_t)stored.size());
+  put<uint32_t>(out, 56, (uint32_t)(m_bits == 8 ? 8 : 16));
+  if (!stored.empty()) std::memcpy(out.data() + kHeader, stored.data(), stored.size());
+}
+
+pcc_status decode_stream(const uint8_t *s, size_t len, int64_t n, const float *rx, const float *ry,
+                         const float *rz, float *ox, float *oy, float *oz, std::string &err) {
+  if (len < kHeader || get<uint32_t>(s) != kMagic || get<uint16_t>(s + 4) != 1)
+    return err = "not an edit stream", PCC_E_INVALID_ARG;
+  const int m = s[6], fl = s[7];
+  if ((int64_t)get<uint64_t>(s + 8) != n) return err = "particle count differs from the stream", PCC_E_INVALID_ARG;
+  const uint64_t nf = get<uint64_t>(s + 16);
+  const double step = get<double>(s + 24), offset = get<double>(s + 32);
+  const uint64_t raw = get<uint64_t>(s + 40), stored = get<uint64_t>(s + 48);
+  const uint32_t symbits = get<uint32_t>(s + 56);
+  if (stored != len - kHeader || !(m == 8 || m == 16 || m == 32) || !(symbits == 8 || symbits == 16) ||
+      nf > (uint64_t)n)
+    return err = "corrupt stream header", PCC_E_INVALID_ARG;
+  std::vector<uint8_t> pay(raw);
+  if (fl & 1) {
+    if (!zstd_available()) return err = "stream needs libzstd.so.1", PCC_E_UNSUPPORTED;
+    if (!zstd_decompress(s + kHeader, stored, pay.data(), raw)) return err = "ZSTD frame is corrupt", PCC_E_INVALID_ARG;
+  } else {
+    if (raw != stored) return err = "corrupt stream header", PCC_E_INVALID_ARG;
+    if (raw) std::memcpy(pay.data(), s + kHeader, raw);
+  }
+  const size_t nb = ((size_t)n + 7) / 8;
+  if (raw < nb) return err = "payload too short", PCC_E_INVALID_ARG;
+  const int per = m == 32 ? 2 : 1;
+  const size_t nsym = (size_t)nf * 3 * per;
+  std::vector<uint32_t> sym(nsym);
+  const uint8_t *p = pay.data() + nb, *end = pay.data() + raw;
+  if (nsym && (fl & 2)) {
+    if (end - p < 4) return err = "payload too short", PCC_E_INVALID_ARG;
+    const uint32_t k = get<uint32_t>(p);
+    p += 4;
+    if ((size_t)(end - p) < (size_t)k * 5 + 8) return err = "payload too short", PCC_E_INVALID_ARG;
+    std::vector<uint32_t> syms(k);
+    std::vector<int> count(kMaxLen + 1, 0);
+    for (uint32_t i = 0; i < k; ++i) syms[i] = get<uint32_t>(p + 4 * i);
+    p += 4 * (size_t)k;
+    std::vector<uint8_t> lens(p, p + k);
+    p += k;
+    const uint64_t nbits = get<uint64_t>(p);
+    p += 8;
+    if ((uint64_t)(end - p) * 8 < nbits) return err = "payload too short", PCC_E_INVALID_ARG;
+    // symbols in canonical order: by length, then symbol value
+    std::vector<uint32_t> order(k);
+    for (uint32_t i = 0; i < k; ++i) {
+      if (lens[i] == 0 || lens[i] > kMaxLen) return err = "bad code length", PCC_E_INVALID_ARG;
+      order[i] = i;
+      count[lens[i]]++;
+    }
+    std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+      return lens[a] != lens[b] ? lens[a] < lens[b] : syms[a] < syms[b];
+    });
+    uint64_t q = 0;
+    for (size_t t = 0; t < nsym; ++t) {
+      // walk the code lengths: codes of length l are a contiguous range
+      int64_t code = 0, first = 0, index = 0;
+      int l = 1;
+      for (;; ++l) {
+        if (l > kMaxLen || q >= nbits) return err = "corrupt Huffman data", PCC_E_INVALID_ARG;
+        code |= (p[q >> 3] >> (q & 7)) & 1;
+        ++q;
+        const int64_t c = count[l];
+        if (code - first < c) {
+          sym[t] = syms[order[index + (code - first)]];
+          break;
+        }
+        index += c;
+        first = (first + c) << 1;
+        code <<= 1;
+      }
+    }
+  } else if (nsym) {
+    const size_t bytes = symbits / 8;
+    if ((size_t)(end - p) < nsym * bytes) return err = "payload too short", PCC_E_INVALID_ARG;
+    for (size_t t = 0; t < nsym; ++t) {
+      uint32_t v = 0;
+      for (size_t b = 0; b < bytes; ++b) v |= (uint32_t)p[bytes * t + b] << (8 * b);
+      sym[t] = v;
+    }
+  }
+  const float *rin[3] = {rx, ry, rz};
+  float *rout[3] = {ox, oy, oz};
+  for (int a = 0; a < 3; ++a)
+    if (n) std::memcpy(rout[a], rin[a], (size_t)n * sizeof(float));
+  // flagged particle ids in increasing order
+  std::vector<int64_t> ids;
+  ids.reserve(nf);
+  for (int64_t k = 0; k < n; ++k)
+    if ((pay[k >> 3] >> (k & 7)) & 1) ids.push_back(k);
+  if (ids.size() != nf) return err = "flag count differs from the header", PCC_E_INVALID_ARG;
+  for (int a = 0; a < 3; ++a)
+    for (size_t r = 0; r < ids.size(); ++r) {
+      const size_t base = ((size_t)a * nf + r) * per;
+      const uint64_t code = per == 2 ? ((uint64_t)sym[base] | ((uint64_t)sym[base + 1] << 16)) : sym[base];
+      const double edit = (double)code * step - offset;
+      rout[a][ids[r]] = (float)((double)rin[a][ids[r]] + edit);
+    }
+  return PCC_OK;
+}
+
+}  // namespace pcc

@@ -1,0 +1,185 @@
+// Edit encoding (Alg. 1 last lines; Sec. 3.3 "Compaction, quantization, and
+// lossless compression"): edits = final - reconstruction in float64, a flag
+// per particle with a non-zero edit, m-bit uniform codes of the three edit
+// components of every flagged particle (planar x | y | z, increasing particle
+// index), their histogram, and the Huffman bit-packing of the codes with a
+// host-built canonical code table.
+#include "kernels.hpp"
+
+namespace pcc {
+
+__device__ inline const double4 *final_buf(const EncBufs &b, int job) {
+  return (b.loop[job].t & 1) ? b.P1 : b.P0;
+}
+
+__global__ void k_edit_flags(EncBufs B) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < B.ne;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int j = job_of(B.e_off, B.njobs, (int64_t)e);
+    const uint32_t k = B.e_list[e];
+    const double4 p = final_buf(B, j)[e];
+    const float4 r = B.rec[k];
+    const bool moved = (p.x - (double)r.x) != 0.0 || (p.y - (double)r.y) != 0.0 ||
+                       (p.z - (double)r.z) != 0.0;
+    B.flag8[B.p_off[j] + __float_as_uint(B.pos[k].w)] = moved ? 1 : 0;
+  }
+}
+
+void launch_edit_flags(const EncBufs &b, hipStream_t s) {
+  fill_u8(b.flag8, 0, b.n, s);
+  if (b.ne) k_edit_flags<<<blocks_for(b.ne, 256, 65536), 256, 0, s>>>(b);
+}
+
+// code = clamp(rint((edit + 2 xi) / step), 0, 2^m - 1); m = 32 codes are
+// split into a low and a high 16-bit symbol
+__global__ void k_edit_codes(EncBufs B, const uint32_t *fstart) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < B.ne;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int j = job_of(B.e_off, B.njobs, (int64_t)e);
+    const uint32_t k = B.e_list[e];
+    const int64_t g = B.p_off[j] + __float_as_uint(B.pos[k].w);
+    if (!B.flag8[g]) continue;
+    const JobDev &J = B.jobs[j];
+    const double4 p = final_buf(B, j)[e];
+    const float4 r = B.rec[k];
+    const double d[3] = {p.x - (double)r.x, p.y - (double)r.y, p.z - (double)r.z};
+    const int per = J.m_bits == 32 ? 2 : 1;
+    const uint64_t nf = (B.sym_off[j + 1] - B.sym_off[j]) / (uint64_t)(3 * per);
+    const uint64_t at = (uint64_t)(B.fpos[g] - fstart[j]);
+    uint32_t *hist = B.hist + (size_t)j * 65536;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double qv = rint((d[a] + J.qoffset) / J.qstep);
+      qv = fmin(fmax(qv, 0.0), J.qmax);
+      const uint64_t code = (uint64_t)qv;
+      const uint64_t base = B.sym_off[j] + (uint64_t)a * per * nf + per * at;
+      if (per == 2) {
+        const uint16_t lo = (uint16_t)(code & 0xffffu), hi = (uint16_t)(code >> 16);
+        B.sym[base] = lo;
+        B.sym[base + 1] = hi;
+        atomicAdd(hist + lo, 1u);
+        atomicAdd(hist + hi, 1u);
+      } else {
+        B.sym[base] = (uint16_t)code;
+        atomicAdd(hist + code, 1u);
+      }
+    }
+  }
+}
+
+void launch_edit_codes(const EncBufs &b, const uint32_t *fstart, hipStream_t s) {
+  if (b.ne) k_edit_codes<<<blocks_for(b.ne, 256, 65536), 256, 0, s>>>(b, fstart);
+}
+
+__global__ void k_flag_bytes(const uint8_t *flag8, const int64_t *p_off, const uint64_t *fb_off,
+                             int njobs, size_t nbytes, uint8_t *bytes) {
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < nbytes;
+       q += (size_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (fb_off[mid] <= q)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const int64_t n = p_off[lo + 1] - p_off[lo];
+    const int64_t first = (int64_t)(q - fb_off[lo]) * 8;
+    uint32_t v = 0;
+    for (int t = 0; t < 8; ++t)
+      if (first + t < n && flag8[p_off[lo] + first + t]) v |= 1u << t;
+    bytes[q] = (uint8_t)v;
+  }
+}
+
+void launch_flag_bytes(const uint8_t *flag8, const int64_t *p_off, const uint64_t *fb_off,
+                       int njobs, size_t nbytes, uint8_t *bytes, hipStream_t s) {
+  if (nbytes)
+    k_flag_bytes<<<blocks_for(nbytes, 256, 65536), 256, 0, s>>>(flag8, p_off, fb_off, njobs,
+                                                                nbytes, bytes);
+}
+
+__device__ inline int job_of_u64(const uint64_t *off, int njobs, uint64_t g) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= g)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// table entry: bit-reversed canonical code in the low 24 bits, length above
+__global__ void k_sym_len(const uint16_t *sym, size_t nsym, const uint64_t *sym_off, int njobs,
+                          const uint32_t *table, uint32_t *len) {
+  for (size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x; s < nsym;
+       s += (size_t)gridDim.x * blockDim.x) {
+    const int j = job_of_u64(sym_off, njobs, s);
+    len[s] = table[(size_t)j * 65536 + sym[s]] >> 24;
+  }
+}
+
+void launch_sym_lengths(const uint16_t *sym, size_t nsym, const uint64_t *sym_off, int njobs,
+                        const uint32_t *table, uint32_t *len, hipStream_t s) {
+  if (nsym)
+    k_sym_len<<<blocks_for(nsym, 256, 65536), 256, 0, s>>>(sym, nsym, sym_off, njobs, table, len);
+}
+
+// each symbol ORs its code bits into the job's word-aligned bitstream; bit q
+// of a job's stream is bit (q mod 32) of its little-endian word q / 32
+__global__ void k_pack(const uint16_t *sym, size_t nsym, const uint64_t *sym_off, int njobs,
+                       const uint32_t *table, const uint64_t *bitpos, const uint64_t *job_bit0,
+                       const uint64_t *job_word0, uint32_t *words) {
+  for (size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x; s < nsym;
+       s += (size_t)gridDim.x * blockDim.x) {
+    const int j = job_of_u64(sym_off, njobs, s);
+    const uint32_t t = table[(size_t)j * 65536 + sym[s]];
+    const uint64_t pos = bitpos[s] - job_bit0[j];
+    const uint64_t w = job_word0[j] + (pos >> 5);
+    const uint64_t v = (uint64_t)(t & 0xffffffu) << (pos & 31);
+    if ((uint32_t)v) atomicOr(words + w, (uint32_t)v);
+    if ((uint32_t)(v >> 32)) atomicOr(words + w + 1, (uint32_t)(v >> 32));
+  }
+}
+
+void launch_pack_bits(const uint16_t *sym, size_t nsym, const uint64_t *sym_off, int njobs,
+                      const uint32_t *table, const uint64_t *bitpos, const uint64_t *job_bit0,
+                      const uint64_t *job_word0, uint32_t *words, hipStream_t s) {
+  if (nsym)
+    k_pack<<<blocks_for(nsym, 256, 65536), 256, 0, s>>>(sym, nsym, sym_off, njobs, table, bitpos,
+                                                        job_bit0, job_word0, words);
+}
+
+// float64 coordinates before quantisation, in each job's particle order
+__global__ void k_debug_rec(EncBufs B) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < B.n;
+       k += (size_t)gridDim.x * blockDim.x) {
+    const int j = job_of(B.p_off, B.njobs, (int64_t)k);
+    const int64_t g = B.p_off[j] + __float_as_uint(B.pos[k].w);
+    const float4 r = B.rec[k];
+    B.debug[g] = (double)r.x;
+    B.debug[B.n + g] = (double)r.y;
+    B.debug[2 * B.n + g] = (double)r.z;
+  }
+}
+__global__ void k_debug_e(EncBufs B) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < B.ne;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int j = job_of(B.e_off, B.njobs, (int64_t)e);
+    const uint32_t k = B.e_list[e];
+    const int64_t g = B.p_off[j] + __float_as_uint(B.pos[k].w);
+    const double4 p = final_buf(B, j)[e];
+    B.debug[g] = p.x;
+    B.debug[B.n + g] = p.y;
+    B.debug[2 * B.n + g] = p.z;
+  }
+}
+
+void launch_debug_xyz(const EncBufs &b, hipStream_t s) {
+  if (b.n) k_debug_rec<<<blocks_for(b.n, 256, 65536), 256, 0, s>>>(b);
+  if (b.ne) k_debug_e<<<blocks_for(b.ne, 256, 65536), 256, 0, s>>>(b);
+}
+
+}  // namespace pcc

@@ -1,0 +1,90 @@
+// Host-side pieces of the library: context, batch pipeline, edit-stream
+// codec (canonical Huffman + ZSTD through the runtime libzstd).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pcc.h"
+#include "kernels.hpp"
+
+namespace pcc {
+
+// Retained device data of the last call (test hook pcc_debug_fetch).
+struct LastCall {
+  bool valid = false;
+  int njobs = 0;
+  std::vector<int64_t> p_off;      // [njobs+1] particles per job (global space)
+  std::vector<int> job_index;      // caller job index of each included job
+  size_t n = 0, na = 0, ne = 0;
+  const uint32_t *a_i = nullptr, *a_j = nullptr;
+  const uint8_t *a_t = nullptr;
+  const uint32_t *safe_root = nullptr;
+  const float4 *pos = nullptr;
+  const uint32_t *e_list = nullptr;
+};
+
+// Adam bias corrections (1 - beta1^t, 1 - beta2^t) for t = 0 .. len - 1,
+// computed on the host with the C library's pow and kept on the device.
+struct BcTable {
+  double beta1, beta2;
+  int64_t len;
+  double2 *dev;
+};
+
+// Optional HIP-event brackets around kernel launches.
+struct KernelTimer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, int>> marks;  // (kernel id, first event index)
+  size_t used = 0;
+  void begin_call() { marks.clear(); used = 0; }
+  int start(int id, hipStream_t s);
+  void stop(int at, hipStream_t s);
+  void collect(double *ms, int64_t *count);
+  ~KernelTimer();
+};
+
+struct Context {
+  int device = 0;
+  KernelTimer kt;
+  int graph_iters = 8;
+  std::vector<BcTable> bc;
+  hipStream_t own = nullptr;
+  Arena arena;
+  LastCall last;
+  hipEvent_t ev[12] = {};
+  void *pinned = nullptr;        // small pinned staging buffer
+  size_t pinned_bytes = 0;
+  void *pinned_big = nullptr;    // staging for stream bytes
+  size_t pinned_big_bytes = 0;
+};
+
+const double2 *bc_table(Context &C, double beta1, double beta2, int64_t len);
+
+pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs, pcc_job_result *res,
+                     hipStream_t s, bool labels_only);
+
+// codec.cpp
+struct HuffTable {
+  std::vector<uint32_t> syms;   // symbols with a code, in (length, symbol) order
+  std::vector<uint8_t> lens;
+  std::vector<uint32_t> table;  // [65536] reversed code | length << 24
+};
+void huffman_build(const uint32_t *hist, int alphabet, HuffTable &out);
+bool zstd_available();
+// returns false when ZSTD is unavailable or fails; dst gets the frame
+bool zstd_compress(const uint8_t *src, size_t len, std::vector<uint8_t> &dst, int level);
+bool zstd_decompress(const uint8_t *src, size_t len, uint8_t *dst, size_t raw_len);
+size_t stream_bound(int64_t n, int m_bits);
+// header + payload assembly
+void assemble_stream(int64_t n, int m_bits, int64_t nflagged, double qstep, double qoffset,
+                     const uint8_t *flags, size_t nflag_bytes, const HuffTable *ht,
+                     const uint32_t *words, uint64_t nbits, std::vector<uint8_t> &out,
+                     size_t *payload_raw);
+pcc_status decode_stream(const uint8_t *stream, size_t len, int64_t n, const float *rx,
+                         const float *ry, const float *rz, float *ox, float *oy, float *oz,
+                         std::string &err);
+
+}  // namespace pcc

@@ -1,0 +1,129 @@
+// Host launchers of the correction kernels (one translation unit per stage).
+#pragma once
+
+#include "pcc_internal.hpp"
+
+namespace pcc {
+
+// Input scan partial of one tile (a range of one job's particles).
+struct ScanPart {
+  float mn[3], mx[3];
+  float maxabs;
+  uint32_t bad_bound;   // |x_hat - x| > xi
+  uint32_t bad_value;   // NaN or Inf
+  uint32_t job;
+};
+struct Tile {
+  int64_t start, end;
+  int32_t job, pad;
+};
+// three float32 coordinate arrays (x, y, z) of the global index space
+struct Soa3 {
+  const float *a[3];
+};
+
+// cells.hip
+void launch_scan_inputs(const Tile *tiles, int ntiles, Soa3 orig3,
+                        Soa3 rec3, const double *xi_job, ScanPart *parts,
+                        hipStream_t s);
+void launch_cell_keys(const JobDev *jobs, const int64_t *p_off, int njobs,
+                      Soa3 orig3, size_t n, uint32_t *keys, uint32_t *vals,
+                      hipStream_t s);
+void launch_gather(const uint32_t *perm, const int64_t *p_off, int njobs,
+                   Soa3 orig3, Soa3 rec3, size_t n,
+                   float4 *pos, float4 *rec, uint32_t *inv_perm, hipStream_t s);
+// unique cells of the sorted keys; returns device counter of unique cells
+void build_cells(const uint32_t *keys, size_t n, uint32_t *cell_of, uint32_t *cell_start,
+                 uint32_t *cell_key, uint32_t *n_cells, Arena &ar, hipStream_t s);
+void launch_neighbors(const JobDev *jobs, const uint32_t *cell_base, int njobs,
+                      const uint32_t *cell_key, const uint32_t *n_cells, size_t max_cells,
+                      int32_t *nbr, hipStream_t s);
+
+// pairs.hip
+struct PairBufs {
+  const JobDev *jobs;
+  const int64_t *p_off;
+  int njobs;
+  size_t n;
+  const float4 *pos, *rec;
+  const uint32_t *cell_of, *cell_start;
+  const int32_t *nbr;
+  uint32_t *safe_par, *fof_par;          // union-find parents (sorted space)
+  uint32_t *cnt_a, *cnt_f;               // per particle counts
+  unsigned long long *job_counts;        // [njobs][4]: pairs, safe, pb, pc
+  const uint64_t *off_a, *off_f;         // write offsets
+  uint32_t *a_i, *a_j;
+  uint8_t *a_t;
+  uint64_t *f_key;
+  uint32_t *f_u, *f_v;
+};
+void launch_pair_pass1(const PairBufs &b, hipStream_t s);   // classify, hook, count V
+void launch_pair_count(const PairBufs &b, hipStream_t s);   // mode-filtered counts
+void launch_pair_write(const PairBufs &b, hipStream_t s);   // mode-filtered writes
+void launch_flatten(uint32_t *par, size_t n, hipStream_t s);
+void launch_labels(const uint32_t *root, const float4 *pos, const int64_t *p_off, int njobs,
+                   size_t n, uint32_t *minid, int32_t *lab_global, hipStream_t s);
+// Boruvka minimum spanning forest over candidate edges (keys distinct).
+// Returns the number of forest edges appended at f_out_*.
+int64_t boruvka(uint64_t *key, uint32_t *u, uint32_t *v, size_t ncand, uint32_t *bpar,
+                size_t n, const uint32_t *inv_perm, const int64_t *p_off, int njobs,
+                uint32_t *out_i, uint32_t *out_j, uint8_t *out_t, Arena &ar, hipStream_t s);
+
+// pgd.hip
+struct PgdBufs {
+  const JobDev *jobs;
+  JobLoop *loop;
+  const int64_t *e_off;   // [njobs+1] editable rows per job
+  int njobs;
+  size_t ne;
+  const uint32_t *row_ptr, *col;
+  double4 *P0, *P1;
+  double *m, *v;          // [3][ne]
+  const float4 *xo;       // original position of each row
+  int32_t *n_active;      // device: jobs not done
+};
+void sort_pairs(uint32_t *a_i, uint32_t *a_j, uint8_t *a_t, size_t na, const float4 *pos,
+                int id_bits, Arena &ar, hipStream_t s);
+void mark_editable(const uint32_t *a_i, const uint32_t *a_j, size_t na, size_t n, uint8_t *is_e,
+                   uint32_t *eid, uint32_t *ne_dev, Arena &ar, hipStream_t s);
+void build_csr(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t, size_t na,
+               const uint8_t *is_e, const uint32_t *eid, size_t n, uint32_t ne, uint32_t *e_list,
+               uint32_t *row_ptr, uint32_t *col, Arena &ar, hipStream_t s);
+void launch_pgd_init(const uint32_t *e_list, size_t ne, const float4 *pos, const float4 *rec,
+                     double4 *P0, float4 *xo, double *m, double *v, hipStream_t s);
+void launch_loop_init(const JobDev *jobs, JobLoop *loop, int njobs, int32_t *n_active,
+                      hipStream_t s);
+void launch_pgd_step(const PgdBufs &b, hipStream_t s);
+void launch_pgd_finalize(const PgdBufs &b, hipStream_t s);
+
+// encode.hip
+struct EncBufs {
+  const JobDev *jobs;
+  const JobLoop *loop;
+  const int64_t *p_off;
+  const int64_t *e_off;
+  int njobs;
+  size_t ne, n;
+  const uint32_t *e_list;
+  const float4 *pos, *rec;
+  const double4 *P0, *P1;
+  uint8_t *flag8;          // [n] global original order
+  uint32_t *fpos;          // exclusive scan of flag8
+  uint16_t *sym;           // symbols
+  const uint64_t *sym_off; // [njobs+1] first symbol of each job
+  uint32_t *hist;          // [njobs][65536]
+  double *debug;           // optional [3][n] global original order
+};
+void launch_edit_flags(const EncBufs &b, hipStream_t s);
+// fstart[j]: flagged particles before job j in the global order
+void launch_edit_codes(const EncBufs &b, const uint32_t *fstart, hipStream_t s);
+void launch_flag_bytes(const uint8_t *flag8, const int64_t *p_off, const uint64_t *fb_off,
+                       int njobs, size_t nbytes, uint8_t *bytes, hipStream_t s);
+void launch_sym_lengths(const uint16_t *sym, size_t nsym, const uint64_t *sym_off, int njobs,
+                        const uint32_t *table, uint32_t *len, hipStream_t s);
+void launch_pack_bits(const uint16_t *sym, size_t nsym, const uint64_t *sym_off, int njobs,
+                      const uint32_t *table, const uint64_t *bitpos, const uint64_t *job_bit0,
+                      const uint64_t *job_word0, uint32_t *words, hipStream_t s);
+void launch_debug_xyz(const EncBufs &b, hipStream_t s);
+
+}  // namespace pcc

@@ -1,0 +1,912 @@
+// Batch pipeline of the correction pass: every stage is one launch (or one
+// short sequence of launches) over all jobs of the call.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+#include "host.hpp"
+
+namespace pcc {
+
+namespace {
+
+constexpr int64_t kTileInputs = 1 << 16;
+constexpr int kGraphIters = 8;
+
+double ulp_f32(double a) {
+  int e;
+  std::frexp(a, &e);
+  double s = std::ldexp(1.0, e - 24);
+  double tiny = std::ldexp(1.0, -149);
+  return s < tiny ? tiny : s;
+}
+
+struct HostJob {
+  int index;             // caller index
+  const pcc_job *in;
+  int64_t n;
+  int64_t p_off;
+  JobDev dev;
+  uint64_t ncell;
+  pcc_stats st;
+  int status;
+};
+
+bool finite(double v) { return std::isfinite(v); }
+
+// Returns 0 or a status; err receives a message.
+int check_params(const pcc_job &j, std::string &err) {
+  const pcc_params &p = j.params;
+  if (!(finite(p.b) && p.b > 0)) return err = "b must be finite and > 0", -1;
+  if (!(finite(p.xi) && p.xi >= 0)) return err = "xi must be finite and >= 0", -1;
+  if (p.mode < 0 || p.mode > 2) return err = "unknown mode", -1;
+  if (!(p.m_bits == 8 || p.m_bits == 16 || p.m_bits == 32)) return err = "m_bits must be 8, 16 or 32", -1;
+  if (p.optimizer < 0 || p.optimizer > 1) return err = "unknown optimizer", -1;
+  if (p.margin_policy < 0 || p.margin_policy > 1) return err = "unknown margin policy", -1;
+  if (!(finite(p.lr) && finite(p.beta1) && finite(p.beta2) && finite(p.adam_eps)))
+    return err = "optimizer constants must be finite", -1;
+  if (!(p.beta1 >= 0 && p.beta1 < 1 && p.beta2 >= 0 && p.beta2 < 1))
+    return err = "Adam betas must lie in [0, 1)", -1;
+  if (!(finite(p.loss_tol) && p.loss_tol >= 0)) return err = "loss_tol must be >= 0", -1;
+  for (int a = 0; a < 3; ++a)
+    if (!(finite(p.box[a]) && p.box[a] >= 0)) return err = "box sides must be finite and >= 0", -1;
+  if (j.orig.n != j.recon.n) return err = "orig and recon differ in size", -1;
+  if (j.orig.n < 0 || j.orig.n >= (int64_t)1 << 31) return err = "n must lie in [0, 2^31)", -1;
+  if (j.orig.memspace != j.recon.memspace) return err = "orig and recon differ in memspace", -1;
+  if (j.orig.memspace != PCC_MEM_HOST && j.orig.memspace != PCC_MEM_DEVICE)
+    return err = "unknown memspace", -1;
+  if (j.orig.n > 0 && (!j.orig.x || !j.orig.y || !j.orig.z || !j.recon.x || !j.recon.y || !j.recon.z))
+    return err = "NULL coordinate pointer", -1;
+  if (j.out.stream_cap > 0 && (!j.out.stream)) return err = "stream_cap > 0 with NULL stream", -1;
+  return 0;
+}
+
+// Constants of Alg. 1 and Sec. 3.1-3.3 for one job (library side).
+int job_constants(const pcc_params &p, const ScanPart &agg, int64_t n, JobDev &J, uint64_t &ncell,
+                  std::string &err) {
+  std::memset(&J, 0, sizeof J);
+  const double two_sqrt3 = 2.0 * std::sqrt(3.0);
+  const double rs = p.b - two_sqrt3 * p.xi;
+  const double rv = p.b + two_sqrt3 * p.xi;
+  J.b2 = p.b * p.b;
+  J.rs2 = rs > 0.0 ? rs * rs : -1.0;
+  J.rv2 = rv * rv;
+  J.mode = p.mode;
+  const double levels = std::ldexp(1.0, p.m_bits) - 1.0;
+  const double eps_q = 2.0 * p.xi / levels;
+  double dq, dt, xi_p;
+  if (p.margin_policy == PCC_MARGIN_PAPER) {
+    dq = eps_q;
+    xi_p = p.xi * (1.0 - std::ldexp(1.0, -p.m_bits));
+    dt = two_sqrt3 * eps_q;
+  } else {
+    const double u = 0.5 * ulp_f32((double)agg.maxabs + 2.0 * p.xi);
+    dq = (eps_q + u) * (1.0 + std::ldexp(1.0, -16));
+    xi_p = p.xi - dq;
+    dt = two_sqrt3 * dq;
+  }
+  J.b = p.b;
+  J.bm = p.b - dt;
+  J.bp = p.b + dt;
+  J.bm2 = J.bm * J.bm;
+  J.bp2 = J.bp * J.bp;
+  J.xi_p = xi_p;
+  J.lr = p.lr;
+  J.beta1 = p.beta1;
+  J.beta2 = p.beta2;
+  J.adam_eps = p.adam_eps;
+  J.one_m_beta1 = 1.0 - p.beta1;
+  J.one_m_beta2 = 1.0 - p.beta2;
+  J.loss_scale = std::ldexp(1.0, 32) / J.b2;
+  J.max_iters = p.max_iters > 0 ? p.max_iters : 100000;
+  J.loss_tol = p.loss_tol;
+  J.optimizer = p.optimizer;
+  J.m_bits = p.m_bits;
+  J.qstep = 4.0 * p.xi / levels;
+  J.qoffset = 2.0 * p.xi;
+  J.qmax = levels;
+  J.n = n;
+  // periodic axes and the cell grid: cells no smaller than r_v
+  const double wmin = rv * (1.0 + std::ldexp(1.0, -20));
+  double lmax = 0.0;
+  uint64_t cells = 1;
+  for (int a = 0; a < 3; ++a) {
+    const double L = p.box[a];
+    double ext;
+    if (L > 0) {
+      J.periodic |= 1 << a;
+      J.L[a] = L;
+      J.hL[a] = 0.5 * L;
+      J.Lf[a] = (float)L;
+      J.hLf[a] = (float)(0.5 * L);
+      J.origin[a] = 0.0;
+      ext = L;
+      lmax = std::max(lmax, L);
+      const double f = std::floor(L / wmin);
+      if (!(f >= 3.0)) {
+        err = "periodic side must hold at least three cells of side b + 2 sqrt(3) xi";
+        return -1;
+      }
+      J.nc[a] = (int32_t)std::min(f, 2097152.0);
+    } else {
+      J.L[a] = 0.0;
+      J.hL[a] = std::numeric_limits<double>::infinity();
+      J.Lf[a] = 0.f;
+      J.hLf[a] = std::numeric_limits<float>::infinity();
+      J.origin[a] = n > 0 ? (double)agg.mn[a] : 0.0;
+      ext = n > 0 ? (double)agg.mx[a] - (double)agg.mn[a] : 0.0;
+      const double f = std::floor(ext / wmin);
+      J.nc[a] = (int32_t)std::max(1.0, std::min(f, 2097152.0));
+    }
+    J.inv_w[a] = ext > 0 ? (double)J.nc[a] / ext : 0.0;
+    cells *= (uint64_t)J.nc[a];
+  }
+  // keep the key space of one job below 2^31 by coarsening open axes first
+  while (cells >= ((uint64_t)1 << 31)) {
+    cells = 1;
+    for (int a = 0; a < 3; ++a) {
+      const int minc = (J.periodic >> a) & 1 ? 3 : 1;
+      J.nc[a] = std::max(minc, (int32_t)(J.nc[a] * 0.8));
+      const double ext = (J.periodic >> a) & 1 ? J.L[a] : (double)agg.mx[a] - (double)agg.mn[a];
+      J.inv_w[a] = ext > 0 ? (double)J.nc[a] / ext : 0.0;
+      cells *= (uint64_t)J.nc[a];
+    }
+  }
+  ncell = cells;
+  // float32 prefilter: every pair with exact d <= r_v passes (see DESIGN)
+  const double e = 4.0 * ulp_f32((double)agg.maxabs + lmax + 1.0);
+  const double thr = (rv + e) * (rv + e) * (1.0 + std::ldexp(1.0, -18));
+  float f = (float)thr;
+  if ((double)f < thr) f = std::nextafter(f, std::numeric_limits<float>::infinity());
+  J.rv2_f32 = f;
+  return 0;
+}
+
+int bits_for(uint64_t v) {
+  int b = 0;
+  while (b < 64 && (v >> b) != 0) ++b;
+  return b;
+}
+
+template <typename T>
+T *dev(Arena &ar, size_t n) {
+  return ar.get<T>(n ? n : 1);
+}
+
+// gather of a few device words at given indices into one host array
+__global__ void k_gather_u64(const uint64_t *src, const int64_t *idx, int m, uint64_t total,
+                             size_t n, uint64_t *dst) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < m) dst[t] = (idx[t] < (int64_t)n) ? src[idx[t]] : total;
+}
+__global__ void k_gather_u32(const uint32_t *src, const int64_t *idx, int m, uint32_t total,
+                             size_t n, uint32_t *dst) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < m) dst[t] = (idx[t] < (int64_t)n) ? src[idx[t]] : total;
+}
+__global__ void k_e_off(const uint32_t *eid, const int64_t *p_off, int njobs, size_t n,
+                        const uint32_t *ne, int64_t *e_off) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > njobs) return;
+  e_off[j] = (j < njobs && p_off[j] < (int64_t)n) ? (int64_t)eid[p_off[j]] : (int64_t)*ne;
+}
+
+struct Staging {
+  Context &C;
+  hipStream_t s;
+  void *get(size_t bytes) {
+    if (C.pinned_bytes < bytes) {
+      if (C.pinned) hipHostFree(C.pinned);
+      C.pinned = nullptr;
+      size_t sz = std::max(bytes, (size_t)1 << 20);
+      PCC_HIP(hipHostMalloc(&C.pinned, sz, hipHostMallocDefault));
+      C.pinned_bytes = sz;
+    }
+    return C.pinned;
+  }
+  template <typename T>
+  void fetch(T *host, const T *devp, size_t count) {
+    if (!count) return;
+    void *p = get(count * sizeof(T));
+    PCC_HIP(hipMemcpyAsync(p, devp, count * sizeof(T), hipMemcpyDeviceToHost, s));
+    PCC_HIP(hipStreamSynchronize(s));
+    std::memcpy(host, p, count * sizeof(T));
+  }
+  template <typename T>
+  void put(T *devp, const T *host, size_t count) {
+    if (!count) return;
+    PCC_HIP(hipMemcpyAsync(devp, host, count * sizeof(T), hipMemcpyHostToDevice, s));
+    PCC_HIP(hipStreamSynchronize(s));
+  }
+};
+
+}  // namespace
+
+int KernelTimer::start(int id, hipStream_t s) {
+  if (!on) return -1;
+  while (pool.size() < used + 2) {
+    hipEvent_t e;
+    PCC_HIP(hipEventCreate(&e));
+    pool.push_back(e);
+  }
+  const int at = (int)used;
+  used += 2;
+  PCC_HIP(hipEventRecord(pool[at], s));
+  marks.push_back({id, at});
+  return at;
+}
+
+void KernelTimer::stop(int at, hipStream_t s) {
+  if (at >= 0) PCC_HIP(hipEventRecord(pool[at + 1], s));
+}
+
+void KernelTimer::collect(double *ms, int64_t *count) {
+  for (auto &m : marks) {
+    float f = 0.f;
+    if (hipEventElapsedTime(&f, pool[m.second], pool[m.second + 1]) == hipSuccess) {
+      ms[m.first] += f;
+      count[m.first] += 1;
+    }
+  }
+}
+
+KernelTimer::~KernelTimer() {
+  for (auto e : pool) hipEventDestroy(e);
+}
+
+const double2 *bc_table(Context &C, double beta1, double beta2, int64_t len) {
+  for (auto &t : C.bc)
+    if (t.beta1 == beta1 && t.beta2 == beta2 && t.len >= len) return t.dev;
+  len = std::max<int64_t>(len, 4096);
+  std::vector<double2> h((size_t)len);
+  for (int64_t t = 0; t < len; ++t) {
+    h[t].x = 1.0 - std::pow(beta1, (double)t);
+    h[t].y = 1.0 - std::pow(beta2, (double)t);
+  }
+  double2 *d = nullptr;
+  PCC_HIP(hipMalloc((void **)&d, (size_t)len * sizeof(double2)));
+  PCC_HIP(hipMemcpy(d, h.data(), (size_t)len * sizeof(double2), hipMemcpyHostToDevice));
+  for (auto &t : C.bc)
+    if (t.beta1 == beta1 && t.beta2 == beta2) {
+      hipFree(t.dev);
+      t.dev = d;
+      t.len = len;
+      return d;
+    }
+  C.bc.push_back({beta1, beta2, len, d});
+  return d;
+}
+
+pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_result *res,
+                     hipStream_t s, bool labels_only) {
+  const auto t_wall0 = std::chrono::steady_clock::now();
+  PCC_HIP(hipSetDevice(C.device));
+  PCC_HIP(hipStreamSynchronize(s));
+  C.last.valid = false;
+  C.arena.reset();
+  KernelTimer &kt = C.kt;
+  kt.begin_call();
+  Arena &ar = C.arena;
+  Staging st{C, s};
+  for (int k = 0; k < 12; ++k)
+    if (!C.ev[k]) PCC_HIP(hipEventCreate(&C.ev[k]));
+
+  std::vector<HostJob> all(njobs_in);
+  for (int k = 0; k < njobs_in; ++k) {
+    HostJob &h = all[k];
+    h.index = k;
+    h.in = &jobs[k];
+    h.n = jobs[k].orig.n;
+    h.status = 0;
+    std::memset(&h.st, 0, sizeof h.st);
+    std::string err;
+    h.status = check_params(jobs[k], err);
+    res[k].status = h.status;
+    std::memset(&res[k].stats, 0, sizeof res[k].stats);
+  }
+
+  // ------------------------------------------------------------------
+  // concatenation of the inputs and the input scan (repeated once if a job
+  // is rejected by the scan)
+  // ------------------------------------------------------------------
+  std::vector<HostJob *> act;
+  std::vector<ScanPart> agg;
+  Soa3 O{}, R{};
+  int64_t N = 0;
+  PCC_HIP(hipEventRecord(C.ev[0], s));
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    act.clear();
+    for (auto &h : all)
+      if (h.status == 0) act.push_back(&h);
+    N = 0;
+    for (auto *h : act) {
+      h->p_off = N;
+      N += h->n;
+    }
+    if (N >= ((int64_t)1 << 31)) throw Error(-1, "more than 2^31 - 1 particles in one call");
+    if (act.size() == 1 && act[0]->in->orig.memspace == PCC_MEM_DEVICE) {
+      const pcc_job &j = *act[0]->in;
+      O = Soa3{{j.orig.x, j.orig.y, j.orig.z}};
+      R = Soa3{{j.recon.x, j.recon.y, j.recon.z}};
+    } else {
+      float *buf = dev<float>(ar, 6 * (size_t)N);
+      for (int a = 0; a < 3; ++a) {
+        O.a[a] = buf + (size_t)a * N;
+        R.a[a] = buf + (size_t)(3 + a) * N;
+      }
+      for (auto *h : act) {
+        const pcc_job &j = *h->in;
+        if (!h->n) continue;
+        const hipMemcpyKind kind =
+            j.orig.memspace == PCC_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        const float *src[6] = {j.orig.x, j.orig.y, j.orig.z, j.recon.x, j.recon.y, j.recon.z};
+        for (int a = 0; a < 6; ++a)
+          PCC_HIP(hipMemcpyAsync(buf + (size_t)a * N + h->p_off, src[a], h->n * sizeof(float),
+                                 kind, s));
+      }
+    }
+    std::vector<Tile> tiles;
+    std::vector<double> xi(act.size());
+    for (size_t q = 0; q < act.size(); ++q) {
+      xi[q] = act[q]->in->params.xi;
+      for (int64_t a = 0; a < act[q]->n; a += kTileInputs)
+        tiles.push_back({act[q]->p_off + a, std::min(act[q]->p_off + act[q]->n, act[q]->p_off + a + kTileInputs),
+                         (int32_t)q, 0});
+    }
+    agg.assign(act.size(), ScanPart{});
+    for (auto &a : agg) {
+      for (int d = 0; d < 3; ++d) {
+        a.mn[d] = std::numeric_limits<float>::max();
+        a.mx[d] = -std::numeric_limits<float>::max();
+      }
+    }
+    if (!tiles.empty()) {
+      Tile *dt = dev<Tile>(ar, tiles.size());
+      double *dxi = dev<double>(ar, xi.size());
+      ScanPart *dp = dev<ScanPart>(ar, tiles.size());
+      PCC_HIP(hipMemcpyAsync(dt, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, s));
+      PCC_HIP(hipMemcpyAsync(dxi, xi.data(), xi.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      launch_scan_inputs(dt, (int)tiles.size(), O, R, dxi, dp, s);
+      std::vector<ScanPart> parts(tiles.size());
+      st.fetch(parts.data(), dp, parts.size());
+      for (auto &p : parts) {
+        ScanPart &a = agg[p.job];
+        for (int d = 0; d < 3; ++d) {
+          a.mn[d] = std::min(a.mn[d], p.mn[d]);
+          a.mx[d] = std::max(a.mx[d], p.mx[d]);
+        }
+        a.maxabs = std::max(a.maxabs, p.maxabs);
+        a.bad_bound += p.bad_bound;
+        a.bad_value += p.bad_value;
+      }
+    }
+    bool rejected = false;
+    for (size_t q = 0; q < act.size(); ++q) {
+      if (agg[q].bad_value) {
+        act[q]->status = PCC_E_INVALID_ARG;
+        rejected = true;
+      } else if (agg[q].bad_bound) {
+        act[q]->status = PCC_E_INPUT_BOUND;
+        rejected = true;
+      }
+    }
+    if (!rejected) break;
+    if (attempt == 1) throw Error(-3, "input scan disagrees with itself");
+  }
+
+  // constants and cell grids
+  uint64_t cell_total = 0;
+  {
+    std::vector<HostJob *> keep;
+    std::vector<ScanPart> kagg;
+    for (size_t q = 0; q < act.size(); ++q) {
+      std::string err;
+      uint64_t nc = 0;
+      if (job_constants(act[q]->in->params, agg[q], act[q]->n, act[q]->dev, nc, err)) {
+        act[q]->status = PCC_E_INVALID_ARG;
+        continue;
+      }
+      act[q]->ncell = nc;
+      keep.push_back(act[q]);
+      kagg.push_back(agg[q]);
+    }
+    if (keep.size() != act.size()) {
+      // rare: rebuild the index space without the rejected jobs
+      for (auto &h : all) res[h.index].status = h.status;
+      std::vector<pcc_job> rest;
+      std::vector<int> map;
+      for (auto &h : all)
+        if (h.status == 0) {
+          rest.push_back(*h.in);
+          map.push_back(h.index);
+        }
+      std::vector<pcc_job_result> sub(rest.size());
+      pcc_status r = rest.empty() ? PCC_OK : run_batch(C, rest.data(), (int)rest.size(), sub.data(), s, labels_only);
+      for (size_t q = 0; q < map.size(); ++q) res[map[q]] = sub[q];
+      (void)r;
+      pcc_status first = PCC_OK;
+      for (int k = 0; k < njobs_in; ++k)
+        if (res[k].status < 0 && first == PCC_OK) first = res[k].status;
+      if (!rest.empty() && C.last.valid)
+        for (auto &ji : C.last.job_index) ji = map[ji];
+      return first;
+    }
+    for (auto *h : act) {
+      h->dev.bc_tab = bc_table(C, h->dev.beta1, h->dev.beta2, h->dev.max_iters + 2);
+      h->dev.cell_base = (uint32_t)cell_total;
+      h->dev.p_off = h->p_off;
+      cell_total += h->ncell;
+    }
+    if (cell_total >= ((uint64_t)1 << 32)) throw Error(-6, "cell key space of the batch exceeds 2^32");
+  }
+  const int J = (int)act.size();
+  for (auto &h : all)
+    if (h.status) res[h.index].status = h.status;
+  if (J == 0 || N == 0) {
+    for (auto *h : act) {
+      // empty jobs: no pairs, an empty stream
+      const pcc_job &j = *h->in;
+      std::vector<uint8_t> strm;
+      size_t raw = 0;
+      if (!labels_only) {
+        assemble_stream(0, j.params.m_bits, 0, h->dev.qstep, h->dev.qoffset, nullptr, 0, nullptr,
+                        nullptr, 0, strm, &raw);
+        if (j.out.stream_len) *j.out.stream_len = strm.size();
+        if (j.out.stream_cap >= strm.size() && j.out.stream)
+          std::memcpy(j.out.stream, strm.data(), strm.size());
+        else if (j.out.stream_cap > 0 || j.out.stream)
+          res[h->index].status = PCC_E_BUFFER_TOO_SMALL;
+        res[h->index].stats.bytes_stream = (int64_t)strm.size();
+      }
+    }
+    pcc_status first = PCC_OK;
+    for (int k = 0; k < njobs_in; ++k)
+      if (res[k].status < 0 && first == PCC_OK) first = res[k].status;
+    return first;
+  }
+  std::vector<int64_t> p_off(J + 1);
+  std::vector<uint32_t> cbase(J + 1);
+  std::vector<JobDev> jd(J);
+  for (int q = 0; q < J; ++q) {
+    p_off[q] = act[q]->p_off;
+    cbase[q] = act[q]->dev.cell_base;
+    jd[q] = act[q]->dev;
+  }
+  p_off[J] = N;
+  cbase[J] = (uint32_t)std::min<uint64_t>(cell_total, 0xffffffffull);
+  JobDev *d_jobs = dev<JobDev>(ar, J);
+  int64_t *d_poff = dev<int64_t>(ar, J + 1);
+  uint32_t *d_cbase = dev<uint32_t>(ar, J + 1);
+  PCC_HIP(hipMemcpyAsync(d_jobs, jd.data(), J * sizeof(JobDev), hipMemcpyHostToDevice, s));
+  PCC_HIP(hipMemcpyAsync(d_poff, p_off.data(), (J + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  PCC_HIP(hipMemcpyAsync(d_cbase, cbase.data(), (J + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+  const size_t n = (size_t)N;
+  PCC_HIP(hipEventRecord(C.ev[1], s));
+
+  // ------------------------------------------------------------------
+  // cell build
+  // ------------------------------------------------------------------
+  uint32_t *keys = dev<uint32_t>(ar, n), *perm = dev<uint32_t>(ar, n);
+  launch_cell_keys(d_jobs, d_poff, J, O, n, keys, perm, s);
+  {
+    const int at = kt.start(5, s);
+    radix_sort_u32(keys, perm, n, bits_for(cell_total ? cell_total - 1 : 0), ar, s);
+    kt.stop(at, s);
+  }
+  float4 *pos = dev<float4>(ar, n), *rec = dev<float4>(ar, n);
+  uint32_t *inv_perm = dev<uint32_t>(ar, n);
+  launch_gather(perm, d_poff, J, O, R, n, pos, rec, inv_perm, s);
+  uint32_t *cell_of = dev<uint32_t>(ar, n), *cell_start = dev<uint32_t>(ar, n + 1);
+  uint32_t *cell_key = dev<uint32_t>(ar, n), *n_cells = dev<uint32_t>(ar, 1);
+  build_cells(keys, n, cell_of, cell_start, cell_key, n_cells, ar, s);
+  int32_t *nbr = dev<int32_t>(ar, n * 13);
+  launch_neighbors(d_jobs, d_cbase, J, cell_key, n_cells, n, nbr, s);
+  PCC_HIP(hipEventRecord(C.ev[2], s));
+
+  // ------------------------------------------------------------------
+  // pair pass 1: classify, hook the safe and FoF union-finds, count V
+  // ------------------------------------------------------------------
+  PairBufs pb{};
+  pb.jobs = d_jobs;
+  pb.p_off = d_poff;
+  pb.njobs = J;
+  pb.n = n;
+  pb.pos = pos;
+  pb.rec = rec;
+  pb.cell_of = cell_of;
+  pb.cell_start = cell_start;
+  pb.nbr = nbr;
+  pb.safe_par = dev<uint32_t>(ar, n);
+  pb.fof_par = dev<uint32_t>(ar, n);
+  pb.cnt_a = dev<uint32_t>(ar, n);
+  pb.cnt_f = dev<uint32_t>(ar, n);
+  pb.job_counts = dev<unsigned long long>(ar, 3 * (size_t)J);
+  iota_u32(pb.safe_par, n, s);
+  iota_u32(pb.fof_par, n, s);
+  PCC_HIP(hipMemsetAsync(pb.job_counts, 0, 3 * J * sizeof(unsigned long long), s));
+  {
+    const int at = kt.start(0, s);
+    launch_pair_pass1(pb, s);
+    kt.stop(at, s);
+  }
+  launch_flatten(pb.safe_par, n, s);
+  launch_flatten(pb.fof_par, n, s);
+  PCC_HIP(hipEventRecord(C.ev[3], s));
+
+  // labels in each job's particle order
+  int32_t *lab = dev<int32_t>(ar, n);
+  uint32_t *minid = dev<uint32_t>(ar, n);
+  launch_labels(pb.fof_par, pos, d_poff, J, n, minid, lab, s);
+  for (auto *h : act) {
+    const pcc_job &j = *h->in;
+    if (!j.out.labels || !h->n) continue;
+    const hipMemcpyKind kind =
+        j.orig.memspace == PCC_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    PCC_HIP(hipMemcpyAsync(j.out.labels, lab + h->p_off, h->n * sizeof(int32_t), kind, s));
+  }
+  std::vector<unsigned long long> jc(3 * (size_t)J);
+  st.fetch(jc.data(), pb.job_counts, jc.size());
+  for (int q = 0; q < J; ++q) {
+    pcc_stats &S = act[q]->st;
+    S.n_safe = (int64_t)jc[3 * q];
+    S.n_pb = (int64_t)jc[3 * q + 1];
+    S.n_pc = (int64_t)jc[3 * q + 2];
+    S.n_pairs = S.n_safe + S.n_pb + S.n_pc;
+  }
+  PCC_HIP(hipEventRecord(C.ev[4], s));
+  if (labels_only) {
+    PCC_HIP(hipStreamSynchronize(s));
+    for (auto *h : act) res[h->index].stats = h->st;
+    return PCC_OK;
+  }
+
+  // ------------------------------------------------------------------
+  // constraint selection: mode-filtered counts, scan, write; HF forest
+  // ------------------------------------------------------------------
+  bool all_vp = true, any_hf = false;
+  for (auto *h : act) {
+    all_vp &= h->dev.mode == PCC_MODE_VP;
+    any_hf |= h->dev.mode == PCC_MODE_HF;
+  }
+  if (!all_vp) {
+    const int at = kt.start(1, s);
+    launch_pair_count(pb, s);
+    kt.stop(at, s);
+  }
+  else fill_u32(pb.cnt_f, 0, n, s);
+  uint64_t *off_a = dev<uint64_t>(ar, n), *off_f = dev<uint64_t>(ar, n);
+  uint64_t *tot = dev<uint64_t>(ar, 2);
+  scan_u32_u64(pb.cnt_a, off_a, n, tot, ar, s);
+  scan_u32_u64(pb.cnt_f, off_f, n, tot + 1, ar, s);
+  uint64_t htot[2];
+  st.fetch(htot, tot, 2);
+  const size_t na_direct = htot[0], nf = htot[1];
+  const size_t na_cap = na_direct + (any_hf ? n : 0);
+  pb.off_a = off_a;
+  pb.off_f = off_f;
+  pb.a_i = dev<uint32_t>(ar, na_cap);
+  pb.a_j = dev<uint32_t>(ar, na_cap);
+  pb.a_t = dev<uint8_t>(ar, na_cap);
+  pb.f_key = dev<uint64_t>(ar, nf);
+  pb.f_u = dev<uint32_t>(ar, nf);
+  pb.f_v = dev<uint32_t>(ar, nf);
+  {
+    const int at = kt.start(2, s);
+    launch_pair_write(pb, s);
+    kt.stop(at, s);
+  }
+  size_t na = na_direct;
+  if (nf) {
+    uint32_t *bpar = dev<uint32_t>(ar, n);
+    PCC_HIP(hipMemcpyAsync(bpar, pb.safe_par, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    const int at = kt.start(7, s);
+    na += (size_t)boruvka(pb.f_key, pb.f_u, pb.f_v, nf, bpar, n, inv_perm, d_poff, J,
+                          pb.a_i + na_direct, pb.a_j + na_direct, pb.a_t + na_direct, ar, s);
+    kt.stop(at, s);
+  }
+  PCC_HIP(hipEventRecord(C.ev[5], s));
+
+  // ------------------------------------------------------------------
+  // editable set and incidence lists
+  // ------------------------------------------------------------------
+  {
+    int64_t nmax = 1;
+    for (auto *h : act) nmax = std::max(nmax, h->n);
+    const int at = kt.start(6, s);
+    sort_pairs(pb.a_i, pb.a_j, pb.a_t, na, pos, bits_for((uint64_t)(nmax - 1)), ar, s);
+    kt.stop(at, s);
+  }
+  uint8_t *is_e = dev<uint8_t>(ar, n);
+  uint32_t *eid = dev<uint32_t>(ar, n);
+  uint32_t *ne_dev = dev<uint32_t>(ar, 1);
+  mark_editable(pb.a_i, pb.a_j, na, n, is_e, eid, ne_dev, ar, s);
+  uint32_t ne = 0;
+  st.fetch(&ne, ne_dev, 1);
+  uint32_t *e_list = dev<uint32_t>(ar, ne);
+  uint32_t *row_ptr = dev<uint32_t>(ar, (size_t)ne + 1);
+  uint32_t *col = dev<uint32_t>(ar, 2 * na);
+  {
+    const int at = kt.start(6, s);
+    build_csr(pb.a_i, pb.a_j, pb.a_t, na, is_e, eid, n, ne, e_list, row_ptr, col, ar, s);
+    kt.stop(at, s);
+  }
+  int64_t *d_eoff = dev<int64_t>(ar, J + 1);
+  k_e_off<<<(J + 256) / 256, 256, 0, s>>>(eid, d_poff, J, n, ne_dev, d_eoff);
+  std::vector<int64_t> e_off(J + 1);
+  st.fetch(e_off.data(), d_eoff, J + 1);
+  {
+    // active pairs per job: half the incidences of its rows
+    std::vector<uint32_t> rp(J + 1);
+    uint32_t *d_rp = dev<uint32_t>(ar, J + 1);
+    k_gather_u32<<<(J + 256) / 256, 256, 0, s>>>(row_ptr, d_eoff, J + 1, (uint32_t)(2 * na),
+                                                  (size_t)ne + 1, d_rp);
+    st.fetch(rp.data(), d_rp, J + 1);
+    for (int q = 0; q < J; ++q) {
+      act[q]->st.n_editable = e_off[q + 1] - e_off[q];
+      act[q]->st.n_active = ((int64_t)rp[q + 1] - (int64_t)rp[q]) / 2;
+    }
+  }
+  PCC_HIP(hipEventRecord(C.ev[6], s));
+
+  // ------------------------------------------------------------------
+  // PGD: K fused iterations per graph launch, then one small readback
+  // ------------------------------------------------------------------
+  PgdBufs gb{};
+  gb.jobs = d_jobs;
+  gb.loop = dev<JobLoop>(ar, J);
+  gb.e_off = d_eoff;
+  gb.njobs = J;
+  gb.ne = ne;
+  gb.row_ptr = row_ptr;
+  gb.col = col;
+  gb.P0 = dev<double4>(ar, ne);
+  gb.P1 = dev<double4>(ar, ne);
+  gb.m = dev<double>(ar, 3 * (size_t)ne);
+  gb.v = dev<double>(ar, 3 * (size_t)ne);
+  float4 *xo = dev<float4>(ar, ne);
+  gb.xo = xo;
+  gb.n_active = dev<int32_t>(ar, 1);
+  launch_pgd_init(e_list, ne, pos, rec, gb.P0, xo, gb.m, gb.v, s);
+  launch_loop_init(d_jobs, gb.loop, J, gb.n_active, s);
+  const int K = std::max(1, std::min(64, C.graph_iters));
+  if (kt.on) {
+    // one launch per kernel, each bracketed by events
+    int32_t *h_act = (int32_t *)st.get(sizeof(int32_t));
+    for (;;) {
+      for (int k = 0; k < K; ++k) {
+        int at = kt.start(3, s);
+        launch_pgd_step(gb, s);
+        kt.stop(at, s);
+        at = kt.start(4, s);
+        launch_pgd_finalize(gb, s);
+        kt.stop(at, s);
+      }
+      PCC_HIP(hipMemcpyAsync(h_act, gb.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      PCC_HIP(hipStreamSynchronize(s));
+      if (*h_act <= 0) break;
+    }
+  } else {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    PCC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < K; ++k) {
+      launch_pgd_step(gb, s);
+      launch_pgd_finalize(gb, s);
+    }
+    PCC_HIP(hipStreamEndCapture(s, &graph));
+    hipError_t ge = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ge != hipSuccess) {
+      hipGraphDestroy(graph);
+      hip_fail(ge, "hipGraphInstantiate", __FILE__, __LINE__);
+    }
+    int32_t *h_act = (int32_t *)st.get(sizeof(int32_t));
+    try {
+      for (;;) {
+        PCC_HIP(hipGraphLaunch(exec, s));
+        PCC_HIP(hipMemcpyAsync(h_act, gb.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        PCC_HIP(hipStreamSynchronize(s));
+        if (*h_act <= 0) break;
+      }
+    } catch (...) {
+      hipGraphExecDestroy(exec);
+      hipGraphDestroy(graph);
+      throw;
+    }
+    hipGraphExecDestroy(exec);
+    hipGraphDestroy(graph);
+  }
+  std::vector<JobLoop> lp(J);
+  st.fetch(lp.data(), gb.loop, J);
+  for (int q = 0; q < J; ++q) {
+    pcc_stats &S = act[q]->st;
+    const double sc = act[q]->dev.loss_scale;
+    S.iters = lp[q].t;
+    S.viol0 = (int64_t)lp[q].viol0;
+    S.viol_final = (int64_t)lp[q].viol_last;
+    S.loss0 = (double)lp[q].loss0 / sc;
+    S.loss_final = (double)lp[q].loss_last / sc;
+    act[q]->status = lp[q].status ? PCC_NOT_CONVERGED : PCC_OK;
+  }
+  PCC_HIP(hipEventRecord(C.ev[7], s));
+
+  // ------------------------------------------------------------------
+  // edit encoding on the device
+  // ------------------------------------------------------------------
+  EncBufs eb{};
+  eb.jobs = d_jobs;
+  eb.loop = gb.loop;
+  eb.p_off = d_poff;
+  eb.e_off = d_eoff;
+  eb.njobs = J;
+  eb.ne = ne;
+  eb.n = n;
+  eb.e_list = e_list;
+  eb.pos = pos;
+  eb.rec = rec;
+  eb.P0 = gb.P0;
+  eb.P1 = gb.P1;
+  eb.flag8 = dev<uint8_t>(ar, n);
+  eb.fpos = dev<uint32_t>(ar, n);
+  uint32_t *nflag_dev = dev<uint32_t>(ar, 1);
+  launch_edit_flags(eb, s);
+  scan_u8_u32(eb.flag8, eb.fpos, n, nflag_dev, ar, s);
+  std::vector<uint32_t> fst(J + 1);
+  {
+    uint32_t *d_fst = dev<uint32_t>(ar, J + 1);
+    uint32_t nfl = 0;
+    st.fetch(&nfl, nflag_dev, 1);
+    k_gather_u32<<<(J + 256) / 256, 256, 0, s>>>(eb.fpos, d_poff, J + 1, nfl, n, d_fst);
+    st.fetch(fst.data(), d_fst, J + 1);
+    eb.sym_off = nullptr;
+    std::vector<uint64_t> so(J + 1, 0), fb(J + 1, 0);
+    for (int q = 0; q < J; ++q) {
+      const int per = act[q]->dev.m_bits == 32 ? 2 : 1;
+      act[q]->st.n_flagged = (int64_t)fst[q + 1] - (int64_t)fst[q];
+      so[q + 1] = so[q] + (uint64_t)3 * per * (uint64_t)act[q]->st.n_flagged;
+      fb[q + 1] = fb[q] + (uint64_t)((act[q]->n + 7) / 8);
+    }
+    const size_t nsym = so[J];
+    uint64_t *d_so = dev<uint64_t>(ar, J + 1), *d_fb = dev<uint64_t>(ar, J + 1);
+    PCC_HIP(hipMemcpyAsync(d_so, so.data(), (J + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    PCC_HIP(hipMemcpyAsync(d_fb, fb.data(), (J + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    eb.sym_off = d_so;
+    eb.sym = dev<uint16_t>(ar, nsym);
+    eb.hist = dev<uint32_t>(ar, (size_t)J * 65536);
+    PCC_HIP(hipMemsetAsync(eb.hist, 0, (size_t)J * 65536 * sizeof(uint32_t), s));
+    launch_edit_codes(eb, d_fst, s);
+    uint8_t *fbytes = dev<uint8_t>(ar, fb[J]);
+    launch_flag_bytes(eb.flag8, d_poff, d_fb, J, fb[J], fbytes, s);
+    // per-job canonical Huffman tables from the histograms
+    std::vector<uint32_t> hist((size_t)J * 65536);
+    st.fetch(hist.data(), eb.hist, hist.size());
+    std::vector<HuffTable> ht(J);
+    std::vector<uint32_t> table((size_t)J * 65536, 0);
+    for (int q = 0; q < J; ++q) {
+      if (act[q]->st.n_flagged == 0) continue;
+      huffman_build(hist.data() + (size_t)q * 65536, act[q]->dev.m_bits == 8 ? 256 : 65536, ht[q]);
+      std::memcpy(table.data() + (size_t)q * 65536, ht[q].table.data(), 65536 * sizeof(uint32_t));
+    }
+    uint32_t *d_table = dev<uint32_t>(ar, table.size());
+    PCC_HIP(hipMemcpyAsync(d_table, table.data(), table.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    uint32_t *len = dev<uint32_t>(ar, nsym);
+    uint64_t *bitpos = dev<uint64_t>(ar, nsym);
+    uint64_t *d_bits_tot = dev<uint64_t>(ar, 1);
+    launch_sym_lengths(eb.sym, nsym, d_so, J, d_table, len, s);
+    scan_u32_u64(len, bitpos, nsym, d_bits_tot, ar, s);
+    std::vector<uint64_t> jb(J + 1);
+    {
+      uint64_t btot = 0;
+      st.fetch(&btot, d_bits_tot, 1);
+      int64_t *d_idx = dev<int64_t>(ar, J + 1);
+      std::vector<int64_t> idx(J + 1);
+      for (int q = 0; q <= J; ++q) idx[q] = (int64_t)so[q];
+      PCC_HIP(hipMemcpyAsync(d_idx, idx.data(), (J + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+      uint64_t *d_jb = dev<uint64_t>(ar, J + 1);
+      k_gather_u64<<<(J + 256) / 256, 256, 0, s>>>(bitpos, d_idx, J + 1, btot, nsym, d_jb);
+      st.fetch(jb.data(), d_jb, J + 1);
+    }
+    std::vector<uint64_t> w0(J + 1, 0);
+    for (int q = 0; q < J; ++q) w0[q + 1] = w0[q] + (jb[q + 1] - jb[q] + 31) / 32 + 1;
+    uint64_t *d_jb0 = dev<uint64_t>(ar, J + 1), *d_w0 = dev<uint64_t>(ar, J + 1);
+    PCC_HIP(hipMemcpyAsync(d_jb0, jb.data(), (J + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    PCC_HIP(hipMemcpyAsync(d_w0, w0.data(), (J + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    uint32_t *words = dev<uint32_t>(ar, w0[J]);
+    fill_u32(words, 0, w0[J], s);
+    launch_pack_bits(eb.sym, nsym, d_so, J, d_table, bitpos, d_jb0, d_w0, words, s);
+    bool want_debug = false;
+    for (auto *h : act) want_debug |= h->in->out.debug_xyz != nullptr;
+    double *dbg = nullptr;
+    if (want_debug) {
+      dbg = dev<double>(ar, 3 * n);
+      eb.debug = dbg;
+      launch_debug_xyz(eb, s);
+    }
+    PCC_HIP(hipEventRecord(C.ev[8], s));
+    // device -> host: flag bytes and bitstreams of all jobs in one copy each
+    const size_t fbytes_n = fb[J], words_n = w0[J];
+    std::vector<uint8_t> hflags(fbytes_n);
+    std::vector<uint32_t> hwords(words_n);
+    st.fetch(hflags.data(), fbytes, fbytes_n);
+    st.fetch(hwords.data(), words, words_n);
+    if (want_debug) {
+      for (auto *h : act) {
+        double *out = h->in->out.debug_xyz;
+        if (!out || !h->n) continue;
+        for (int a = 0; a < 3; ++a)
+          st.fetch(out + (size_t)a * h->n, dbg + (size_t)a * n + h->p_off, (size_t)h->n);
+      }
+    }
+    float ms = 0.f;
+    const float *dummy = nullptr;
+    (void)dummy;
+    // host lossless stage and stream assembly
+    const auto t_h0 = std::chrono::steady_clock::now();
+    for (int q = 0; q < J; ++q) {
+      HostJob &h = *act[q];
+      const pcc_job &j = *h.in;
+      std::vector<uint8_t> strm;
+      size_t raw = 0;
+      assemble_stream(h.n, j.params.m_bits, h.st.n_flagged, h.dev.qstep, h.dev.qoffset,
+                      hflags.data() + fb[q], fb[q + 1] - fb[q],
+                      h.st.n_flagged ? &ht[q] : nullptr, hwords.data() + w0[q], jb[q + 1] - jb[q],
+                      strm, &raw);
+      h.st.bytes_flags = (int64_t)(fb[q + 1] - fb[q]);
+      h.st.bytes_codes = (int64_t)((jb[q + 1] - jb[q] + 7) / 8);
+      h.st.bytes_stream = (int64_t)strm.size();
+      if (j.out.stream_len) *j.out.stream_len = strm.size();
+      if (j.out.stream && j.out.stream_cap >= strm.size())
+        std::memcpy(j.out.stream, strm.data(), strm.size());
+      else if (j.out.stream || j.out.stream_cap)
+        h.status = PCC_E_BUFFER_TOO_SMALL;
+    }
+    const double host_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_h0).count();
+    PCC_HIP(hipStreamSynchronize(s));
+    double stage[PCC_NSTAGES] = {};
+    for (int k = 0; k < 8; ++k) {
+      ms = 0.f;
+      if (hipEventElapsedTime(&ms, C.ev[k], C.ev[k + 1]) == hipSuccess) stage[k] = ms;
+    }
+    stage[8] = host_ms;
+    stage[9] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_wall0).count();
+    double kms[PCC_NKERNELS] = {};
+    int64_t kcnt[PCC_NKERNELS] = {};
+    kt.collect(kms, kcnt);
+    for (auto *h : act) {
+      for (int k = 0; k < PCC_NSTAGES; ++k) h->st.t_stage_ms[k] = stage[k];
+      for (int k = 0; k < PCC_NKERNELS; ++k) {
+        h->st.kernel_ms[k] = kms[k];
+        h->st.kernel_launches[k] = kcnt[k];
+      }
+    }
+  }
+
+  // retained state for the test hook
+  C.last.valid = true;
+  C.last.njobs = J;
+  C.last.p_off = p_off;
+  C.last.job_index.resize(J);
+  for (int q = 0; q < J; ++q) C.last.job_index[q] = act[q]->index;
+  C.last.n = n;
+  C.last.na = na;
+  C.last.ne = ne;
+  C.last.a_i = pb.a_i;
+  C.last.a_j = pb.a_j;
+  C.last.a_t = pb.a_t;
+  C.last.safe_root = pb.safe_par;
+  C.last.pos = pos;
+  C.last.e_list = e_list;
+
+  pcc_status first = PCC_OK;
+  for (auto *h : act) {
+    res[h->index].status = h->status;
+    res[h->index].stats = h->st;
+  }
+  for (int k = 0; k < njobs_in; ++k)
+    if (res[k].status < 0 && first == PCC_OK) first = res[k].status;
+  return first;
+}
+
+}  // namespace pcc

@@ -1,0 +1,220 @@
+"""GPU parity of the gfx950 path (through the C ABI) against the CPU oracle.
+
+Bit-exact: FoF and safe labels, active pair sets and their types, editable
+sets, iteration counts.  Float64 coordinates before quantisation: within
+1e-4 * xi per coordinate after every iteration (per-iteration through
+max_iters = k).  Every stream is decoded by both decoders and the method's
+guarantees are checked on the result.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import golden_cases
+import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_2604_18801_amd as pcc
+    assert torch.cuda.is_available()
+    c = pcc.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _pairs(ctx, job=0):
+    i = ctx.debug_fetch(job, "active_i")
+    j = ctx.debug_fetch(job, "active_j")
+    t = ctx.debug_fetch(job, "active_type")
+    order = np.lexsort((j, i))
+    return i[order], j[order], t[order]
+
+
+def _run(ctx, w, mode, **kw):
+    print("case", w.name, "n", w.n, "mode", mode, kw, flush=True)
+    stream, lab, st = ctx.correct(_dev(w.orig), _dev(w.recon), w.b, w.xi, mode=mode, box=w.box,
+                                  debug_xyz=True, **kw)
+    return stream, lab.cpu().numpy(), st
+
+
+def _compare(ctx, w, mode, **kw):
+    ref = oracle.correct(w.orig, w.recon, w.b, w.xi, mode=mode, box=w.box, **kw)
+    stream, lab, st = _run(ctx, w, mode, **kw)
+    np.testing.assert_array_equal(lab, ref.labels)
+    np.testing.assert_array_equal(ctx.debug_fetch(0, "safe_labels"), ref.safe_labels)
+    ai, aj, at = _pairs(ctx)
+    np.testing.assert_array_equal(ai, ref.a_i)
+    np.testing.assert_array_equal(aj, ref.a_j)
+    np.testing.assert_array_equal(at, ref.a_type)
+    np.testing.assert_array_equal(np.sort(ctx.debug_fetch(0, "editable")), ref.e_ids)
+    for k in ("n_pairs", "n_safe", "n_pb", "n_pc", "n_active", "n_editable", "viol0"):
+        assert st[k] == ref.stats[k], (k, st[k], ref.stats[k])
+    assert st["iters"] == ref.iters and st["status"] == ref.status
+    dp = np.abs(st["debug_xyz"] - ref.p).max() if w.n else 0.0
+    assert dp <= TOL * w.xi, dp
+    return ref, stream, st
+
+
+@pytest.mark.parametrize("case", golden_cases.load(), ids=lambda c: c["name"])
+def test_golden_fixtures(ctx, case):
+    pos = case["points"]
+    for mode in ("vp", "sc", "hf"):
+        stream, lab, st = ctx.correct(_dev(pos), _dev(pos), case["b"], case["xi"], mode=mode,
+                                      box=case["box"])
+        np.testing.assert_array_equal(lab.cpu().numpy(), case["fof"])
+        np.testing.assert_array_equal(ctx.debug_fetch(0, "safe_labels"), case["safe"])
+        ai, aj, _ = _pairs(ctx)
+        assert sorted(zip(ai.tolist(), aj.tolist())) == case["active"][mode], mode
+
+
+@pytest.mark.parametrize("mode", ["vp", "sc", "hf"])
+def test_plain_workload_full_parity(ctx, mode):
+    import paper_2604_18801_amd as pcc
+    w = synth.plain_blobs()
+    ref, stream, st = _compare(ctx, w, mode)
+    assert st["status"] == 0 and st["viol_final"] == 0
+    # both decoders on both streams; guarantees on the result
+    xg = pcc.decode(stream, w.recon)
+    np.testing.assert_array_equal(xg, oracle.decode(stream, w.recon))
+    np.testing.assert_array_equal(pcc.decode(ref.stream, w.recon), oracle.decode(ref.stream, w.recon))
+    assert np.abs(xg.astype(np.float64) - w.orig).max() <= w.xi
+    np.testing.assert_array_equal(oracle.fof_labels(xg, w.b, w.box), ref.labels)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 10, 25, 60])
+def test_plain_workload_per_iteration(ctx, k):
+    w = synth.plain_blobs()
+    ref = oracle.correct(w.orig, w.recon, w.b, w.xi, mode="vp", max_iters=k)
+    _, _, st = _run(ctx, w, "vp", max_iters=k)
+    assert st["iters"] == ref.iters == k
+    assert np.abs(st["debug_xyz"] - ref.p).max() <= TOL * w.xi
+
+
+@pytest.mark.parametrize("mode,k", [("hf", 0), ("sc", 30), ("vp", 30)])
+def test_periodic_cosmology_parity(ctx, mode, k):
+    w = synth.cosmology(32, xi=0.05)
+    _compare(ctx, w, mode, max_iters=k)
+
+
+@pytest.mark.parametrize("m", [8, 32])
+def test_bit_depths(ctx, m):
+    import paper_2604_18801_amd as pcc
+    w = synth.plain_blobs(8192, seed=9)
+    ref, stream, st = _compare(ctx, w, "hf", m_bits=m)
+    x = pcc.decode(stream, w.recon)
+    assert np.abs(x.astype(np.float64) - w.orig).max() <= w.xi
+    np.testing.assert_array_equal(oracle.fof_labels(x, w.b, w.box), ref.labels)
+
+
+def test_sgd_and_paper_margins(ctx):
+    w = synth.plain_blobs(4096, seed=5)
+    _compare(ctx, w, "hf", optimizer="sgd", lr=0.05, max_iters=40)
+    _compare(ctx, w, "sc", margin="paper", max_iters=40)
+
+
+def test_edge_cases(ctx):
+    import paper_2604_18801_amd as pcc
+    z = np.zeros((3, 0), np.float32)
+    stream, lab, st = ctx.correct(_dev(z), _dev(z), 0.1, 0.01)
+    assert st["status"] == 0 and st["n_pairs"] == 0 and len(stream) >= 64
+    assert pcc.decode(stream, z).shape == (3, 0)
+    one = np.array([[0.5], [0.5], [0.5]], np.float32)
+    stream, lab, st = ctx.correct(_dev(one), _dev(one), 0.1, 0.01)
+    assert lab.cpu().numpy().tolist() == [0] and st["n_flagged"] == 0
+    # all particles on one point: one component, no created pair
+    same = np.full((3, 300), 0.25, np.float32)
+    w = synth.Workload("same", same, same.copy(), 0.1, 0.01, (0.0, 0.0, 0.0))
+    _compare(ctx, w, "hf")
+    # xi = 0: no vulnerable pair
+    w0 = synth.plain_blobs(4096, seed=2)
+    w0 = synth.Workload("exact", w0.orig, w0.orig.copy(), w0.b, 0.0, (0.0, 0.0, 0.0))
+    ref, stream, st = _compare(ctx, w0, "vp")
+    assert st["n_active"] == 0 and st["n_flagged"] == 0
+    # two particles, each side of the threshold
+    for w in (synth.Workload("pair_pb", np.array([[0, 0.2421875], [0, 0], [0, 0]], np.float32),
+                             np.array([[-0.015625, 0.2578125], [0, 0], [0, 0]], np.float32),
+                             0.25, 0.02, (0.0, 0.0, 0.0)),
+              synth.Workload("pair_pc0", np.array([[0, 0.28125], [0, 0], [0, 0]], np.float32),
+                             np.array([[0.140625, 0.140625], [0, 0], [0, 0]], np.float32),
+                             0.25, 0.15, (0.0, 0.0, 0.0))):
+        _compare(ctx, w, "vp")
+
+
+def test_error_statuses(ctx):
+    import paper_2604_18801_amd as pcc
+    w = synth.plain_blobs(2000, seed=3)
+    bad = w.recon.copy()
+    bad[1, 7] = w.orig[1, 7] + np.float32(3 * w.xi)
+    with pytest.raises(pcc.PccError) as e:
+        ctx.correct(_dev(w.orig), _dev(bad), w.b, w.xi)
+    assert e.value.status == -5
+    nan = w.orig.copy()
+    nan[0, 3] = np.nan
+    with pytest.raises(pcc.PccError) as e:
+        ctx.correct(_dev(nan), _dev(w.recon), w.b, w.xi)
+    assert e.value.status == -1
+    with pytest.raises(pcc.PccError) as e:
+        ctx.correct(_dev(w.orig), _dev(w.recon), w.b, w.xi, m_bits=7)
+    assert e.value.status == -1
+    with pytest.raises(pcc.PccError) as e:
+        ctx.correct(_dev(w.orig), _dev(w.recon), w.b, w.xi, stream_cap=16)
+    assert e.value.status == -4
+    # the context keeps working after errors
+    _compare(ctx, w, "hf")
+
+
+def test_determinism(ctx):
+    w = synth.cosmology(32, seed=7, xi=0.05)
+    s1, l1, st1 = _run(ctx, w, "hf")
+    s2, l2, st2 = _run(ctx, w, "hf")
+    assert s1 == s2
+    np.testing.assert_array_equal(l1, l2)
+    np.testing.assert_array_equal(st1["debug_xyz"], st2["debug_xyz"])
+
+
+def test_fof_labels_entry_point(ctx):
+    for w in (synth.plain_blobs(), synth.cosmology(32, xi=0.05)):
+        lab = ctx.fof_labels(_dev(w.orig), w.b, w.box).cpu().numpy()
+        np.testing.assert_array_equal(lab, oracle.fof_labels(w.orig, w.b, w.box))
+        lab = ctx.fof_labels(w.orig, w.b, w.box)  # host memory
+        np.testing.assert_array_equal(lab, oracle.fof_labels(w.orig, w.b, w.box))
+
+
+def test_batch_equals_single_calls(ctx):
+    ws = [synth.plain_blobs(3000 + 1000 * k, seed=30 + k) for k in range(3)]
+    ws.append(synth.cosmology(20, seed=40, xi=0.05))
+    ws.append(synth.Workload("empty", np.zeros((3, 0), np.float32), np.zeros((3, 0), np.float32),
+                             0.1, 0.01, (0.0, 0.0, 0.0)))
+    modes = ["vp", "sc", "hf", "hf", "vp"]
+    jobs = [dict(orig=_dev(w.orig), recon=_dev(w.recon), b=w.b, xi=w.xi, mode=m, box=w.box,
+                 debug_xyz=True) for w, m in zip(ws, modes)]
+    out = ctx.correct_batch(jobs)
+    for (status, stream, lab, st), w, m in zip(out, ws, modes):
+        s1, l1, st1 = _run(ctx, w, m)
+        assert status == st1["status"]
+        assert stream == s1
+        np.testing.assert_array_equal(lab.cpu().numpy(), l1)
+        np.testing.assert_array_equal(st["debug_xyz"], st1["debug_xyz"])
+        assert st["iters"] == st1["iters"] and st["n_active"] == st1["n_active"]
+
+
+@pytest.mark.parametrize("mode", ["vp", "sc", "hf"])
+def test_trajectory_is_bitwise_the_oracles(ctx, mode):
+    # rows summed in increasing partner index, host pow for the bias
+    # corrections, correctly rounded division and square root: the float64
+    # iterates are the oracle's to the last bit
+    w = synth.plain_blobs()
+    ref = oracle.correct(w.orig, w.recon, w.b, w.xi, mode=mode)
+    _, _, st = _run(ctx, w, mode)
+    assert st["iters"] == ref.iters
+    np.testing.assert_array_equal(st["debug_xyz"], ref.p)

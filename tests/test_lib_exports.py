@@ -1,0 +1,60 @@
+"""The C-ABI library loads and exports every function include/pcc.h declares
+(no device call is made)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pcc.h")
+LIB = os.path.join(ROOT, "paper_2604_18801_amd", "libpcc.so")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pcc_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpcc.so not built")
+def test_every_declared_symbol_is_exported():
+    names = _declared()
+    assert "pcc_correct" in names and "pcc_correct_batch" in names
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpcc.so not built")
+def test_host_only_entry_points():
+    import paper_2604_18801_amd as pcc
+    L = pcc.lib()
+    assert pcc.version() == 1
+    assert L.pcc_status_string(-5).decode().startswith("reconstruction")
+    p = pcc.make_params(0.2, 0.05)
+    assert p.m_bits == 16 and p.mode == 2 and abs(p.lr - 1e-3) < 1e-18
+    assert L.pcc_stream_bound(1000, ctypes.byref(p)) > 1000 * 6
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpcc.so not built")
+def test_library_decoder_reads_oracle_streams():
+    # the host decoder of the library against streams written by the oracle
+    import numpy as np
+    import oracle
+    import synth
+    import paper_2604_18801_amd as pcc
+    w = synth.plain_blobs(2048, seed=21)
+    for m in (8, 16, 32):
+        r = oracle.correct(w.orig, w.recon, w.b, w.xi, mode="hf", m_bits=m)
+        np.testing.assert_array_equal(pcc.decode(r.stream, w.recon), oracle.decode(r.stream, w.recon))
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpcc.so not built")
+def test_context_creation_without_gpu_fails_cleanly():
+    import torch
+    import paper_2604_18801_amd as pcc
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(pcc.PccError):
+        pcc.Context(0)
