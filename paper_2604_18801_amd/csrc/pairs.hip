@@ -249,10 +249,23 @@ void launch_pair_write(const PairBufs &b, hipStream_t s) {
   if (b.n) k_pairs<3><<<blocks_for(b.n, 256, 1 << 30), 256, 0, s>>>(b);
 }
 
+// root of x without writing anything on the way
+__device__ inline uint32_t uf_root_ro(const uint32_t *par, uint32_t x) {
+  for (;;) {
+    const uint32_t p = ld_par(par, x);
+    if (p == x) return x;
+    x = p;
+  }
+}
+
+// After the hooks: every node points at its root.  Only the owner of a node
+// writes it, and it writes the root, so concurrent walks see either an
+// ancestor or the root and nothing can undo a finished entry (a halving
+// store from another thread could, which is why finds here do not halve).
 __global__ void k_flatten(uint32_t *par, size_t n) {
   for (size_t x = (size_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
        x += (size_t)gridDim.x * blockDim.x)
-    par[x] = uf_find(par, (uint32_t)x);
+    st_par(par, (uint32_t)x, uf_root_ro(par, (uint32_t)x));
 }
 
 void launch_flatten(uint32_t *par, size_t n, hipStream_t s) {
