@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-extra-modes", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the correction pass is built and measured on a "
@@ -113,6 +115,19 @@ def main():
     o = torch.from_numpy(w.orig).cuda()
     r = torch.from_numpy(w.recon).cuda()
     torch.cuda.synchronize()
+    probe = None
+    if args.copy_probe_mib > 0:
+        nel = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        probe = {"bytes_read": nel * 4, "bytes_written": nel * 4,
+                 "ms": round(1e3 * (time.perf_counter() - t), 3)}
+        del src, dst
+        log("copy probe: %s" % probe)
 
     def step(mode=args.mode, **kw):
         return ctx.correct(o, r, w.b, w.xi, mode=mode, box=w.box, **kw)
@@ -172,6 +187,8 @@ def main():
         "kernel_ms_per_step": {k: round(v / len(stats), 3) for k, v in kms.items()},
         "roofline": roofline,
     }
+    if probe:
+        out["copy_probe"] = probe
     if not args.no_verify:
         memb, boxv = verify(ctx, w, stream, labels)
         out["membership_errors"] = memb

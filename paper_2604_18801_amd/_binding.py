@@ -13,7 +13,8 @@ from typing import Dict, List, Optional, Sequence, Tuple
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpcc.so")
+# PCC_LIBRARY selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("PCC_LIBRARY") or os.path.join(HERE, "libpcc.so")
 
 OK, NOT_CONVERGED = 0, 1
 MODES = {"vp": 0, "sc": 1, "hf": 2}

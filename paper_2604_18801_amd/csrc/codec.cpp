@@ -66,6 +66,9 @@ Zstd &zstd() {
 // public parameter numbers of ZSTD_CCtx_setParameter
 constexpr int kZstdLevel = 100;
 constexpr int kZstdWorkers = 400;
+// ZSTD level of the stream payload: the payload is mostly Huffman output and
+// a sparse flag mask, for which the fastest level loses little
+constexpr int kZstdLevelDefault = 1;
 
 template <typename T>
 void put(std::vector<uint8_t> &b, size_t at, T v) {
@@ -212,7 +215,7 @@ void assemble_stream(int64_t n, int m_bits, int64_t nflagged, double qstep, doub
   }
   *payload_raw = raw;
   std::vector<uint8_t> z;
-  const bool zok = zstd_compress(pay.data(), pay.size(), z, 3);
+  const bool zok = zstd_compress(pay.data(), pay.size(), z, kZstdLevelDefault);
   const std::vector<uint8_t> &stored = zok ? z : pay;
   out.assign(kHeader + stored.size(), 0);
   put<uint32_t>(out, 0, kMagic);

@@ -46,7 +46,6 @@ __global__ void k_edit_codes(EncBufs B, const uint32_t *fstart) {
     const int per = J.m_bits == 32 ? 2 : 1;
     const uint64_t nf = (B.sym_off[j + 1] - B.sym_off[j]) / (uint64_t)(3 * per);
     const uint64_t at = (uint64_t)(B.fpos[g] - fstart[j]);
-    uint32_t *hist = B.hist + (size_t)j * 65536;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       double qv = rint((d[a] + J.qoffset) / J.qstep);
@@ -54,14 +53,10 @@ __global__ void k_edit_codes(EncBufs B, const uint32_t *fstart) {
       const uint64_t code = (uint64_t)qv;
       const uint64_t base = B.sym_off[j] + (uint64_t)a * per * nf + per * at;
       if (per == 2) {
-        const uint16_t lo = (uint16_t)(code & 0xffffu), hi = (uint16_t)(code >> 16);
-        B.sym[base] = lo;
-        B.sym[base + 1] = hi;
-        atomicAdd(hist + lo, 1u);
-        atomicAdd(hist + hi, 1u);
+        B.sym[base] = (uint16_t)(code & 0xffffu);
+        B.sym[base + 1] = (uint16_t)(code >> 16);
       } else {
         B.sym[base] = (uint16_t)code;
-        atomicAdd(hist + code, 1u);
       }
     }
   }
@@ -150,6 +145,62 @@ void launch_pack_bits(const uint16_t *sym, size_t nsym, const uint64_t *sym_off,
   if (nsym)
     k_pack<<<blocks_for(nsym, 256, 65536), 256, 0, s>>>(sym, nsym, sym_off, njobs, table, bitpos,
                                                         job_bit0, job_word0, words);
+}
+
+// Histogram of the symbols of every job without contended atomics: keys
+// (job, symbol) are sorted, and the length of every run of equal keys is
+// stored in its bin.
+__global__ void k_hist_keys(const uint16_t *sym, size_t nsym, const uint64_t *sym_off, int njobs,
+                            uint32_t *keys, uint32_t *idx) {
+  for (size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x; s < nsym;
+       s += (size_t)gridDim.x * blockDim.x) {
+    const int j = job_of_u64(sym_off, njobs, s);
+    keys[s] = ((uint32_t)j << 16) | sym[s];
+    idx[s] = 0;
+  }
+}
+__global__ void k_run_flags(const uint32_t *keys, size_t nsym, uint8_t *flag) {
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < nsym;
+       q += (size_t)gridDim.x * blockDim.x)
+    flag[q] = (q == 0 || keys[q] != keys[q - 1]) ? 1 : 0;
+}
+__global__ void k_run_starts(const uint8_t *flag, const uint32_t *rank, size_t nsym,
+                             uint32_t *starts) {
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < nsym;
+       q += (size_t)gridDim.x * blockDim.x)
+    if (flag[q]) starts[rank[q]] = (uint32_t)q;
+}
+// run r spans [starts[r], starts[r + 1]); its length is its key's count
+__global__ void k_run_hist(const uint32_t *keys, const uint32_t *starts, const uint32_t *nruns,
+                           size_t nsym, uint32_t *hist) {
+  const uint32_t R = *nruns;
+  for (size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x; r < R;
+       r += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t s = starts[r];
+    const uint32_t e = r + 1 < R ? starts[r + 1] : (uint32_t)nsym;
+    const uint32_t k = keys[s];
+    hist[(size_t)(k >> 16) * 65536 + (k & 0xffffu)] = e - s;
+  }
+}
+
+void symbol_histogram(const uint16_t *sym, size_t nsym, const uint64_t *sym_off, int njobs,
+                      uint32_t *hist, Arena &ar, hipStream_t s) {
+  fill_u32(hist, 0, (size_t)njobs * 65536, s);
+  if (!nsym) return;
+  if (nsym > 0xffffffffull) throw Error(-6, "more than 2^32 - 1 edit symbols");
+  uint32_t *keys = ar.get<uint32_t>(nsym), *idx = ar.get<uint32_t>(nsym);
+  uint8_t *flag = ar.get<uint8_t>(nsym);
+  uint32_t *rank = ar.get<uint32_t>(nsym), *starts = ar.get<uint32_t>(nsym);
+  uint32_t *nruns = ar.get<uint32_t>(1);
+  const int nb = blocks_for(nsym, 256, 65536);
+  k_hist_keys<<<nb, 256, 0, s>>>(sym, nsym, sym_off, njobs, keys, idx);
+  int jb = 0;
+  while (jb < 16 && ((uint32_t)(njobs - 1) >> jb) != 0) ++jb;
+  radix_sort_u32(keys, idx, nsym, 16 + jb, ar, s);
+  k_run_flags<<<nb, 256, 0, s>>>(keys, nsym, flag);
+  scan_u8_u32(flag, rank, nsym, nruns, ar, s);
+  k_run_starts<<<nb, 256, 0, s>>>(flag, rank, nsym, starts);
+  k_run_hist<<<nb, 256, 0, s>>>(keys, starts, nruns, nsym, hist);
 }
 
 // float64 coordinates before quantisation, in each job's particle order

@@ -57,9 +57,19 @@ struct PairBufs {
   uint64_t *f_key;
   uint32_t *f_u, *f_v;
 };
-void launch_pair_pass1(const PairBufs &b, hipStream_t s);   // classify, hook, count V
-void launch_pair_count(const PairBufs &b, hipStream_t s);   // mode-filtered counts
-void launch_pair_write(const PairBufs &b, hipStream_t s);   // mode-filtered writes
+// Work plan of the pair passes: particles of sparse cells (one thread each)
+// and (cell, 64-particle chunk) units of dense cells (one wave each).
+struct PairPlan {
+  uint32_t *sparse = nullptr;
+  size_t n_sparse = 0;
+  uint32_t *ucell = nullptr, *uchunk = nullptr;
+  size_t n_units = 0;
+};
+void plan_pairs(PairPlan &pl, const uint32_t *cell_of, const uint32_t *cell_start,
+                const uint32_t *n_cells, size_t n, Arena &ar, hipStream_t s);
+void launch_pair_pass1(const PairBufs &b, const PairPlan &pl, hipStream_t s);  // classify, hook
+void launch_pair_count(const PairBufs &b, const PairPlan &pl, hipStream_t s);  // filtered counts
+void launch_pair_write(const PairBufs &b, const PairPlan &pl, hipStream_t s);  // filtered writes
 void launch_flatten(uint32_t *par, size_t n, hipStream_t s);
 void launch_labels(const uint32_t *root, const float4 *pos, const int64_t *p_off, int njobs,
                    size_t n, uint32_t *minid, int32_t *lab_global, hipStream_t s);
@@ -74,6 +84,8 @@ struct PgdBufs {
   const JobDev *jobs;
   JobLoop *loop;
   const int64_t *e_off;   // [njobs+1] editable rows per job
+  const int64_t *tile_off;  // [njobs+1] first 64-row tile of each job
+  int64_t ntiles;
   int njobs;
   size_t ne;
   const uint32_t *row_ptr, *col;
@@ -86,9 +98,15 @@ void sort_pairs(uint32_t *a_i, uint32_t *a_j, uint8_t *a_t, size_t na, const flo
                 int id_bits, Arena &ar, hipStream_t s);
 void mark_editable(const uint32_t *a_i, const uint32_t *a_j, size_t na, size_t n, uint8_t *is_e,
                    uint32_t *eid, uint32_t *ne_dev, Arena &ar, hipStream_t s);
+void list_editable(const uint8_t *is_e, const uint32_t *eid, size_t n, uint32_t *e_list,
+                   hipStream_t s);
+// reorders the editable rows (job-major, then Morton order of their cells);
+// e_list and eid are updated in place
+void order_rows(uint32_t *e_list, size_t ne, uint32_t *eid, const float4 *pos, const JobDev *jobs,
+                const int64_t *p_off, int njobs, Arena &ar, hipStream_t s);
 void build_csr(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t, size_t na,
-               const uint8_t *is_e, const uint32_t *eid, size_t n, uint32_t ne, uint32_t *e_list,
-               uint32_t *row_ptr, uint32_t *col, Arena &ar, hipStream_t s);
+               const uint32_t *eid, uint32_t ne, uint32_t *row_ptr, uint32_t *col, Arena &ar,
+               hipStream_t s);
 void launch_pgd_init(const uint32_t *e_list, size_t ne, const float4 *pos, const float4 *rec,
                      double4 *P0, float4 *xo, double *m, double *v, hipStream_t s);
 void launch_loop_init(const JobDev *jobs, JobLoop *loop, int njobs, int32_t *n_active,
@@ -117,6 +135,9 @@ struct EncBufs {
 void launch_edit_flags(const EncBufs &b, hipStream_t s);
 // fstart[j]: flagged particles before job j in the global order
 void launch_edit_codes(const EncBufs &b, const uint32_t *fstart, hipStream_t s);
+// per-job histograms [njobs][65536] of the symbols
+void symbol_histogram(const uint16_t *sym, size_t nsym, const uint64_t *sym_off, int njobs,
+                      uint32_t *hist, Arena &ar, hipStream_t s);
 void launch_flag_bytes(const uint8_t *flag8, const int64_t *p_off, const uint64_t *fb_off,
                        int njobs, size_t nbytes, uint8_t *bytes, hipStream_t s);
 void launch_sym_lengths(const uint16_t *sym, size_t nsym, const uint64_t *sym_off, int njobs,

@@ -12,6 +12,8 @@
 #include "kernels.hpp"
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 
 namespace pcc {
 
@@ -56,6 +58,12 @@ __device__ inline void uf_union(uint32_t *par, uint32_t a, uint32_t b) {
                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
       return;
   }
+}
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // ----------------------------------------------------------------------------
@@ -138,29 +146,123 @@ __device__ inline double dist2_exact(const float4 &a, const float4 &b, const Job
   return (dx * dx + dy * dy) + dz * dz;
 }
 
+// State of one home particle k during a pass.
+struct Home {
+  uint32_t k;
+  float4 pi, ri;
+  uint32_t sk, fk;     // safe and FoF roots (passes 2 and 3)
+  uint64_t wa, wf;     // write cursors (pass 3)
+  uint32_t ca, cf;     // counts (passes 1 and 2)
+};
+
 template <int PASS>
-__global__ void __launch_bounds__(256) k_pairs(PairBufs B) {
-  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = k < B.n;
-  const int job = valid ? job_of(B.p_off, B.njobs, (int64_t)k) : 0;
-  unsigned long long cnt[3] = {0ull, 0ull, 0ull};  // safe, pb, pc
-  if (valid) {
-    const JobPair q = load_job(B.jobs[job]);
-    const float4 pi = B.pos[k];
-    const uint32_t cell = B.cell_of[k];
-    uint32_t sk = 0, fk = 0;
-    float4 ri = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (PASS >= 2) {
-      sk = B.safe_par[k];
-      fk = B.fof_par[k];
+__device__ inline void home_begin(const PairBufs &B, Home &h, uint32_t k) {
+  h.k = k;
+  h.pi = B.pos[k];
+  h.ri = make_float4(0.f, 0.f, 0.f, 0.f);
+  h.sk = h.fk = 0;
+  if (PASS >= 2) {
+    h.sk = B.safe_par[k];
+    h.fk = B.fof_par[k];
+  }
+  if (PASS == 3) h.ri = B.rec[k];
+  h.wa = PASS == 3 ? B.off_a[k] : 0;
+  h.wf = PASS == 3 ? B.off_f[k] : 0;
+  h.ca = h.cf = 0;
+}
+
+template <int PASS>
+__device__ inline void home_end(const PairBufs &B, const Home &h) {
+  if (PASS == 1) B.cnt_a[h.k] = h.ca;
+  if (PASS == 2) {
+    B.cnt_a[h.k] = h.ca;
+    B.cnt_f[h.k] = h.cf;
+  }
+}
+
+// One candidate partner j of the home particle: float32 prefilter, exact
+// float64 class, then the work of the pass.
+template <int PASS>
+__device__ inline void visit(const PairBufs &B, const JobPair &q, Home &h, uint32_t j,
+                             const float4 &pj, unsigned long long (&cnt)[3]) {
+  const float dx = wrap_f(h.pi.x - pj.x, q.Lf[0], q.hLf[0]);
+  const float dy = wrap_f(h.pi.y - pj.y, q.Lf[1], q.hLf[1]);
+  const float dz = wrap_f(h.pi.z - pj.z, q.Lf[2], q.hLf[2]);
+  const float d2f = (dx * dx + dy * dy) + dz * dz;
+  if (d2f > q.rv2f) return;
+  const double d2 = dist2_exact(h.pi, pj, q);
+  if (d2 > q.rv2) return;
+  const int cls = d2 <= q.rs2 ? kSafe : (d2 <= q.b2 ? kPb : kPc);
+  if (PASS == 1) {
+    if (cls == kSafe) {
+      cnt[0]++;
+      uf_union(B.safe_par, h.k, j);
+      uf_union(B.fof_par, h.k, j);
+    } else if (cls == kPb) {
+      cnt[1]++;
+      h.ca++;
+      uf_union(B.fof_par, h.k, j);
+    } else {
+      cnt[2]++;
+      h.ca++;
     }
-    if (PASS == 3) ri = B.rec[k];
-    uint64_t wa = PASS == 3 ? B.off_a[k] : 0, wf = PASS == 3 ? B.off_f[k] : 0;
-    uint32_t ca = 0, cf = 0;
+    return;
+  }
+  if (cls == kSafe) return;
+  bool to_a = false, to_f = false;
+  if (q.mode == 0) {
+    to_a = true;
+  } else if (q.mode == 1) {
+    to_a = B.safe_par[j] != h.sk;
+  } else if (cls == kPc) {
+    to_a = B.fof_par[j] != h.fk;
+  } else {
+    to_f = B.safe_par[j] != h.sk;
+  }
+  if (PASS == 2) {
+    h.ca += to_a;
+    h.cf += to_f;
+    return;
+  }
+  if (to_a) {
+    B.a_i[h.wa] = h.k;
+    B.a_j[h.wa] = j;
+    B.a_t[h.wa] = (uint8_t)cls;
+    h.wa++;
+  }
+  if (to_f) {
+    const float4 rj = B.rec[j];
+    const double ex = wrap_d((double)h.ri.x - (double)rj.x, q.L[0], q.hL[0]);
+    const double ey = wrap_d((double)h.ri.y - (double)rj.y, q.L[1], q.hL[1]);
+    const double ez = wrap_d((double)h.ri.z - (double)rj.z, q.L[2], q.hL[2]);
+    const uint64_t viol0 = ((ex * ex + ey * ey) + ez * ez) > q.bm2 ? 1ull : 0ull;
+    const uint32_t li = __float_as_uint(h.pi.w), lj = __float_as_uint(pj.w);
+    const uint64_t lo = li < lj ? li : lj, hi = li < lj ? lj : li;
+    B.f_key[h.wf] = (viol0 << 62) | (lo << 31) | hi;
+    B.f_u[h.wf] = h.sk;
+    B.f_v[h.wf] = B.safe_par[j];
+    h.wf++;
+  }
+}
+
+// Sparse cells: one thread per particle (list of particles of cells with
+// fewer than kDenseCell members).  Partners: later particles of its own cell,
+// then every particle of the 13 forward cells, in index order.
+template <int PASS>
+__global__ void __launch_bounds__(256) k_pairs_sparse(PairBufs B, const uint32_t *list, size_t m) {
+  unsigned long long cnt[3] = {0ull, 0ull, 0ull};  // safe, pb, pc
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int cjob = t < m ? job_of(B.p_off, B.njobs, (int64_t)list[t]) : -1;
+  if (t < m) {
+    const uint32_t k = list[t];
+    const JobPair q = load_job(B.jobs[cjob]);
+    Home h;
+    home_begin<PASS>(B, h, k);
+    const uint32_t cell = B.cell_of[k];
     for (int s = 0; s < 14; ++s) {
       uint32_t j0, j1;
       if (s == 0) {
-        j0 = (uint32_t)k + 1;
+        j0 = k + 1;
         j1 = B.cell_start[cell + 1];
       } else {
         const int32_t nb = B.nbr[(size_t)cell * 13 + s - 1];
@@ -168,85 +270,150 @@ __global__ void __launch_bounds__(256) k_pairs(PairBufs B) {
         j0 = B.cell_start[nb];
         j1 = B.cell_start[nb + 1];
       }
-      for (uint32_t j = j0; j < j1; ++j) {
-        const float4 pj = B.pos[j];
-        const float dx = wrap_f(pi.x - pj.x, q.Lf[0], q.hLf[0]);
-        const float dy = wrap_f(pi.y - pj.y, q.Lf[1], q.hLf[1]);
-        const float dz = wrap_f(pi.z - pj.z, q.Lf[2], q.hLf[2]);
-        const float d2f = (dx * dx + dy * dy) + dz * dz;
-        if (d2f > q.rv2f) continue;
-        const double d2 = dist2_exact(pi, pj, q);
-        if (d2 > q.rv2) continue;
-        const int cls = d2 <= q.rs2 ? kSafe : (d2 <= q.b2 ? kPb : kPc);
-        if (PASS == 1) {
-          if (cls == kSafe) {
-            cnt[0]++;
-            uf_union(B.safe_par, (uint32_t)k, j);
-            uf_union(B.fof_par, (uint32_t)k, j);
-          } else if (cls == kPb) {
-            cnt[1]++;
-            ca++;
-            uf_union(B.fof_par, (uint32_t)k, j);
-          } else {
-            cnt[2]++;
-            ca++;
-          }
-          continue;
-        }
-        if (cls == kSafe) continue;
-        bool to_a = false, to_f = false;
-        if (q.mode == 0) {
-          to_a = true;
-        } else if (q.mode == 1) {
-          to_a = B.safe_par[j] != sk;
-        } else if (cls == kPc) {
-          to_a = B.fof_par[j] != fk;
-        } else {
-          to_f = B.safe_par[j] != sk;
-        }
-        if (PASS == 2) {
-          ca += to_a;
-          cf += to_f;
-        } else {
-          if (to_a) {
-            B.a_i[wa] = (uint32_t)k;
-            B.a_j[wa] = j;
-            B.a_t[wa] = (uint8_t)cls;
-            wa++;
-          }
-          if (to_f) {
-            const float4 rj = B.rec[j];
-            const double ex = wrap_d((double)ri.x - (double)rj.x, q.L[0], q.hL[0]);
-            const double ey = wrap_d((double)ri.y - (double)rj.y, q.L[1], q.hL[1]);
-            const double ez = wrap_d((double)ri.z - (double)rj.z, q.L[2], q.hL[2]);
-            const uint64_t viol0 = ((ex * ex + ey * ey) + ez * ez) > q.bm2 ? 1ull : 0ull;
-            const uint32_t li = __float_as_uint(pi.w), lj = __float_as_uint(pj.w);
-            const uint64_t lo = li < lj ? li : lj, hi = li < lj ? lj : li;
-            B.f_key[wf] = (viol0 << 62) | (lo << 31) | hi;
-            B.f_u[wf] = sk;
-            B.f_v[wf] = B.safe_par[j];
-            wf++;
-          }
+      for (uint32_t j = j0; j < j1; ++j) visit<PASS>(B, q, h, j, B.pos[j], cnt);
+    }
+    home_end<PASS>(B, h);
+  }
+  if (PASS == 1) job_add<3>(B.job_counts, cjob, cjob >= 0, cnt);
+}
+
+constexpr int kPairWaves = 4;
+
+// Dense cells: one wave per 64 home particles of one cell.  Each partner
+// cell is staged through LDS 64 particles at a time with coalesced loads;
+// every lane then runs over the same staged particles (broadcast reads), so
+// the lanes of a wave never diverge on trip counts.  Every home particle
+// sees its partners in the same order as in the sparse kernel.
+template <int PASS>
+__global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense(PairBufs B, const uint32_t *ucell,
+                                                                 const uint32_t *uchunk, size_t m) {
+  __shared__ float4 stage[kPairWaves][64];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const size_t unit = (size_t)blockIdx.x * kPairWaves + w;
+  if (unit >= m) return;  // the whole wave leaves together
+  const uint32_t cell = ucell[unit];
+  const uint32_t cs = B.cell_start[cell], ce = B.cell_start[cell + 1];
+  const uint32_t k0 = cs + 64u * uchunk[unit];
+  const uint32_t nh = (ce - k0) < 64u ? (ce - k0) : 64u;
+  const bool valid = (uint32_t)lane < nh;
+  const int job = __builtin_amdgcn_readfirstlane(job_of(B.p_off, B.njobs, (int64_t)k0));
+  const JobPair q = load_job(B.jobs[job]);
+  unsigned long long cnt[3] = {0ull, 0ull, 0ull};
+  Home h;
+  home_begin<PASS>(B, h, valid ? k0 + lane : k0);
+  for (int s = 0; s < 14; ++s) {
+    uint32_t j0, j1;
+    if (s == 0) {
+      j0 = k0 + 1;  // later particles of the home cell
+      j1 = ce;
+    } else {
+      const int32_t nb = B.nbr[(size_t)cell * 13 + s - 1];
+      if (nb < 0) continue;
+      j0 = B.cell_start[nb];
+      j1 = B.cell_start[nb + 1];
+    }
+    for (uint32_t t0 = j0; t0 < j1; t0 += 64) {
+      const uint32_t cnt_t = (j1 - t0) < 64u ? (j1 - t0) : 64u;
+      if ((uint32_t)lane < cnt_t) stage[w][lane] = B.pos[t0 + lane];
+      wave_sync();
+      if (valid) {
+        for (uint32_t t = 0; t < cnt_t; ++t) {
+          const uint32_t j = t0 + t;
+          if (s == 0 && j <= h.k) continue;
+          visit<PASS>(B, q, h, j, stage[w][t], cnt);
         }
       }
-    }
-    if (PASS == 1) B.cnt_a[k] = ca;
-    if (PASS == 2) {
-      B.cnt_a[k] = ca;
-      B.cnt_f[k] = cf;
+      wave_sync();
     }
   }
+  if (valid) home_end<PASS>(B, h);
   if (PASS == 1) job_add<3>(B.job_counts, job, valid, cnt);
 }
 
-void launch_pair_pass1(const PairBufs &b, hipStream_t s) {
-  if (b.n) k_pairs<1><<<blocks_for(b.n, 256, 1 << 30), 256, 0, s>>>(b);
+constexpr int kDenseCell = 32;
+
+// particles of sparse cells, and (cell, 64-chunk) units of dense cells
+__global__ void k_sparse_flags(const uint32_t *cell_of, const uint32_t *cell_start, size_t n,
+                               uint8_t *flag) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t c = cell_of[k];
+    flag[k] = (cell_start[c + 1] - cell_start[c]) < (uint32_t)kDenseCell ? 1 : 0;
+  }
 }
-void launch_pair_count(const PairBufs &b, hipStream_t s) {
-  if (b.n) k_pairs<2><<<blocks_for(b.n, 256, 1 << 30), 256, 0, s>>>(b);
+__global__ void k_sparse_list(const uint8_t *flag, const uint32_t *pos32, size_t n, uint32_t *list) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (size_t)gridDim.x * blockDim.x)
+    if (flag[k]) list[pos32[k]] = (uint32_t)k;
 }
-void launch_pair_write(const PairBufs &b, hipStream_t s) {
-  if (b.n) k_pairs<3><<<blocks_for(b.n, 256, 1 << 30), 256, 0, s>>>(b);
+__global__ void k_unit_counts(const uint32_t *cell_start, const uint32_t *n_cells, size_t max_cells,
+                              uint32_t *units) {
+  const uint32_t U = *n_cells;
+  for (size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x; u < max_cells;
+       u += (size_t)gridDim.x * blockDim.x) {
+    uint32_t c = 0;
+    if (u < U) {
+      const uint32_t nu = cell_start[u + 1] - cell_start[u];
+      c = nu >= (uint32_t)kDenseCell ? (nu + 63u) / 64u : 0u;
+    }
+    units[u] = c;
+  }
+}
+__global__ void k_unit_list(const uint32_t *units, const uint32_t *uoff, size_t max_cells,
+                            uint32_t *ucell, uint32_t *uchunk) {
+  for (size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x; u < max_cells;
+       u += (size_t)gridDim.x * blockDim.x)
+    for (uint32_t c = 0; c < units[u]; ++c) {
+      ucell[uoff[u] + c] = (uint32_t)u;
+      uchunk[uoff[u] + c] = c;
+    }
+}
+
+void plan_pairs(PairPlan &pl, const uint32_t *cell_of, const uint32_t *cell_start,
+                const uint32_t *n_cells, size_t n, Arena &ar, hipStream_t s) {
+  uint8_t *flag = ar.get<uint8_t>(n ? n : 1);
+  uint32_t *pos32 = ar.get<uint32_t>(n ? n : 1);
+  uint32_t *cnt = ar.get<uint32_t>(2);
+  pl.sparse = ar.get<uint32_t>(n ? n : 1);
+  uint32_t *units = ar.get<uint32_t>(n ? n : 1), *uoff = ar.get<uint32_t>(n ? n : 1);
+  pl.ucell = ar.get<uint32_t>(n ? n : 1);
+  pl.uchunk = ar.get<uint32_t>(n ? n : 1);
+  const int nb = blocks_for(n, 256, 65536);
+  if (n) {
+    k_sparse_flags<<<nb, 256, 0, s>>>(cell_of, cell_start, n, flag);
+    scan_u8_u32(flag, pos32, n, cnt, ar, s);
+    k_sparse_list<<<nb, 256, 0, s>>>(flag, pos32, n, pl.sparse);
+    k_unit_counts<<<nb, 256, 0, s>>>(cell_start, n_cells, n, units);
+    scan_u32_u32(units, uoff, n, cnt + 1, ar, s);
+    k_unit_list<<<nb, 256, 0, s>>>(units, uoff, n, pl.ucell, pl.uchunk);
+  } else {
+    PCC_HIP(hipMemsetAsync(cnt, 0, 2 * sizeof(uint32_t), s));
+  }
+  uint32_t h[2] = {0, 0};
+  PCC_HIP(hipMemcpyAsync(h, cnt, sizeof h, hipMemcpyDeviceToHost, s));
+  PCC_HIP(hipStreamSynchronize(s));
+  pl.n_sparse = h[0];
+  pl.n_units = h[1];
+}
+
+template <int PASS>
+static void launch_pairs(const PairBufs &b, const PairPlan &pl, hipStream_t s) {
+  if (pl.n_sparse)
+    k_pairs_sparse<PASS><<<blocks_for(pl.n_sparse, 256, 1 << 30), 256, 0, s>>>(b, pl.sparse,
+                                                                                pl.n_sparse);
+  if (pl.n_units)
+    k_pairs_dense<PASS><<<(unsigned)((pl.n_units + kPairWaves - 1) / kPairWaves), 64 * kPairWaves,
+                          0, s>>>(b, pl.ucell, pl.uchunk, pl.n_units);
+}
+
+void launch_pair_pass1(const PairBufs &b, const PairPlan &pl, hipStream_t s) {
+  launch_pairs<1>(b, pl, s);
+}
+void launch_pair_count(const PairBufs &b, const PairPlan &pl, hipStream_t s) {
+  launch_pairs<2>(b, pl, s);
+}
+void launch_pair_write(const PairBufs &b, const PairPlan &pl, hipStream_t s) {
+  launch_pairs<3>(b, pl, s);
 }
 
 // root of x without writing anything on the way
@@ -301,18 +468,43 @@ void launch_labels(const uint32_t *root, const float4 *pos, const int64_t *p_off
 // With distinct keys the minimum spanning forest is unique, so this equals
 // Kruskal's forest in ascending key order.
 // ----------------------------------------------------------------------------
-__global__ void k_bor_min(const uint64_t *key, const uint32_t *u, const uint32_t *v, size_t m,
-                          uint32_t *bpar, unsigned long long *best, uint8_t *alive) {
-  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < m;
-       c += (size_t)gridDim.x * blockDim.x) {
-    const uint32_t cu = uf_find(bpar, u[c]), cv = uf_find(bpar, v[c]);
-    if (cu == cv) {
-      alive[c] = 0;
-      continue;
+// Each alive edge offers its key to the best (smallest) edge of both of its
+// components.  Edges of one home particle sit in consecutive lanes and share
+// their first component: a segmented minimum over such runs leaves one
+// atomic per run; a read of the current best skips atomics that cannot win.
+__global__ void __launch_bounds__(256) k_bor_min(const uint64_t *key, const uint32_t *u,
+                                                 const uint32_t *v, size_t m, uint32_t *bpar,
+                                                 unsigned long long *best, uint8_t *alive) {
+  const int lane = threadIdx.x & 63;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  // the loop runs the same number of times in every lane of a wave
+  const size_t base0 = (size_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
+  for (size_t b0 = base0; b0 < m; b0 += stride) {
+    const size_t c = b0 + lane;
+    const bool in = c < m;
+    uint32_t cu = 0xffffffffu, cv = 0xffffffffu;
+    unsigned long long k = ~0ull;
+    bool live = false;
+    if (in) {
+      cu = uf_find(bpar, u[c]);
+      cv = uf_find(bpar, v[c]);
+      live = cu != cv;
+      alive[c] = live ? 1 : 0;
+      k = key[c];
     }
-    alive[c] = 1;
-    atomicMin(best + cu, (unsigned long long)key[c]);
-    atomicMin(best + cv, (unsigned long long)key[c]);
+    // segmented minimum over runs of equal cu among live lanes
+    const uint32_t gid = live ? cu : 0xffffffffu;
+    unsigned long long seg = live ? k : ~0ull;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const unsigned long long o = __shfl_down(seg, d, kWave);
+      const uint32_t og = __shfl_down(gid, d, kWave);
+      if (lane + d < 64 && og == gid && o < seg) seg = o;
+    }
+    const uint32_t prev = __shfl_up(gid, 1, kWave);
+    const bool head = live && (lane == 0 || prev != gid);
+    if (head && best[cu] > seg) atomicMin(best + cu, seg);
+    if (live && best[cv] > k) atomicMin(best + cv, k);
   }
 }
 
@@ -355,16 +547,36 @@ __global__ void k_bor_emit(const uint64_t *key, const uint32_t *u, size_t m, con
   }
 }
 
-__global__ void k_bor_compact(const uint64_t *key, const uint32_t *u, const uint32_t *v, size_t m,
-                              const uint8_t *alive, const uint32_t *pos32, uint64_t *nkey,
+// After the round's unions: candidates that were not selected are kept only
+// if their ends are still in different components, and carry the current
+// roots, so the next round's finds end at once.
+__global__ void k_bor_relabel(const uint32_t *u, const uint32_t *v, size_t m, const uint8_t *sel,
+                              uint32_t *bpar, uint32_t *ru, uint32_t *rv, uint8_t *alive) {
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < m;
+       c += (size_t)gridDim.x * blockDim.x) {
+    uint8_t a = 0;
+    uint32_t cu = 0, cv = 0;
+    if (!sel[c]) {
+      cu = uf_find(bpar, u[c]);
+      cv = uf_find(bpar, v[c]);
+      a = cu != cv ? 1 : 0;
+    }
+    alive[c] = a;
+    ru[c] = cu;
+    rv[c] = cv;
+  }
+}
+
+__global__ void k_bor_compact(const uint64_t *key, const uint32_t *ru, const uint32_t *rv,
+                              size_t m, const uint8_t *alive, const uint32_t *pos32, uint64_t *nkey,
                               uint32_t *nu, uint32_t *nv) {
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < m;
        c += (size_t)gridDim.x * blockDim.x) {
     if (!alive[c]) continue;
     const uint32_t p = pos32[c];
     nkey[p] = key[c];
-    nu[p] = u[c];
-    nv[p] = v[c];
+    nu[p] = ru[c];
+    nv[p] = rv[c];
   }
 }
 
@@ -381,6 +593,7 @@ int64_t boruvka(uint64_t *key, uint32_t *u, uint32_t *v, size_t ncand, uint32_t 
   uint64_t *key2 = ar.get<uint64_t>(ncand);
   uint32_t *u2 = ar.get<uint32_t>(ncand);
   uint32_t *v2 = ar.get<uint32_t>(ncand);
+  uint32_t *ru = ar.get<uint32_t>(ncand), *rv = ar.get<uint32_t>(ncand);
   uint32_t *hcnt = nullptr;
   PCC_HIP(hipHostMalloc((void **)&hcnt, 2 * sizeof(uint32_t), hipHostMallocDefault));
   int64_t emitted = 0;
@@ -395,11 +608,15 @@ int64_t boruvka(uint64_t *key, uint32_t *u, uint32_t *v, size_t ncand, uint32_t 
       scan_u8_u32(sel, pos32, m, cnt, ar, s);
       k_bor_emit<<<nb, 256, 0, s>>>(key, u, m, sel, pos32, inv_perm, p_off, njobs,
                                     out_i + emitted, out_j + emitted, out_t + emitted);
+      k_bor_relabel<<<nb, 256, 0, s>>>(u, v, m, sel, bpar, ru, rv, alive);
       scan_u8_u32(alive, pos32, m, cnt + 1, ar, s);
-      k_bor_compact<<<nb, 256, 0, s>>>(key, u, v, m, alive, pos32, key2, u2, v2);
+      k_bor_compact<<<nb, 256, 0, s>>>(key, ru, rv, m, alive, pos32, key2, u2, v2);
       PCC_HIP(hipMemcpyAsync(hcnt, cnt, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
       PCC_HIP(hipStreamSynchronize(s));
       emitted += hcnt[0];
+      if (getenv("PCC_VERBOSE"))
+        fprintf(stderr, "[pcc] forest round: %zu candidates, %u selected, %u left\n", m, hcnt[0],
+                hcnt[1]);
       if (hcnt[0] == 0 && hcnt[1] != 0)
         throw Error(-3, "spanning forest made no progress");
       m = hcnt[1];

@@ -503,6 +503,8 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
   build_cells(keys, n, cell_of, cell_start, cell_key, n_cells, ar, s);
   int32_t *nbr = dev<int32_t>(ar, n * 13);
   launch_neighbors(d_jobs, d_cbase, J, cell_key, n_cells, n, nbr, s);
+  PairPlan plan;
+  plan_pairs(plan, cell_of, cell_start, n_cells, n, ar, s);
   PCC_HIP(hipEventRecord(C.ev[2], s));
 
   // ------------------------------------------------------------------
@@ -528,7 +530,7 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
   PCC_HIP(hipMemsetAsync(pb.job_counts, 0, 3 * J * sizeof(unsigned long long), s));
   {
     const int at = kt.start(0, s);
-    launch_pair_pass1(pb, s);
+    launch_pair_pass1(pb, plan, s);
     kt.stop(at, s);
   }
   launch_flatten(pb.safe_par, n, s);
@@ -572,7 +574,7 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
   }
   if (!all_vp) {
     const int at = kt.start(1, s);
-    launch_pair_count(pb, s);
+    launch_pair_count(pb, plan, s);
     kt.stop(at, s);
   }
   else fill_u32(pb.cnt_f, 0, n, s);
@@ -594,7 +596,7 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
   pb.f_v = dev<uint32_t>(ar, nf);
   {
     const int at = kt.start(2, s);
-    launch_pair_write(pb, s);
+    launch_pair_write(pb, plan, s);
     kt.stop(at, s);
   }
   size_t na = na_direct;
@@ -627,13 +629,15 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
   uint32_t *e_list = dev<uint32_t>(ar, ne);
   uint32_t *row_ptr = dev<uint32_t>(ar, (size_t)ne + 1);
   uint32_t *col = dev<uint32_t>(ar, 2 * na);
-  {
-    const int at = kt.start(6, s);
-    build_csr(pb.a_i, pb.a_j, pb.a_t, na, is_e, eid, n, ne, e_list, row_ptr, col, ar, s);
-    kt.stop(at, s);
-  }
+  list_editable(is_e, eid, n, e_list, s);
   int64_t *d_eoff = dev<int64_t>(ar, J + 1);
   k_e_off<<<(J + 256) / 256, 256, 0, s>>>(eid, d_poff, J, n, ne_dev, d_eoff);
+  {
+    const int at = kt.start(6, s);
+    order_rows(e_list, ne, eid, pos, d_jobs, d_poff, J, ar, s);
+    build_csr(pb.a_i, pb.a_j, pb.a_t, na, eid, ne, row_ptr, col, ar, s);
+    kt.stop(at, s);
+  }
   std::vector<int64_t> e_off(J + 1);
   st.fetch(e_off.data(), d_eoff, J + 1);
   {
@@ -657,6 +661,14 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
   gb.jobs = d_jobs;
   gb.loop = dev<JobLoop>(ar, J);
   gb.e_off = d_eoff;
+  {
+    std::vector<int64_t> toff(J + 1, 0);
+    for (int q = 0; q < J; ++q) toff[q + 1] = toff[q] + (e_off[q + 1] - e_off[q] + 63) / 64;
+    int64_t *d_toff = dev<int64_t>(ar, J + 1);
+    PCC_HIP(hipMemcpyAsync(d_toff, toff.data(), (J + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    gb.tile_off = d_toff;
+    gb.ntiles = toff[J];
+  }
   gb.njobs = J;
   gb.ne = ne;
   gb.row_ptr = row_ptr;
@@ -774,8 +786,8 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
     eb.sym_off = d_so;
     eb.sym = dev<uint16_t>(ar, nsym);
     eb.hist = dev<uint32_t>(ar, (size_t)J * 65536);
-    PCC_HIP(hipMemsetAsync(eb.hist, 0, (size_t)J * 65536 * sizeof(uint32_t), s));
     launch_edit_codes(eb, d_fst, s);
+    symbol_histogram(eb.sym, nsym, d_so, J, eb.hist, ar, s);
     uint8_t *fbytes = dev<uint8_t>(ar, fb[J]);
     launch_flag_bytes(eb.flag8, d_poff, d_fb, J, fb[J], fbytes, s);
     // per-job canonical Huffman tables from the histograms
