@@ -58,6 +58,21 @@ def kernel_bytes(name, st, n):
     return None
 
 
+def recorded_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if the
+    kernel's source is unchanged since they were taken (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path)).get(kernel)
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError, TypeError, AttributeError):
+        return None
+    if hashlib.sha1(src).hexdigest() != rec["source_sha1"]:
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
 def verify(ctx, w, stream, labels):
     import numpy as np
     import torch
@@ -164,9 +179,10 @@ def main():
         nbytes = kernel_bytes(dom, stats[-1], w.n)
         if nbytes is not None and avg_s > 0:
             ach = nbytes / avg_s / 1e9
+            tb = recorded_traffic(dom)
             roofline = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1),
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                        "traffic": None, "bytes_per_launch": int(nbytes),
+                        "traffic": int(tb) if tb else None, "bytes_per_launch": int(nbytes),
                         "avg_launch_us": round(avg_s * 1e6, 2), "launches": int(klaunch[dom])}
         else:
             roofline = {"kernel": dom, "bound": "alu", "achieved": None, "peak": None,
