@@ -44,10 +44,13 @@ def workload(name):
     raise SystemExit("unknown workload " + name)
 
 
-# algorithmic bytes of one launch of each kernel
+# algorithmic bytes of all launches of a kernel in one step
 def kernel_bytes(name, st, n):
     if name == "pgd_step":
-        return 160 * st["n_editable"] + 8 * st["n_active"]
+        # per evaluated row: position read and write (24 + 24 B), original
+        # position (12 B), Adam moments read and written (96 B), row pointer
+        # (4 B); per evaluated incidence: its column entry (4 B)
+        return 160 * st["pgd_rows_evaluated"] + 4 * st["pgd_incidences_evaluated"]
     if name in ("pair_classify", "pair_count", "pair_write"):
         # sorted positions (16 B) and cell index (4 B) per particle, plus
         # the per-particle counts or the written pairs
@@ -176,7 +179,8 @@ def main():
     if kms and max(kms.values()) > 0:
         dom = max(kms, key=kms.get)
         avg_s = kms[dom] / 1e3 / max(1, klaunch[dom])
-        nbytes = kernel_bytes(dom, stats[-1], w.n)
+        per_step = [kernel_bytes(dom, st, w.n) for st in stats]
+        nbytes = None if None in per_step else sum(per_step) / max(1, klaunch[dom])
         if nbytes is not None and avg_s > 0:
             ach = nbytes / avg_s / 1e9
             tb = recorded_traffic(dom)
@@ -198,6 +202,8 @@ def main():
                    "parallelism": "single GPU"},
         "status": last["status"], "iters": last["iters"], "n_active": last["n_active"],
         "n_editable": last["n_editable"], "n_flagged": last["n_flagged"],
+        "pgd_rows_evaluated": last["pgd_rows_evaluated"],
+        "pgd_incidences_evaluated": last["pgd_incidences_evaluated"],
         "stream_bytes": last["bytes_stream"],
         "stage_ms": {k: round(v, 3) for k, v in last["t_stage_ms"].items()},
         "kernel_ms_per_step": {k: round(v / len(stats), 3) for k, v in kms.items()},

@@ -126,6 +126,10 @@ typedef struct {
   double t_stage_ms[PCC_NSTAGES];
   double kernel_ms[PCC_NKERNELS];
   int64_t kernel_launches[PCC_NKERNELS];
+  /* work of the PGD steps, summed over all steps: rows (editable particles)
+     and row incidences whose constraints were evaluated; a row is skipped
+     in a step when it is an exact fixed point of that step */
+  int64_t pgd_rows_evaluated, pgd_incidences_evaluated;
 } pcc_stats;
 
 typedef struct {

@@ -58,7 +58,8 @@ class Stats(C.Structure):
                 ("loss_final", C.c_double), ("viol0", C.c_int64), ("viol_final", C.c_int64),
                 ("bytes_flags", C.c_int64), ("bytes_codes", C.c_int64),
                 ("bytes_stream", C.c_int64), ("t_stage_ms", C.c_double * NSTAGES),
-                ("kernel_ms", C.c_double * NKERNELS), ("kernel_launches", C.c_int64 * NKERNELS)]
+                ("kernel_ms", C.c_double * NKERNELS), ("kernel_launches", C.c_int64 * NKERNELS),
+                ("pgd_rows_evaluated", C.c_int64), ("pgd_incidences_evaluated", C.c_int64)]
 
 
 class Job(C.Structure):

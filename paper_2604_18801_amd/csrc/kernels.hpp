@@ -50,7 +50,8 @@ struct PairBufs {
   const int32_t *nbr;
   uint32_t *safe_par, *fof_par;          // union-find parents (sorted space)
   uint32_t *cnt_a, *cnt_f;               // per particle counts
-  unsigned long long *job_counts;        // [njobs][4]: pairs, safe, pb, pc
+  unsigned long long *job_counts;        // [njobs][count_slots][16]: safe, pb, pc partial sums
+  int count_slots;                       // power of two
   const uint64_t *off_a, *off_f;         // write offsets
   uint32_t *a_i, *a_j;
   uint8_t *a_t;
@@ -89,10 +90,26 @@ struct PgdBufs {
   int njobs;
   size_t ne;
   const uint32_t *row_ptr, *col;
+  size_t ninc;            // incidences: twice the active pairs
   double4 *P0, *P1;
   double *m, *v;          // [3][ne]
   const float4 *xo;       // original position of each row
   int32_t *n_active;      // device: jobs not done
+  // Hot rows (the only rows evaluated after the first step), per job in
+  // wl[e_off[j] .. e_off[j] + wl_n[j]); a step processes the first
+  // wl_step[j] of them.  hot[e]: 0 cold, 1 hot, 2 hot with its partners
+  // marked hot.
+  uint32_t *hot;      // [ne]
+  uint32_t *wl;       // [ne]
+  uint32_t *wl_n;     // [njobs]
+  uint32_t *wl_step;  // [njobs]
+  uint64_t *inc_n;    // [njobs] incidences of the rows in wl[0 .. wl_n)
+  uint64_t *inc_step; // [njobs] incidences of the rows a step processes
+  // violation count and fixed-point loss of one evaluation: per job,
+  // acc_slots partial sums, each on its own 128-byte line (waves add into
+  // the slot of their index, so no address takes many atomics)
+  unsigned long long *acc;  // [njobs][acc_slots][16]
+  int acc_slots;            // power of two
 };
 void sort_pairs(uint32_t *a_i, uint32_t *a_j, uint8_t *a_t, size_t na, const float4 *pos,
                 int id_bits, Arena &ar, hipStream_t s);
@@ -109,6 +126,13 @@ void build_csr(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t, siz
                hipStream_t s);
 void launch_pgd_init(const uint32_t *e_list, size_t ne, const float4 *pos, const float4 *rec,
                      double4 *P0, float4 *xo, double *m, double *v, hipStream_t s);
+// worklist of the first step: every row; no row hot yet
+void launch_hot_init(const PgdBufs &b, hipStream_t s);
+// After the first step: renumbers each job's rows so that its hot rows come
+// first (both groups keep their order).  The row arrays, the CSR (partner
+// order within a row unchanged) and the row -> particle list are permuted
+// into new buffers, and the worklist becomes the hot rows.
+void renumber_hot(PgdBufs &b, uint32_t *&e_list, Arena &ar, hipStream_t s);
 void launch_loop_init(const JobDev *jobs, JobLoop *loop, int njobs, int32_t *n_active,
                       hipStream_t s);
 void launch_pgd_step(const PgdBufs &b, hipStream_t s);

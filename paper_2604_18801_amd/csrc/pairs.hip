@@ -29,34 +29,41 @@ __device__ inline void st_par(uint32_t *p, uint32_t i, uint32_t v) {
   __hip_atomic_store(p + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// find with path halving: every parent pointer only ever moves to an ancestor
+// Find with path halving.  Parent reads are plain loads: a value read from a
+// stale cache line is still an ancestor (parents only ever move to ancestors),
+// and a stale "root" is caught by the compare-and-swap of the union, whose
+// returned value lets the search go on from fresh data.
 __device__ inline uint32_t uf_find(uint32_t *par, uint32_t x) {
   for (;;) {
-    const uint32_t p = ld_par(par, x);
+    const uint32_t p = par[x];
     if (p == x) return x;
-    const uint32_t gp = ld_par(par, p);
+    const uint32_t gp = par[p];
     if (gp == p) return p;
     st_par(par, x, gp);
     x = gp;
   }
 }
 
-// hook the larger root under the smaller one with a compare-and-swap; retry
-// from the new roots when another thread got there first
-__device__ inline void uf_union(uint32_t *par, uint32_t a, uint32_t b) {
+// Hook the larger root under the smaller one with a compare-and-swap.  On
+// failure the swap returns the node's current parent, a strictly smaller
+// index, and the search continues from there; so every retry makes progress.
+// Returns the root the two sets now share (as far as this thread knows).
+__device__ inline uint32_t uf_union(uint32_t *par, uint32_t a, uint32_t b) {
+  a = uf_find(par, a);
+  b = uf_find(par, b);
   for (;;) {
-    a = uf_find(par, a);
-    b = uf_find(par, b);
-    if (a == b) return;
+    if (a == b) return a;
     if (a < b) {
       const uint32_t t = a;
       a = b;
       b = t;
     }
-    uint32_t expected = a;
-    if (__hip_atomic_compare_exchange_strong(par + a, &expected, b, __ATOMIC_RELAXED,
+    uint32_t seen = a;
+    if (__hip_atomic_compare_exchange_strong(par + a, &seen, b, __ATOMIC_RELAXED,
                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-      return;
+      return b;
+    a = uf_find(par, seen);
+    b = uf_find(par, b);
   }
 }
 
@@ -75,12 +82,19 @@ __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
   return v;
 }
 
+// Adds the counts of a wave's lanes to their jobs' counters.  Each job has
+// `slots` copies of its K counters, each copy on its own 128-byte line; a
+// wave adds into the copy of its index, so that no address takes more than
+// a few atomics (same-address device atomics serialise).
 template <int K>
-__device__ inline void job_add(unsigned long long *ctr, int job, bool valid,
+__device__ inline void job_add(unsigned long long *ctr, int slots, int job, bool valid,
                                const unsigned long long (&v)[K]) {
+  static_assert(K <= 16, "counters of one slot share a 128-byte line");
   const int jv = valid ? job : -1;
   uint64_t todo = __ballot(valid);
   const int lane = threadIdx.x & 63;
+  const int slot = (int)(((size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) &
+                         (size_t)(slots - 1));
   while (todo) {
     const int leader = __ffsll((long long)todo) - 1;
     const int lj = __shfl(jv, leader, kWave);
@@ -88,7 +102,7 @@ __device__ inline void job_add(unsigned long long *ctr, int job, bool valid,
 #pragma unroll
     for (int c = 0; c < K; ++c) {
       const unsigned long long s = wave_sum_u64(jv == lj ? v[c] : 0ull);
-      if (lane == leader && s) atomicAdd(ctr + (size_t)lj * K + c, s);
+      if (lane == leader && s) atomicAdd(ctr + ((size_t)lj * slots + slot) * 16 + c, s);
     }
     todo &= ~grp;
   }
@@ -150,7 +164,7 @@ __device__ inline double dist2_exact(const float4 &a, const float4 &b, const Job
 struct Home {
   uint32_t k;
   float4 pi, ri;
-  uint32_t sk, fk;     // safe and FoF roots (passes 2 and 3)
+  uint32_t sk, fk;     // safe and FoF roots (passes 2 and 3); root guesses (pass 1)
   uint64_t wa, wf;     // write cursors (pass 3)
   uint32_t ca, cf;     // counts (passes 1 and 2)
 };
@@ -160,7 +174,7 @@ __device__ inline void home_begin(const PairBufs &B, Home &h, uint32_t k) {
   h.k = k;
   h.pi = B.pos[k];
   h.ri = make_float4(0.f, 0.f, 0.f, 0.f);
-  h.sk = h.fk = 0;
+  h.sk = h.fk = k;
   if (PASS >= 2) {
     h.sk = B.safe_par[k];
     h.fk = B.fof_par[k];
@@ -194,14 +208,16 @@ __device__ inline void visit(const PairBufs &B, const JobPair &q, Home &h, uint3
   if (d2 > q.rv2) return;
   const int cls = d2 <= q.rs2 ? kSafe : (d2 <= q.b2 ? kPb : kPc);
   if (PASS == 1) {
+    // h.sk / h.fk hold an ancestor of k in each forest: a partner whose
+    // parent is that node is already in k's set and needs no union
     if (cls == kSafe) {
       cnt[0]++;
-      uf_union(B.safe_par, h.k, j);
-      uf_union(B.fof_par, h.k, j);
+      if (B.safe_par[j] != h.sk) h.sk = uf_union(B.safe_par, h.sk, j);
+      if (B.fof_par[j] != h.fk) h.fk = uf_union(B.fof_par, h.fk, j);
     } else if (cls == kPb) {
       cnt[1]++;
       h.ca++;
-      uf_union(B.fof_par, h.k, j);
+      if (B.fof_par[j] != h.fk) h.fk = uf_union(B.fof_par, h.fk, j);
     } else {
       cnt[2]++;
       h.ca++;
@@ -274,7 +290,7 @@ __global__ void __launch_bounds__(256) k_pairs_sparse(PairBufs B, const uint32_t
     }
     home_end<PASS>(B, h);
   }
-  if (PASS == 1) job_add<3>(B.job_counts, cjob, cjob >= 0, cnt);
+  if (PASS == 1) job_add<3>(B.job_counts, B.count_slots, cjob, cjob >= 0, cnt);
 }
 
 constexpr int kPairWaves = 4;
@@ -327,7 +343,7 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense(PairBufs B, con
     }
   }
   if (valid) home_end<PASS>(B, h);
-  if (PASS == 1) job_add<3>(B.job_counts, job, valid, cnt);
+  if (PASS == 1) job_add<3>(B.job_counts, B.count_slots, job, valid, cnt);
 }
 
 constexpr int kDenseCell = 32;

@@ -67,8 +67,8 @@ struct JobLoop {
   int32_t done;
   int32_t status;         // 0 converged, 1 cap reached
   double bc1, bc2;        // 1 - beta^t for the next step
-  unsigned long long viol_acc, loss_acc;   // accumulators of one evaluation
   unsigned long long viol0, loss0, viol_last, loss_last;
+  unsigned long long rows_eval, inc_eval;  // rows and incidences evaluated, all steps
   int32_t have0;
   int32_t pad;
 };

@@ -293,104 +293,145 @@ __device__ inline RowConst row_const(const JobDev &J) {
 }
 
 constexpr int kPgdWaves = 4;
-constexpr int kPgdBlocks = 2048;  // resident waves: 8192, about 8 per SIMD
+#ifndef PCC_PGD_BLOCKS
+#define PCC_PGD_BLOCKS 1024
+#endif
+constexpr int kPgdBlocks = PCC_PGD_BLOCKS;  // 4096 waves: one round of 4 per SIMD
 
-// flush of the per-job violation count and fixed-point loss of one wave
-__device__ inline void flush_counts(JobLoop *loop, int job, unsigned long long &viol,
+// flush of a wave's violation count (the same in every lane) and
+// fixed-point loss (per lane) for one job into the wave's slot
+__device__ inline void flush_counts(const PgdBufs &B, int job, unsigned long long &viol,
                                     unsigned long long &lossq) {
-  const unsigned long long sv = wsum(viol), sl = wsum(lossq);
-  if ((threadIdx.x & 63) == 0 && job >= 0) {
-    if (sv) atomicAdd(&loop[job].viol_acc, sv);
-    if (sl) atomicAdd(&loop[job].loss_acc, sl);
+  const unsigned long long sl = wsum(lossq);
+  if ((threadIdx.x & 63) == 0 && job >= 0 && (viol | sl)) {
+    const int slot = (int)((blockIdx.x * kPgdWaves + (threadIdx.x >> 6)) & (B.acc_slots - 1));
+    unsigned long long *a = B.acc + ((size_t)job * B.acc_slots + slot) * 16;
+    if (viol) atomicAdd(a, viol);
+    if (sl) atomicAdd(a + 1, sl);
   }
   viol = 0;
   lossq = 0;
 }
 
-// Each wave walks tiles of up to 64 consecutive rows of one job (tiles never
-// straddle two jobs, so the job and its constants are wave-uniform).  The
-// incidences of a tile (a contiguous range of the column array) are spread
-// over the 64 lanes, 64 at a time: each lane gathers one partner, evaluates
-// one constraint and leaves its gradient term in LDS; then each row's owner
-// lane adds the terms of its row in column order (increasing partner
-// index).  Finally every lane takes the Adam step and the projection of its
-// own row.  Violation counts stay in registers until the wave moves to
-// another job or finishes.
+__device__ inline uint64_t dbits(double x) { return (uint64_t)__double_as_longlong(x); }
+
+// Each wave walks tiles of up to 64 rows of one job's worklist (tiles never
+// straddle two jobs, so the job and its constants are wave-uniform).
+//
+// Hot rows.  A row whose constraints are all satisfied, whose Adam moments
+// are zero and whose position lies in the box is a fixed point of the step
+// bit for bit (zero gradient, zero moments, zero displacement, clamp of a
+// point already inside), and stays one while none of its partners moves.
+// The first step evaluates every row.  A row that is live in some step
+// (moved, had a violated constraint or nonzero moments) becomes hot, and so
+// do its partners, once; from then on hot rows are evaluated in every step.
+// A cold row has never been live and no partner of it has, so none of its
+// distances has changed since the first step: it is still a fixed point
+// with no violated pair.  Its position is the same in both buffers.  So the
+// iterates, the violation counts and the loss are exactly those of
+// evaluating every row in every step.
+//
+// The incidences of the tile's rows are concatenated and spread over the 64
+// lanes, 64 at a time: each lane gathers one partner, evaluates one
+// constraint and leaves its gradient term in LDS; then each row's owner
+// lane adds the terms of its row in column order (increasing partner index).
+// Finally every row takes the Adam step and the projection.  Counts stay in
+// registers until the wave moves to another job or finishes.
 #ifndef PCC_PGD_MIN_WAVES
-#define PCC_PGD_MIN_WAVES 1
+#define PCC_PGD_MIN_WAVES 4
 #endif
 __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(PgdBufs B) {
   __shared__ double4 s_self[kPgdWaves][64];
   __shared__ double s_term[kPgdWaves][3][64];
-  __shared__ uint32_t s_rp[kPgdWaves][65];
+  __shared__ uint32_t s_rp[kPgdWaves][64];  // first incidence of each row in the CSR
+  __shared__ uint32_t s_vb[kPgdWaves][64];  // first slot of each row in the tile's work list
+  __shared__ uint32_t s_e[kPgdWaves][64];   // row index
+  __shared__ uint8_t s_mk[kPgdWaves][64];   // the row marks its partners hot
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t nwaves = (int64_t)gridDim.x * kPgdWaves;
   unsigned long long viol = 0, lossq = 0;
-  int cjob = -1;  // job whose counts are held in viol / lossq
+  int cjob = -1;  // job whose counts are held in the registers above
   for (int64_t tile = (int64_t)blockIdx.x * kPgdWaves + w; tile < B.ntiles; tile += nwaves) {
     const int job = __builtin_amdgcn_readfirstlane(job_of(B.tile_off, B.njobs, tile));
     if (B.loop[job].done) continue;
+    const int64_t eoff = B.e_off[job];
+    const int64_t w0 = (tile - B.tile_off[job]) * 64;  // first worklist entry of the tile
+    const int64_t left = (int64_t)B.wl_step[job] - w0;
+    if (left <= 0) continue;
     if (job != cjob) {
-      flush_counts(B.loop, cjob, viol, lossq);
+      flush_counts(B, cjob, viol, lossq);
       cjob = job;
     }
-    const JobDev &J = B.jobs[job];
-    const int64_t e0 = B.e_off[job] + (tile - B.tile_off[job]) * 64;
-    const int64_t left = B.e_off[job + 1] - e0;
+    const int64_t t_step = B.loop[job].t;
     const int nrow = (int)(left < 64 ? left : 64);
     const bool valid = lane < nrow;
-    const size_t e = (size_t)e0 + lane;
-    const int cur = (int)(B.loop[job].t & 1);
+    const JobDev &J = B.jobs[job];
+    const int cur = (int)(t_step & 1);
     const double4 *__restrict__ Pc = cur ? B.P1 : B.P0;
     double4 *__restrict__ Pn = cur ? B.P0 : B.P1;
     const double L0 = J.L[0], L1 = J.L[1], L2 = J.L[2];
     const double h0 = J.hL[0], h1 = J.hL[1], h2 = J.hL[2];
     const double bm = J.bm, bp = J.bp, bm2 = J.bm2, bp2 = J.bp2, scale = J.loss_scale;
-    // the row's own state, loaded ahead of the gathers
+    // the row's position and incidence range; its Adam state is loaded
+    // after the gathers (fewer live registers, more waves in flight)
+    size_t e = 0;
+    uint32_t q0 = 0, len = 0;
     double4 pe = make_double4(0.0, 0.0, 0.0, 0.0);
-    float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-    double mo[3] = {0.0, 0.0, 0.0}, vo[3] = {0.0, 0.0, 0.0};
     if (valid) {
+      e = B.wl[eoff + w0 + lane];
+      q0 = B.row_ptr[e];
+      len = B.row_ptr[e + 1] - q0;
       pe = Pc[e];
-      x = B.xo[e];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        mo[k] = B.m[(size_t)k * B.ne + e];
-        vo[k] = B.v[(size_t)k * B.ne + e];
-      }
     }
+    uint32_t incl = len;  // inclusive prefix sum of len over the wave
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(incl, d, kWave);
+      if (lane >= d) incl += y;
+    }
+    const uint32_t vb = incl - len, total = __shfl(incl, 63, kWave);
     s_self[w][lane] = pe;
-    s_rp[w][lane] = valid ? B.row_ptr[e] : 0xffffffffu;
-    if (lane == 0) s_rp[w][64] = B.row_ptr[e0 + nrow];
+    s_rp[w][lane] = q0;
+    s_vb[w][lane] = vb;
+    s_e[w][lane] = (uint32_t)e;
     wave_sync();
-    const uint32_t qs = s_rp[w][0], qe = s_rp[w][64];
-    const uint32_t my_q0 = valid ? s_rp[w][lane] : qe;
-    const uint32_t my_q1 = valid ? (lane + 1 < nrow ? s_rp[w][lane + 1] : qe) : qe;
     double gx = 0.0, gy = 0.0, gz = 0.0;
-    for (uint32_t c0 = qs; c0 < qe; c0 += 64) {
+    bool hrow = false;  // some constraint of the row is violated
+    // owner row of slot q (last r with s_vb[r] <= q) and its column entry;
+    // each chunk loads the next chunk's entries before it waits for its own
+    // gathers
+    auto locate = [&](uint32_t q, int &r, uint32_t &col) {
+      int lo = 0, hi = nrow - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_vb[w][mid] <= q)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      r = lo;
+      col = B.col[s_rp[w][lo] + (q - s_vb[w][lo])];
+    };
+    int r_nx = 0;
+    uint32_t col_nx = 0;
+    if ((uint32_t)lane < total) locate(lane, r_nx, col_nx);
+    for (uint32_t c0 = 0; c0 < total; c0 += 64) {
       const uint32_t q = c0 + lane;
       double tx = 0.0, ty = 0.0, tz = 0.0;
-      if (q < qe) {
-        // owner row of incidence q: last r with s_rp[r] <= q
-        int lo = 0, hi = nrow - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (s_rp[w][mid] <= q)
-            lo = mid;
-          else
-            hi = mid - 1;
-        }
-        const int r = lo;
-        const uint32_t col = B.col[q];
+      bool hit = false, hit_once = false;
+      const int r = r_nx;
+      const uint32_t col = col_nx;
+      double4 po = make_double4(0.0, 0.0, 0.0, 0.0);
+      if (q < total) po = Pc[col & 0x7fffffffu];
+      if (q + 64 < total) locate(q + 64, r_nx, col_nx);
+      if (q < total) {
         const uint32_t o = col & 0x7fffffffu;
+        const uint32_t er = s_e[w][r];
         const double4 me = s_self[w][r];
-        const double4 po = Pc[o];
         const double dx = wrapd(me.x - po.x, L0, h0);
         const double dy = wrapd(me.y - po.y, L1, h1);
         const double dz = wrapd(me.z - po.z, L2, h2);
         const double d2 = (dx * dx + dy * dy) + dz * dz;
-        const size_t er = (size_t)e0 + r;
-        bool hit = false;
         double h = 0.0;
         if (!(col >> 31)) {
           // potentially broken: an original link pulled back inside b - delta_t
@@ -427,31 +468,48 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
           tz = -(2.0 * h * uz);
           hit = true;
         }
-        if (hit && o > er) {
-          viol++;
-          lossq += (unsigned long long)(h * h * scale);
-        }
+        if (hit && o > er) lossq += (unsigned long long)(h * h * scale);
+        hit_once = hit && o > er;
       }
       s_term[w][0][lane] = tx;
       s_term[w][1][lane] = ty;
       s_term[w][2][lane] = tz;
+      const uint64_t hb = __ballot(hit);
+      viol += (unsigned)__popcll(__ballot(hit_once));
       wave_sync();
       // the owner adds the terms of its row that fall in this chunk, in order
-      const uint32_t a = my_q0 > c0 ? my_q0 : c0;
-      const uint32_t b = my_q1 < c0 + 64 ? my_q1 : c0 + 64;
+      const uint32_t a = vb > c0 ? vb : c0;
+      const uint32_t b = vb + len < c0 + 64 ? vb + len : c0 + 64;
       for (uint32_t t = a; t < b; ++t) {
         gx += s_term[w][0][t - c0];
         gy += s_term[w][1][t - c0];
         gz += s_term[w][2][t - c0];
       }
+      if (b > a) {
+        const uint32_t wd = b - a;
+        const uint64_t mask = (wd >= 64 ? ~0ull : ((1ull << wd) - 1ull)) << (a - c0);
+        hrow |= (hb & mask) != 0;
+      }
       wave_sync();
     }
+    bool mark = false;
     if (valid) {
+      const uint32_t hotv = B.hot[e];
+      const float4 x = B.xo[e];
+      double mo[3], vo[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        mo[k] = B.m[(size_t)k * B.ne + e];
+        vo[k] = B.v[(size_t)k * B.ne + e];
+      }
       const double bc1 = B.loop[job].bc1, bc2 = B.loop[job].bc2;
       const double g[3] = {gx, gy, gz};
+      pe = s_self[w][lane];
       const double p[3] = {pe.x, pe.y, pe.z};
       const double xs[3] = {(double)x.x, (double)x.y, (double)x.z};
       double np[3];
+      uint64_t state = 0;
+      bool moved = false;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         double r;
@@ -463,28 +521,236 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
           const double v = J.beta2 * vo[k] + J.one_m_beta2 * g[k] * g[k];
           B.m[ia] = m;
           B.v[ia] = v;
+          state |= dbits(m) | dbits(v);
           const double mh = m / bc1;
           const double vh = v / bc2;
           r = p[k] - J.lr * mh / (sqrt(vh) + J.adam_eps);
         }
         np[k] = fmin(fmax(r, xs[k] - J.xi_p), xs[k] + J.xi_p);
+        moved |= dbits(np[k]) != dbits(p[k]);
+        // one coordinate at a time: interleaving the three divide and
+        // square-root sequences costs registers, hence occupancy
+        __builtin_amdgcn_sched_barrier(0);
       }
       Pn[e] = make_double4(np[0], np[1], np[2], 0.0);
+      // a live row that has not yet done so marks itself and its partners hot
+      mark = (moved || hrow || state != 0) && hotv != 2;
+      if (mark) B.hot[e] = 2;
+    }
+    if (__ballot(mark)) {
+      s_mk[w][lane] = mark ? 1 : 0;
+      wave_sync();
+      for (uint32_t c0 = 0; c0 < total; c0 += 64) {
+        const uint32_t q = c0 + lane;
+        bool app = false;
+        uint32_t o = 0;
+        if (q < total) {
+          int lo = 0, hi = nrow - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_vb[w][mid] <= q)
+              lo = mid;
+            else
+              hi = mid - 1;
+          }
+          if (s_mk[w][lo]) {
+            o = B.col[s_rp[w][lo] + (q - s_vb[w][lo])] & 0x7fffffffu;
+            uint32_t cold = 0u;
+            // the first marking of a cold row appends it to the worklist
+            // (after the first step, which lists every row and is followed
+            // by a compaction of the hot ones)
+            app = __hip_atomic_compare_exchange_strong(B.hot + o, &cold, 1u, __ATOMIC_RELAXED,
+                                                       __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT) &&
+                  t_step > 0;
+          }
+        }
+        const uint64_t am = __ballot(app);
+        if (am) {
+          const unsigned long long deg = app ? B.row_ptr[o + 1] - B.row_ptr[o] : 0u;
+          const unsigned long long sdeg = wsum(deg);
+          uint32_t base = 0;
+          if (lane == 0) {
+            base = atomicAdd(B.wl_n + job, (uint32_t)__popcll(am));
+            atomicAdd((unsigned long long *)B.inc_n + job, sdeg);
+          }
+          base = __shfl(base, 0, kWave);
+          if (app) B.wl[eoff + base + __popcll(am & ((1ull << lane) - 1ull))] = o;
+        }
+      }
     }
     wave_sync();  // LDS of this tile is reused by the next one
   }
-  flush_counts(B.loop, cjob, viol, lossq);
+  flush_counts(B, cjob, viol, lossq);
 }
 
-__global__ void k_pgd_finalize(PgdBufs B) {
+__global__ void k_hot_init(PgdBufs B, size_t n) {
+  const size_t nacc = (size_t)B.njobs * B.acc_slots * 16;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    if (i < B.ne) {
+      B.hot[i] = 0;
+      B.wl[i] = (uint32_t)i;
+    }
+    if (i < (size_t)B.njobs) {
+      B.wl_n[i] = 0;
+      B.wl_step[i] = (uint32_t)(B.e_off[i + 1] - B.e_off[i]);
+      B.inc_n[i] = 0;
+      B.inc_step[i] = B.ne ? (uint64_t)B.row_ptr[B.e_off[i + 1]] - B.row_ptr[B.e_off[i]] : 0;
+    }
+    if (i < nacc) B.acc[i] = 0;
+  }
+}
+
+void launch_hot_init(const PgdBufs &b, hipStream_t s) {
+  const size_t n = std::max(std::max(b.ne, (size_t)b.njobs), (size_t)b.njobs * b.acc_slots * 16);
+  if (n) k_hot_init<<<blocks_for(n, 256, 65536), 256, 0, s>>>(b, n);
+}
+
+__global__ void k_hot_flags(const uint32_t *hot, size_t ne, uint8_t *f) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ne;
+       i += (size_t)gridDim.x * blockDim.x)
+    f[i] = hot[i] != 0;
+}
+
+// new index of each row: the job's hot rows first, then its cold rows
+__global__ void k_new_ids(const uint8_t *f, const uint32_t *pos, const uint32_t *total, size_t ne,
+                          const int64_t *e_off, int njobs, uint32_t *new_id) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int j = job_of(e_off, njobs, (int64_t)e);
+    const int64_t s = e_off[j], t = e_off[j + 1];
+    const uint32_t hs = pos[s], ht = t < (int64_t)ne ? pos[t] : *total;
+    const uint32_t before = pos[e] - hs;  // hot rows of the job before e
+    new_id[e] = f[e] ? (uint32_t)s + before
+                     : (uint32_t)s + (ht - hs) + ((uint32_t)(e - s) - before);
+  }
+}
+
+struct RowPerm {
+  const uint32_t *new_id;
+  const double4 *P0, *P1;
+  const double *m, *v;
+  const float4 *xo;
+  const uint32_t *hot, *e_list, *row_ptr;
+  double4 *nP0, *nP1;
+  double *nm, *nv;
+  float4 *nxo;
+  uint32_t *nhot, *ne_list, *nlen, *wl;
+};
+
+__global__ void k_permute_rows(RowPerm R, size_t ne) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t r = R.new_id[e];
+    R.nP0[r] = R.P0[e];
+    R.nP1[r] = R.P1[e];
+    R.nxo[r] = R.xo[e];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      R.nm[(size_t)k * ne + r] = R.m[(size_t)k * ne + e];
+      R.nv[(size_t)k * ne + r] = R.v[(size_t)k * ne + e];
+    }
+    R.nhot[r] = R.hot[e];
+    R.ne_list[r] = R.e_list[e];
+    R.nlen[r] = R.row_ptr[e + 1] - R.row_ptr[e];
+    R.wl[e] = (uint32_t)e;
+  }
+}
+
+__global__ void k_permute_cols(const uint32_t *new_id, const uint32_t *row_ptr, const uint32_t *col,
+                               const uint32_t *nrow_ptr, size_t ne, uint32_t *ncol) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t a = row_ptr[e], b = row_ptr[e + 1], d = nrow_ptr[new_id[e]];
+    for (uint32_t q = a; q < b; ++q) {
+      const uint32_t c = col[q];
+      ncol[d + (q - a)] = new_id[c & 0x7fffffffu] | (c & 0x80000000u);
+    }
+  }
+}
+
+__global__ void k_hot_counts(const uint32_t *pos, const uint32_t *total, const uint32_t *nrow_ptr,
+                             const int64_t *e_off, int njobs, size_t ne, uint32_t *wl_n,
+                             uint32_t *wl_step, uint64_t *inc_n, uint64_t *inc_step) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= B.njobs) return;
+  if (j >= njobs) return;
+  const int64_t s = e_off[j], t = e_off[j + 1];
+  const uint32_t a = s < (int64_t)ne ? pos[s] : *total, b = t < (int64_t)ne ? pos[t] : *total;
+  wl_n[j] = b - a;
+  wl_step[j] = b - a;
+  // the hot rows are now e_off[j] .. e_off[j] + (b - a) - 1
+  const uint64_t inc = (uint64_t)nrow_ptr[s + (b - a)] - nrow_ptr[s];
+  inc_n[j] = inc;
+  inc_step[j] = inc;
+}
+
+void renumber_hot(PgdBufs &b, uint32_t *&e_list, Arena &ar, hipStream_t s) {
+  const size_t ne = b.ne;
+  if (!ne) return;
+  uint8_t *f = ar.get<uint8_t>(ne);
+  uint32_t *pos = ar.get<uint32_t>(ne), *total = ar.get<uint32_t>(1);
+  uint32_t *new_id = ar.get<uint32_t>(ne);
+  const int nb = blocks_for(ne, 256, 65536);
+  k_hot_flags<<<nb, 256, 0, s>>>(b.hot, ne, f);
+  scan_u8_u32(f, pos, ne, total, ar, s);
+  k_new_ids<<<nb, 256, 0, s>>>(f, pos, total, ne, b.e_off, b.njobs, new_id);
+  RowPerm R;
+  R.new_id = new_id;
+  R.P0 = b.P0;
+  R.P1 = b.P1;
+  R.m = b.m;
+  R.v = b.v;
+  R.xo = b.xo;
+  R.hot = b.hot;
+  R.e_list = e_list;
+  R.row_ptr = b.row_ptr;
+  R.nP0 = ar.get<double4>(ne);
+  R.nP1 = ar.get<double4>(ne);
+  R.nm = ar.get<double>(3 * ne);
+  R.nv = ar.get<double>(3 * ne);
+  R.nxo = ar.get<float4>(ne);
+  R.nhot = ar.get<uint32_t>(ne);
+  R.ne_list = ar.get<uint32_t>(ne);
+  R.nlen = ar.get<uint32_t>(ne);
+  R.wl = b.wl;
+  k_permute_rows<<<nb, 256, 0, s>>>(R, ne);
+  uint32_t *nrow_ptr = ar.get<uint32_t>(ne + 1);
+  scan_u32_u32(R.nlen, nrow_ptr, ne, nrow_ptr + ne, ar, s);
+  uint32_t *ncol = ar.get<uint32_t>(b.ninc ? b.ninc : 1);
+  k_permute_cols<<<nb, 256, 0, s>>>(new_id, b.row_ptr, b.col, nrow_ptr, ne, ncol);
+  k_hot_counts<<<(b.njobs + 255) / 256, 256, 0, s>>>(pos, total, nrow_ptr, b.e_off, b.njobs, ne,
+                                                      b.wl_n, b.wl_step, b.inc_n, b.inc_step);
+  b.P0 = R.nP0;
+  b.P1 = R.nP1;
+  b.m = R.nm;
+  b.v = R.nv;
+  b.xo = R.nxo;
+  b.hot = R.nhot;
+  b.row_ptr = nrow_ptr;
+  b.col = ncol;
+  e_list = R.ne_list;
+}
+
+// one wave per job: sums (and clears) the job's partial counts, then decides
+__global__ void k_pgd_finalize(PgdBufs B) {
+  const int j = blockIdx.x, lane = threadIdx.x;
   JobLoop &L = B.loop[j];
   if (L.done) return;
   const JobDev &J = B.jobs[j];
-  const unsigned long long viol = L.viol_acc, lq = L.loss_acc;
-  L.viol_acc = 0;
-  L.loss_acc = 0;
+  unsigned long long viol = 0, lq = 0;
+  unsigned long long *a = B.acc + (size_t)j * B.acc_slots * 16;
+  for (int k = lane; k < B.acc_slots; k += kWave) {
+    viol += a[16 * k];
+    lq += a[16 * k + 1];
+    a[16 * k] = 0;
+    a[16 * k + 1] = 0;
+  }
+  viol = wsum(viol);
+  lq = wsum(lq);
+  if (lane != 0) return;
+  L.rows_eval += B.wl_step[j];
+  L.inc_eval += B.inc_step[j];
   if (!L.have0) {
     L.viol0 = viol;
     L.loss0 = lq;
@@ -499,6 +765,12 @@ __global__ void k_pgd_finalize(PgdBufs B) {
     atomicSub(B.n_active, 1);
     return;
   }
+  // rows that became hot in this step join the next one (the worklist of
+  // the first step is replaced by the compaction that follows it)
+  if (L.t > 0) {
+    B.wl_step[j] = B.wl_n[j];
+    B.inc_step[j] = B.inc_n[j];
+  }
   L.t += 1;
   L.bc1 = J.bc_tab[L.t + 1].x;
   L.bc2 = J.bc_tab[L.t + 1].y;
@@ -509,7 +781,7 @@ void launch_pgd_step(const PgdBufs &b, hipStream_t s) {
     k_pgd_step<<<blocks_for(b.ne, 64 * kPgdWaves, kPgdBlocks), 64 * kPgdWaves, 0, s>>>(b);
 }
 void launch_pgd_finalize(const PgdBufs &b, hipStream_t s) {
-  k_pgd_finalize<<<(b.njobs + 255) / 256, 256, 0, s>>>(b);
+  if (b.njobs) k_pgd_finalize<<<b.njobs, kWave, 0, s>>>(b);
 }
 
 }  // namespace pcc

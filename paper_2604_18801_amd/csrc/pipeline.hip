@@ -524,10 +524,13 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
   pb.fof_par = dev<uint32_t>(ar, n);
   pb.cnt_a = dev<uint32_t>(ar, n);
   pb.cnt_f = dev<uint32_t>(ar, n);
-  pb.job_counts = dev<unsigned long long>(ar, 3 * (size_t)J);
+  pb.count_slots = 64;
+  while (pb.count_slots > 1 && (int64_t)pb.count_slots * J > 4096) pb.count_slots >>= 1;
+  const size_t n_jc = (size_t)J * pb.count_slots * 16;
+  pb.job_counts = dev<unsigned long long>(ar, n_jc);
   iota_u32(pb.safe_par, n, s);
   iota_u32(pb.fof_par, n, s);
-  PCC_HIP(hipMemsetAsync(pb.job_counts, 0, 3 * J * sizeof(unsigned long long), s));
+  PCC_HIP(hipMemsetAsync(pb.job_counts, 0, n_jc * sizeof(unsigned long long), s));
   {
     const int at = kt.start(0, s);
     launch_pair_pass1(pb, plan, s);
@@ -548,13 +551,16 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
         j.orig.memspace == PCC_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     PCC_HIP(hipMemcpyAsync(j.out.labels, lab + h->p_off, h->n * sizeof(int32_t), kind, s));
   }
-  std::vector<unsigned long long> jc(3 * (size_t)J);
+  std::vector<unsigned long long> jc(n_jc);
   st.fetch(jc.data(), pb.job_counts, jc.size());
   for (int q = 0; q < J; ++q) {
+    unsigned long long c[3] = {0, 0, 0};
+    for (int k = 0; k < pb.count_slots; ++k)
+      for (int a = 0; a < 3; ++a) c[a] += jc[((size_t)q * pb.count_slots + k) * 16 + a];
     pcc_stats &S = act[q]->st;
-    S.n_safe = (int64_t)jc[3 * q];
-    S.n_pb = (int64_t)jc[3 * q + 1];
-    S.n_pc = (int64_t)jc[3 * q + 2];
+    S.n_safe = (int64_t)c[0];
+    S.n_pb = (int64_t)c[1];
+    S.n_pc = (int64_t)c[2];
     S.n_pairs = S.n_safe + S.n_pb + S.n_pc;
   }
   PCC_HIP(hipEventRecord(C.ev[4], s));
@@ -673,6 +679,7 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
   gb.ne = ne;
   gb.row_ptr = row_ptr;
   gb.col = col;
+  gb.ninc = 2 * na;
   gb.P0 = dev<double4>(ar, ne);
   gb.P1 = dev<double4>(ar, ne);
   gb.m = dev<double>(ar, 3 * (size_t)ne);
@@ -680,13 +687,36 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
   float4 *xo = dev<float4>(ar, ne);
   gb.xo = xo;
   gb.n_active = dev<int32_t>(ar, 1);
+  gb.hot = dev<uint32_t>(ar, ne);
+  gb.wl = dev<uint32_t>(ar, ne);
+  gb.wl_n = dev<uint32_t>(ar, J);
+  gb.wl_step = dev<uint32_t>(ar, J);
+  gb.inc_n = dev<uint64_t>(ar, J);
+  gb.inc_step = dev<uint64_t>(ar, J);
+  gb.acc_slots = 64;
+  while (gb.acc_slots > 1 && (int64_t)gb.acc_slots * J > 4096) gb.acc_slots >>= 1;
+  gb.acc = dev<unsigned long long>(ar, (size_t)J * gb.acc_slots * 16);
   launch_pgd_init(e_list, ne, pos, rec, gb.P0, xo, gb.m, gb.v, s);
+  launch_hot_init(gb, s);
   launch_loop_init(d_jobs, gb.loop, J, gb.n_active, s);
+  {
+    // the first step evaluates every row; later ones only the hot rows
+    int at = kt.start(3, s);
+    launch_pgd_step(gb, s);
+    kt.stop(at, s);
+    at = kt.start(4, s);
+    launch_pgd_finalize(gb, s);
+    kt.stop(at, s);
+    renumber_hot(gb, e_list, ar, s);
+  }
   const int K = std::max(1, std::min(64, C.graph_iters));
   if (kt.on) {
     // one launch per kernel, each bracketed by events
     int32_t *h_act = (int32_t *)st.get(sizeof(int32_t));
     for (;;) {
+      PCC_HIP(hipMemcpyAsync(h_act, gb.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      PCC_HIP(hipStreamSynchronize(s));
+      if (*h_act <= 0) break;
       for (int k = 0; k < K; ++k) {
         int at = kt.start(3, s);
         launch_pgd_step(gb, s);
@@ -695,9 +725,6 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
         launch_pgd_finalize(gb, s);
         kt.stop(at, s);
       }
-      PCC_HIP(hipMemcpyAsync(h_act, gb.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      PCC_HIP(hipStreamSynchronize(s));
-      if (*h_act <= 0) break;
     }
   } else {
     hipGraph_t graph = nullptr;
@@ -716,10 +743,10 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
     int32_t *h_act = (int32_t *)st.get(sizeof(int32_t));
     try {
       for (;;) {
-        PCC_HIP(hipGraphLaunch(exec, s));
         PCC_HIP(hipMemcpyAsync(h_act, gb.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         PCC_HIP(hipStreamSynchronize(s));
         if (*h_act <= 0) break;
+        PCC_HIP(hipGraphLaunch(exec, s));
       }
     } catch (...) {
       hipGraphExecDestroy(exec);
@@ -739,6 +766,8 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
     S.viol_final = (int64_t)lp[q].viol_last;
     S.loss0 = (double)lp[q].loss0 / sc;
     S.loss_final = (double)lp[q].loss_last / sc;
+    S.pgd_rows_evaluated = (int64_t)lp[q].rows_eval;
+    S.pgd_incidences_evaluated = (int64_t)lp[q].inc_eval;
     act[q]->status = lp[q].status ? PCC_NOT_CONVERGED : PCC_OK;
   }
   PCC_HIP(hipEventRecord(C.ev[7], s));

@@ -218,3 +218,22 @@ def test_trajectory_is_bitwise_the_oracles(ctx, mode):
     _, _, st = _run(ctx, w, mode)
     assert st["iters"] == ref.iters
     np.testing.assert_array_equal(st["debug_xyz"], ref.p)
+
+
+@pytest.mark.parametrize("k", [1, 2, 7, 40, 0])
+def test_active_set_steps_are_exact(ctx, k):
+    # rows that are fixed points of a step are skipped; the iterates stay
+    # the oracle's to the last bit at every stopping point (k = 0: no cap)
+    w = synth.cosmology(32, seed=4, xi=0.05)
+    kw = {"max_iters": k} if k else {}
+    ref = oracle.correct(w.orig, w.recon, w.b, w.xi, mode="hf", box=w.box, **kw)
+    _, lab, st = _run(ctx, w, "hf", **kw)
+    np.testing.assert_array_equal(lab, ref.labels)
+    assert st["iters"] == ref.iters and st["status"] == ref.status
+    np.testing.assert_array_equal(st["debug_xyz"], ref.p)
+    ne, steps = st["n_editable"], st["iters"] + 1
+    # the first step evaluates every row; no step evaluates more
+    assert ne <= st["pgd_rows_evaluated"] <= steps * ne
+    assert 2 * st["n_active"] <= st["pgd_incidences_evaluated"] <= steps * 2 * st["n_active"]
+    if k == 0:
+        assert st["pgd_rows_evaluated"] < steps * ne
