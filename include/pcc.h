@@ -43,6 +43,7 @@ enum {
   PCC_OK = 0,
   PCC_NOT_CONVERGED = 1,      /* warning: T_max reached with violations left;
                                  the outputs are valid and inside the box */
+  PCC_PENDING = 2,            /* server: the job is queued or running */
   PCC_E_INVALID_ARG = -1,     /* b <= 0, xi < 0, NaN/Inf input, m not in
                                  {8,16,32}, n < 0, periodic side < 3 (b +
                                  2 sqrt(3) xi), n >= 2^31, NULL pointers */
@@ -143,6 +144,11 @@ typedef struct {
   pcc_status status;
   int32_t reserved;
   pcc_stats stats;
+  /* served jobs only (zero otherwise): milliseconds since the server was
+     created at which the job was submitted, its batch started and the job
+     finished; the number of jobs in its batch and the worker that ran it */
+  double t_submit_ms, t_start_ms, t_finish_ms;
+  int32_t batch_jobs, worker;
 } pcc_job_result;
 
 int pcc_version(void);
@@ -228,6 +234,45 @@ enum {
 };
 pcc_status pcc_debug_fetch(pcc_context *ctx, int32_t job, int32_t what, void *host_dst,
                            int64_t cap, int64_t *count);
+
+/*
+ * Served form: a job queue in front of the batched pass.  Worker threads
+ * (n_streams of them, each with its own HIP stream and workspace on the
+ * context's device) take the queued jobs in arrival order and run as many
+ * of them together as max_inflight and their share of hbm_budget allow
+ * (continuous batching: a batch starts as soon as a worker is free and takes
+ * whatever has arrived).  Each job's results equal those of pcc_correct on
+ * that job alone.  Job buffers are borrowed until the job has finished;
+ * device inputs must be ready (their producing stream synchronised) when
+ * the job is submitted.  The server's calls are thread-safe; the context is
+ * used only to pick the device and its options, and stays the caller's.
+ */
+typedef struct pcc_server pcc_server;
+typedef struct {
+  size_t hbm_budget;     /* device bytes the workers may use together; 0 = 80%
+                            of the free memory at creation */
+  int32_t max_inflight;  /* jobs per batch at most; 0 = 256 */
+  int32_t n_streams;     /* batches in flight at once (workers); 0 = 2 */
+} pcc_server_config;
+
+pcc_status pcc_server_create(pcc_context *ctx, const pcc_server_config *cfg,
+                             pcc_server **out);
+/* Queue a job; never blocks.  *ticket identifies it in the calls below. */
+pcc_status pcc_server_submit(pcc_server *srv, const pcc_job *job, uint64_t *ticket);
+/* PCC_PENDING while the job is queued or running, else the job's status
+   (and *result filled; result may be NULL). */
+pcc_status pcc_server_poll(pcc_server *srv, uint64_t ticket, pcc_job_result *result);
+/* Like poll, but blocks up to timeout_ms (negative: no limit). */
+pcc_status pcc_server_wait(pcc_server *srv, uint64_t ticket, int64_t timeout_ms,
+                           pcc_job_result *result);
+/* Remove a job that has not started: PCC_OK, and the job's status becomes
+   PCC_E_CANCELLED.  A job that has started runs to completion
+   (PCC_E_INVALID_ARG, as for an unknown ticket). */
+pcc_status pcc_server_cancel(pcc_server *srv, uint64_t ticket);
+/* Block until every submitted job has finished. */
+pcc_status pcc_server_drain(pcc_server *srv);
+/* Drain, stop the workers and free the server. */
+pcc_status pcc_server_destroy(pcc_server *srv);
 
 #ifdef __cplusplus
 }

@@ -4,5 +4,5 @@ The whole correction pass runs in the gfx950 library ``libpcc.so`` behind the
 C ABI of ``include/pcc.h``; this package is its ctypes binding.
 """
 from ._binding import (  # noqa: F401
-    Context, PccError, decode, lib, make_params, version, LIB_PATH, MODES, STAGE_NAMES,
+    Context, PccError, Server, decode, lib, make_params, version, LIB_PATH, MODES, STAGE_NAMES,
 )

@@ -67,7 +67,16 @@ class Job(C.Structure):
 
 
 class JobResult(C.Structure):
-    _fields_ = [("status", C.c_int32), ("reserved", C.c_int32), ("stats", Stats)]
+    _fields_ = [("status", C.c_int32), ("reserved", C.c_int32), ("stats", Stats),
+                ("t_submit_ms", C.c_double), ("t_start_ms", C.c_double),
+                ("t_finish_ms", C.c_double), ("batch_jobs", C.c_int32), ("worker", C.c_int32)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("max_inflight", C.c_int32), ("n_streams", C.c_int32)]
+
+
+PENDING = 2
 
 
 _lib = None
@@ -102,9 +111,19 @@ def lib() -> C.CDLL:
         L.pcc_context_set.argtypes = [C.c_void_p, C.c_int32, C.c_int64]
         L.pcc_debug_fetch.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int64,
                                       C.POINTER(C.c_int64)]
+        L.pcc_server_create.argtypes = [C.c_void_p, C.POINTER(ServerConfig),
+                                        C.POINTER(C.c_void_p)]
+        L.pcc_server_submit.argtypes = [C.c_void_p, C.POINTER(Job), C.POINTER(C.c_uint64)]
+        L.pcc_server_poll.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(JobResult)]
+        L.pcc_server_wait.argtypes = [C.c_void_p, C.c_uint64, C.c_int64, C.POINTER(JobResult)]
+        L.pcc_server_cancel.argtypes = [C.c_void_p, C.c_uint64]
+        L.pcc_server_drain.argtypes = [C.c_void_p]
+        L.pcc_server_destroy.argtypes = [C.c_void_p]
         for name in ("pcc_context_create", "pcc_context_destroy", "pcc_correct",
                      "pcc_correct_batch", "pcc_decode", "pcc_fof_labels", "pcc_debug_fetch",
-                     "pcc_context_set"):
+                     "pcc_context_set", "pcc_server_create", "pcc_server_submit",
+                     "pcc_server_poll", "pcc_server_wait", "pcc_server_cancel",
+                     "pcc_server_drain", "pcc_server_destroy"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -169,6 +188,45 @@ def _stream_handle(on_device: bool):
         return None
     import torch
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class _JobBuffers:
+    """A pcc_job built from a job dict (orig, recon, b, xi; optional mode,
+    box, opts, debug_xyz) together with the Python objects that own its
+    buffers, which must live until the job has finished."""
+
+    def __init__(self, jd: Dict):
+        po, ko = _view(jd["orig"])
+        pr, kr = _view(jd["recon"])
+        self.on_device = po.memspace == MEM_DEVICE
+        params = make_params(jd["b"], jd["xi"], mode=jd.get("mode", "hf"), box=jd.get("box"),
+                             **dict(jd.get("opts", {})))
+        cap = lib().pcc_stream_bound(po.n, C.byref(params))
+        self.sbuf = np.zeros(max(cap, 1), dtype=np.uint8)
+        self.slen = C.c_size_t(0)
+        if self.on_device:
+            import torch
+            self.lab = torch.empty(max(po.n, 1), dtype=torch.int32, device=ko.device)
+            lptr = self.lab.data_ptr()
+        else:
+            self.lab = np.zeros(max(po.n, 1), dtype=np.int32)
+            lptr = self.lab.ctypes.data
+        self.dbg = np.zeros((3, max(po.n, 1)), dtype=np.float64) if jd.get("debug_xyz") else None
+        self.n = po.n
+        self.keep = (ko, kr)
+        self.job = Job()
+        self.job.orig, self.job.recon, self.job.params = po, pr, params
+        self.job.out = Outputs(lptr, self.sbuf.ctypes.data, cap, C.pointer(self.slen),
+                               self.dbg.ctypes.data if self.dbg is not None else None)
+
+    def result(self, r: "JobResult"):
+        st = stats_dict(r.stats)
+        st["status"] = r.status
+        for k in ("t_submit_ms", "t_start_ms", "t_finish_ms", "batch_jobs", "worker"):
+            st[k] = getattr(r, k)
+        if self.dbg is not None:
+            st["debug_xyz"] = self.dbg[:, : self.n]
+        return r.status, bytes(self.sbuf[: self.slen.value]), self.lab[: self.n], st
 
 
 class Context:
@@ -236,41 +294,16 @@ class Context:
         """jobs: dicts with orig, recon, b, xi and optional mode, box, opts.
         Returns a list of (status, stream bytes, labels, stats)."""
         cj = (Job * len(jobs))()
-        keep, bufs = [], []
+        held = []
         on_dev = False
         for k, jd in enumerate(jobs):
-            po, ko = _view(jd["orig"])
-            pr, kr = _view(jd["recon"])
-            on_dev |= po.memspace == MEM_DEVICE
-            opts = dict(jd.get("opts", {}))
-            params = make_params(jd["b"], jd["xi"], mode=jd.get("mode", "hf"), box=jd.get("box"),
-                                 **opts)
-            cap = lib().pcc_stream_bound(po.n, C.byref(params))
-            sbuf = np.zeros(max(cap, 1), dtype=np.uint8)
-            slen = C.c_size_t(0)
-            if po.memspace == MEM_DEVICE:
-                import torch
-                lab = torch.empty(max(po.n, 1), dtype=torch.int32, device=ko.device)
-                lptr = lab.data_ptr()
-            else:
-                lab = np.zeros(max(po.n, 1), dtype=np.int32)
-                lptr = lab.ctypes.data
-            dbg = np.zeros((3, max(po.n, 1)), dtype=np.float64) if jd.get("debug_xyz") else None
-            cj[k].orig, cj[k].recon, cj[k].params = po, pr, params
-            cj[k].out = Outputs(lptr, sbuf.ctypes.data, cap, C.pointer(slen),
-                                dbg.ctypes.data if dbg is not None else None)
-            keep.append((ko, kr))
-            bufs.append((sbuf, slen, lab, dbg, po.n))
+            h = _JobBuffers(jd)
+            cj[k] = h.job
+            on_dev |= h.on_device
+            held.append(h)
         res = (JobResult * len(jobs))()
         lib().pcc_correct_batch(self._h, cj, len(jobs), res, _stream_handle(on_dev))
-        out = []
-        for k, (sbuf, slen, lab, dbg, n) in enumerate(bufs):
-            st = stats_dict(res[k].stats)
-            st["status"] = res[k].status
-            if dbg is not None:
-                st["debug_xyz"] = dbg[:, :n]
-            out.append((res[k].status, bytes(sbuf[: slen.value]), lab[:n], st))
-        return out
+        return [h.result(res[k]) for k, h in enumerate(held)]
 
     def fof_labels(self, pts, b: float, box=None):
         p, keep = _view(pts)
@@ -297,6 +330,72 @@ class Context:
         _check(lib().pcc_debug_fetch(self._h, int(job), code, buf.ctypes.data, cnt.value,
                                      C.byref(cnt)))
         return buf[: cnt.value]
+
+
+class Server:
+    """Served form: a queue of jobs run in batches by worker threads on the
+    context's GPU.  submit() returns a ticket; poll() / wait() return None
+    while the job is pending, else (status, stream bytes, labels, stats) with
+    the submit / start / finish times (ms since the server started) in
+    stats.  Device inputs are synchronised on the current stream at submit."""
+
+    def __init__(self, ctx: Context, hbm_budget: int = 0, max_inflight: int = 0,
+                 n_streams: int = 0):
+        cfg = ServerConfig(int(hbm_budget), int(max_inflight), int(n_streams))
+        h = C.c_void_p()
+        _check(lib().pcc_server_create(ctx._h, C.byref(cfg), C.byref(h)))
+        self._h = h
+        self._ctx = ctx
+        self._held: Dict[int, _JobBuffers] = {}
+
+    def submit(self, **jd) -> int:
+        hb = _JobBuffers(jd)
+        if hb.on_device:
+            import torch
+            torch.cuda.current_stream().synchronize()
+        tk = C.c_uint64(0)
+        _check(lib().pcc_server_submit(self._h, C.byref(hb.job), C.byref(tk)))
+        self._held[tk.value] = hb
+        return tk.value
+
+    def _finish(self, ticket: int, status: int, r: "JobResult"):
+        if status == PENDING:
+            return None
+        hb = self._held.pop(ticket)
+        return hb.result(r)
+
+    def poll(self, ticket: int):
+        r = JobResult()
+        status = lib().pcc_server_poll(self._h, C.c_uint64(ticket), C.byref(r))
+        if status == -1 and ticket not in self._held:
+            _check(status)
+        return self._finish(ticket, status, r)
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        r = JobResult()
+        status = lib().pcc_server_wait(self._h, C.c_uint64(ticket), int(timeout_ms), C.byref(r))
+        if status == -1 and ticket not in self._held:
+            _check(status)
+        return self._finish(ticket, status, r)
+
+    def cancel(self, ticket: int) -> bool:
+        """True if the job was removed before it started."""
+        return lib().pcc_server_cancel(self._h, C.c_uint64(ticket)) == 0
+
+    def drain(self):
+        _check(lib().pcc_server_drain(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pcc_server_destroy(self._h)
+            self._h = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def decode(stream: bytes, recon: np.ndarray) -> np.ndarray:

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build", "pcc")
 LIB = os.path.join(HERE, "libpcc.so")
 SOURCES = ["prims.hip", "cells.hip", "pairs.hip", "pgd.hip", "encode.hip", "pipeline.hip",
-           "codec.cpp", "capi.cpp"]
+           "codec.cpp", "capi.cpp", "server.cpp"]
 ARCH = os.environ.get("PCC_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -49,7 +49,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(workers) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-ldl"]
+    cmd = [_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-ldl", "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))

@@ -6,10 +6,6 @@
 
 #include "host.hpp"
 
-struct pcc_context {
-  pcc::Context c;
-};
-
 namespace {
 thread_local std::string g_err;
 
@@ -45,6 +41,7 @@ const char *pcc_status_string(pcc_status s) {
   switch (s) {
     case PCC_OK: return "ok";
     case PCC_NOT_CONVERGED: return "not converged (iteration cap reached)";
+    case PCC_PENDING: return "pending";
     case PCC_E_INVALID_ARG: return "invalid argument";
     case PCC_E_OUT_OF_MEMORY: return "out of memory";
     case PCC_E_DEVICE: return "device error";
@@ -57,6 +54,14 @@ const char *pcc_status_string(pcc_status s) {
 }
 
 const char *pcc_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+namespace pcc {
+void set_last_error(const std::string &m) { g_err = m; }
+}  // namespace pcc
+
+extern "C" {
 
 pcc_status pcc_context_set(pcc_context *ctx, int32_t key, int64_t value) {
   if (!ctx) return fail(PCC_E_INVALID_ARG, "NULL context");

@@ -63,6 +63,9 @@ struct Context {
 
 const double2 *bc_table(Context &C, double beta1, double beta2, int64_t len);
 
+// message returned by pcc_last_error on the calling thread
+void set_last_error(const std::string &m);
+
 pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs, pcc_job_result *res,
                      hipStream_t s, bool labels_only);
 
@@ -88,3 +91,8 @@ pcc_status decode_stream(const uint8_t *stream, size_t len, int64_t n, const flo
                          std::string &err);
 
 }  // namespace pcc
+
+// the opaque handle of the C ABI
+struct pcc_context {
+  pcc::Context c;
+};

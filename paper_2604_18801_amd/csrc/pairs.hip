@@ -346,7 +346,10 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense(PairBufs B, con
   if (PASS == 1) job_add<3>(B.job_counts, B.count_slots, job, valid, cnt);
 }
 
-constexpr int kDenseCell = 32;
+#ifndef PCC_DENSE_CELL
+#define PCC_DENSE_CELL 32
+#endif
+constexpr int kDenseCell = PCC_DENSE_CELL;  // cells with at least this many particles go dense
 
 // particles of sparse cells, and (cell, 64-chunk) units of dense cells
 __global__ void k_sparse_flags(const uint32_t *cell_of, const uint32_t *cell_start, size_t n,

@@ -124,6 +124,9 @@ void scan_u8_u32(const uint8_t *in, uint32_t *out, size_t n, uint32_t *total,
                  Arena &ar, hipStream_t s);
 void scan_u32_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *total,
                   Arena &ar, hipStream_t s);
+// exclusive scans; `out` may be `in`
+void scan_u64_u64(const uint64_t *in, uint64_t *out, size_t n, uint64_t *total,
+                  Arena &ar, hipStream_t s);
 // stable LSD radix sort of (key, value) on the low `bits` bits of the keys;
 // results land in keys/vals (tmp buffers from the arena).
 void radix_sort_u32(uint32_t *keys, uint32_t *vals, size_t n, int bits, Arena &ar,

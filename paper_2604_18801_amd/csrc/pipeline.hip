@@ -2,6 +2,8 @@
 // short sequence of launches) over all jobs of the call.
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -605,6 +607,9 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
     launch_pair_write(pb, plan, s);
     kt.stop(at, s);
   }
+  if (getenv("PCC_VERBOSE"))
+    fprintf(stderr, "[pcc] sparse homes %zu, dense units %zu, active (direct) %zu, "
+            "forest candidates %zu\n", plan.n_sparse, plan.n_units, na_direct, nf);
   size_t na = na_direct;
   if (nf) {
     uint32_t *bpar = dev<uint32_t>(ar, n);

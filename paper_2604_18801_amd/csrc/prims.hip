@@ -199,6 +199,10 @@ void scan_u32_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *total, 
                   hipStream_t s) {
   scan_impl<uint32_t, uint32_t>(in, out, n, total, ar, s);
 }
+void scan_u64_u64(const uint64_t *in, uint64_t *out, size_t n, uint64_t *total, Arena &ar,
+                  hipStream_t s) {
+  scan_impl<uint64_t, uint64_t>(in, out, n, total, ar, s);
+}
 
 // ---------------------------------------------------------------------------
 // stable LSD radix sort, 8-bit digits
