@@ -99,6 +99,185 @@ def cpu_baseline(w, side, mode):
                       "mode %s, %d iterations, %.2f s single-threaded" % (sub.n, side, mode, r.iters, dt)}
 
 
+def _percentile(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
+
+
+def _verify_many(ctx, ws, results):
+    """Membership errors and box violations summed over jobs (decoded stream,
+    FoF of the decoded positions on the GPU against the labels)."""
+    memb = boxv = 0
+    for w, (status, stream, lab, st) in zip(ws, results):
+        if status < 0 or w.n == 0:
+            continue
+        m, bv = verify(ctx, w, stream, lab)
+        memb += m
+        boxv += bv
+    return memb, boxv
+
+
+def bench_md_batch(args):
+    """Batched MD (the first K blocks of the 256-block batch): one
+    pcc_correct_batch call over all blocks is a step."""
+    import torch
+    import paper_2604_18801_amd as pcc
+    import synth
+    sizes = synth.md_batch_sizes()[: args.blocks]
+    t = time.perf_counter()
+    ws = [synth.md_block(int(n), 3_000_000 + k) for k, n in enumerate(sizes)]
+    total = int(sum(w.n for w in ws))
+    log("generated %d MD blocks, %d atoms in %.1f s" % (len(ws), total, time.perf_counter() - t))
+    ctx = pcc.Context(0)
+    kw = {"max_iters": args.max_iters} if args.max_iters else {}
+    jobs = [dict(orig=torch.from_numpy(w.orig).cuda(), recon=torch.from_numpy(w.recon).cuda(),
+                 b=w.b, xi=w.xi, mode=args.mode, box=w.box, opts=kw) for w in ws]
+    torch.cuda.synchronize()
+    for k in range(args.warmup):
+        ctx.correct_batch(jobs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        res = ctx.correct_batch(jobs)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    statuses = [r[0] for r in res]
+    out = {
+        "metric": METRIC, "value": round(total * args.steps / elapsed, 1), "unit": "particles/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded generator; no dataset)",
+        "config": {"workload": "batched MD: blocks 0..%d of the 256-block batch (sizes "
+                               "10^U(4, log10 2e6)), droplets on FCC in vapour, b=1.5, "
+                               "xi=0.05, non-periodic" % (len(ws) - 1),
+                   "blocks": len(ws), "atoms": total, "mode": args.mode,
+                   "parallelism": "single GPU, one batched call"},
+        "iters_max": int(max(r[3]["iters"] for r in res)),
+        "not_converged": int(sum(1 for s in statuses if s == 1)),
+        "failed": int(sum(1 for s in statuses if s < 0)),
+        "roofline": None, "cpu_baseline": None,
+    }
+    if not args.no_verify:
+        out["membership_errors"], out["box_violations"] = _verify_many(ctx, ws, res)
+        if out["membership_errors"] or out["box_violations"] or out["failed"]:
+            out["value_valid"] = False
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_served(args):
+    """Served stream: the first J jobs of the 2000-job mix, device-resident.
+    A closed-loop pass (all jobs submitted at once) gives the sustained job
+    rate mu; the timed pass submits the same jobs at Poisson arrivals of
+    rate args.rate * mu.  Latency = finish - arrival per job."""
+    import numpy as np
+    import torch
+    import paper_2604_18801_amd as pcc
+    import synth
+    specs = synth.served_jobs(2000)[: args.jobs]
+    t = time.perf_counter()
+    ws = [synth.make_job(s) for s in specs]
+    total = int(sum(w.n for w in ws))
+    log("generated %d served jobs, %d particles in %.1f s" % (len(ws), total,
+                                                              time.perf_counter() - t))
+    ctx = pcc.Context(0)
+    # Adam's step alpha in units of b: the paper's alpha = 1e-3 at b = 0.2 of
+    # the mean spacing, i.e. alpha = 0.005 b (MD lengths are in sigma)
+    if args.served_modes == "hf":
+        for w in ws:
+            w.mode = 2
+    modes = [int(w.mode) for w in ws]
+    jobs = []
+    for w in ws:
+        kw = {"lr": 0.005 * w.b}
+        if args.max_iters:
+            kw["max_iters"] = args.max_iters
+        jobs.append(dict(orig=torch.from_numpy(w.orig).cuda(), recon=torch.from_numpy(w.recon).cuda(),
+                         b=w.b, xi=w.xi, mode=int(w.mode), box=w.box, opts=kw))
+    torch.cuda.synchronize()
+    srv = pcc.Server(ctx)
+
+    def run(arrivals):
+        t_start = time.perf_counter()
+        tickets, done = [], {}
+        last = t_start
+
+        def collect():
+            for k, tk in enumerate(tickets):
+                if k not in done:
+                    r = srv.poll(tk)
+                    if r is not None:
+                        done[k] = r
+
+        for k, jd in enumerate(jobs):
+            if arrivals is not None:
+                dt = arrivals[k] - (time.perf_counter() - t_start)
+                if dt > 0:
+                    time.sleep(dt)
+            tickets.append(srv.submit(**jd))
+        while len(done) < len(tickets):
+            time.sleep(0.05)
+            collect()
+            if time.perf_counter() - last > 10.0:
+                last = time.perf_counter()
+                log("  %d of %d jobs finished after %.1f s" % (len(done), len(tickets),
+                                                                last - t_start))
+        return [done[k] for k in range(len(tickets))]
+
+    t = time.perf_counter()
+    res = run(None)
+    closed = time.perf_counter() - t
+    mu = len(jobs) / closed
+    log("closed loop: %d jobs in %.2f s (%.1f jobs/s)" % (len(jobs), closed, mu))
+    lam = args.rate * mu
+    rng = np.random.default_rng(4_000_001)
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, len(jobs)))
+    t = time.perf_counter()
+    res = run(arrivals)
+    elapsed = time.perf_counter() - t
+    lat = [r[3]["t_finish_ms"] - r[3]["t_submit_ms"] for r in res]
+    statuses = [r[0] for r in res]
+    out = {
+        "metric": METRIC, "value": round(total / elapsed, 1), "unit": "particles/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": round(1e3 * elapsed, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded generator; no dataset)",
+        "config": {"workload": "served stream: jobs 0..%d of the 2000-job mix (cosmology-like, "
+                               "MD, SPH-like; sizes LogNormal(ln 2e5, 1) clipped to [1e4, 1e7]; "
+                               "xi = b U(0.1, 0.5); modes VP/SC/HF)" % (len(jobs) - 1),
+                   "jobs": len(jobs), "particles": total, "arrival_rate_frac": args.rate,
+                   "modes": args.served_modes, "adam_lr": "0.005 b",
+                   "max_iters": args.max_iters or 100000,
+                   "parallelism": "single GPU, server with 2 workers"},
+        "latency_ms": {"p50": round(_percentile(lat, 50), 2), "p99": round(_percentile(lat, 99), 2),
+                       "max": round(max(lat), 2)},
+        "closed_loop_jobs_per_s": round(mu, 3), "arrival_jobs_per_s": round(lam, 3),
+        "mean_batch_jobs": round(float(np.mean([r[3]["batch_jobs"] for r in res])), 2),
+        "iters_by_mode": {m: int(max([r[3]["iters"] for r, md in zip(res, modes) if md == k]
+                                     or [0])) for k, m in enumerate(("vp", "sc", "hf"))},
+        "not_converged": int(sum(1 for s in statuses if s == 1)),
+        "failed": int(sum(1 for s in statuses if s < 0)),
+        "roofline": None, "cpu_baseline": None,
+    }
+    srv.close()
+    if args.detail:
+        with open(args.detail, "w") as f:
+            for s, w, r in zip(specs, ws, res):
+                f.write(json.dumps({"kind": s["kind"], "n": w.n, "xi_over_b": round(s["xi_over_b"], 3),
+                                    "mode": int(w.mode), "status": r[0], "iters": r[3]["iters"],
+                                    "viol0": r[3]["viol0"], "viol_final": r[3]["viol_final"],
+                                    "n_active": r[3]["n_active"],
+                                    "latency_ms": round(r[3]["t_finish_ms"] - r[3]["t_submit_ms"], 2)})
+                        + "\n")
+    if not args.no_verify:
+        out["membership_errors"], out["box_violations"] = _verify_many(ctx, ws, res)
+        if out["membership_errors"] or out["box_violations"] or out["failed"]:
+            out["value_valid"] = False
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +292,16 @@ def main():
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
+    ap.add_argument("--blocks", type=int, default=32,
+                    help="md_batch: blocks 0..K-1 of the 256-block batch")
+    ap.add_argument("--jobs", type=int, default=120, help="served: first J jobs of the stream")
+    ap.add_argument("--rate", type=float, default=0.7,
+                    help="served: arrival rate as a fraction of the closed-loop job rate")
+    ap.add_argument("--max-iters", type=int, default=0,
+                    help="iteration cap (0: the library's safety cap)")
+    ap.add_argument("--detail", default="", help="served: write one JSON row per job here")
+    ap.add_argument("--served-modes", default="hf", choices=("hf", "spec"),
+                    help="served: every job in HF mode, or the stream's own VP/SC/HF draw")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the correction pass is built and measured on a "
@@ -123,6 +312,11 @@ def main():
     import numpy as np
     import torch
     import paper_2604_18801_amd as pcc
+
+    if args.workload == "md_batch":
+        return bench_md_batch(args)
+    if args.workload == "served":
+        return bench_served(args)
 
     t = time.perf_counter()
     w, desc = workload(args.workload)

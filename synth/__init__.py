@@ -14,5 +14,6 @@ from .generators import (  # noqa: F401
     sph_voids,
     md_batch_sizes,
     served_jobs,
+    make_job,
     sub_box,
 )

@@ -186,6 +186,33 @@ def cosmology(n_side: int = 256, seed: int = 1, xi: float = 0.05, b: float = 0.2
 # --------------------------------------------------------------------------
 # molecular-dynamics-like workload
 # --------------------------------------------------------------------------
+def _within_any(p: np.ndarray, c: np.ndarray, r: np.ndarray, k: int = 8) -> np.ndarray:
+    """For each point of p, whether |p - c_i| < r_i for some sphere i.  The
+    distance is the same numpy expression for every (point, sphere) pair
+    examined; a k-d tree only limits which pairs are examined (points with k
+    or more spheres in reach are checked against all of them)."""
+    out = np.zeros(p.shape[0], dtype=bool)
+    if c.shape[0] == 0 or p.shape[0] == 0:
+        return out
+    from scipy.spatial import cKDTree
+    kk = min(k, c.shape[0])
+    _, idx = cKDTree(c).query(p, k=kk, distance_upper_bound=float(r.max()) * (1 + 1e-9) + 1e-9)
+    idx = idx.reshape(p.shape[0], kk)
+    valid = idx < c.shape[0]
+    safe = np.where(valid, idx, 0)
+    d = np.linalg.norm(p[:, None, :] - c[safe], axis=2)
+    out = (valid & (d < r[safe])).any(axis=1)
+    full = valid[:, -1]  # k spheres in reach: there may be more
+    if full.any():
+        q = p[full]
+        hit = np.zeros(q.shape[0], dtype=bool)
+        for s in range(0, c.shape[0], 64):
+            dd = np.linalg.norm(q[:, None, :] - c[None, s:s + 64, :], axis=2)
+            hit |= (dd < r[None, s:s + 64]).any(axis=1)
+        out[full] = hit
+    return out
+
+
 def _random_rotation(rng):
     q, r = np.linalg.qr(rng.normal(size=(3, 3)))
     q *= np.sign(np.diag(r))
@@ -249,10 +276,7 @@ def md_block(n: int, seed: int, b: float = 1.5, xi: float = 0.05,
     while got < n_vap:
         m = max(1024, int(1.3 * (n_vap - got)))
         p = rng.random((m, 3)) * L
-        keep = np.ones(m, dtype=bool)
-        for s in range(0, dc.shape[0], 64):
-            d = np.linalg.norm(p[:, None, :] - dc[None, s:s + 64, :], axis=2)
-            keep &= ~(d < (dr[None, s:s + 64] + 1.0)).any(axis=1)
+        keep = ~_within_any(p, dc, dr + 1.0)
         p = p[keep][: n_vap - got]
         vap.append(p)
         got += p.shape[0]
@@ -283,10 +307,7 @@ def sph_voids(n: int, seed: int, b: float = 0.2, xi: float = 0.05,
     while got < n:
         m = max(1024, int(1.2 * (n - got)))
         p = rng.random((m, 3)) * L
-        inv = np.zeros(m, dtype=bool)
-        for s in range(0, nv, 64):
-            d = np.linalg.norm(p[:, None, :] - vc[None, s:s + 64, :], axis=2)
-            inv |= (d < void_r).any(axis=1)
+        inv = _within_any(p, vc, np.full(nv, float(void_r)))
         keep = ~inv | (rng.random(m) < inside)
         p = p[keep][: n - got]
         pts.append(p)
