@@ -167,8 +167,13 @@ pcc_status pcc_context_destroy(pcc_context *ctx);
  *                          instead of as a captured graph.  Default 0.
  *   PCC_CTX_GRAPH_ITERS    PGD iterations per captured graph launch (1..64,
  *                          default 8); one small readback follows each launch.
+ *   PCC_CTX_EXACT_PAIRS    0/1: always count the pairs a mode keeps in a pass
+ *                          of its own before writing them (the path taken
+ *                          anyway when the slots sized by the pair classes
+ *                          would not fit in half the free device memory).
+ *                          Results are the same either way.  Default 0.
  */
-enum { PCC_CTX_KERNEL_TIMING = 1, PCC_CTX_GRAPH_ITERS = 2 };
+enum { PCC_CTX_KERNEL_TIMING = 1, PCC_CTX_GRAPH_ITERS = 2, PCC_CTX_EXACT_PAIRS = 3 };
 pcc_status pcc_context_set(pcc_context *ctx, int32_t key, int64_t value);
 
 void pcc_params_init(pcc_params *p);

@@ -250,7 +250,7 @@ class Context:
             pass
 
     def set_option(self, key: str, value: int):
-        code = {"kernel_timing": 1, "graph_iters": 2}[key]
+        code = {"kernel_timing": 1, "graph_iters": 2, "exact_pairs": 3}[key]
         _check(lib().pcc_context_set(self._h, code, int(value)))
 
     # ------------------------------------------------------------------

@@ -75,6 +75,11 @@ pcc_status pcc_context_set(pcc_context *ctx, int32_t key, int64_t value) {
     ctx->c.graph_iters = (int)value;
     return PCC_OK;
   }
+  if (key == PCC_CTX_EXACT_PAIRS) {
+    if (value != 0 && value != 1) return fail(PCC_E_INVALID_ARG, "exact pairs is 0 or 1");
+    ctx->c.force_exact_pairs = value != 0;
+    return PCC_OK;
+  }
   return fail(PCC_E_INVALID_ARG, "unknown context option");
 }
 

@@ -50,6 +50,7 @@ struct Context {
   int device = 0;
   KernelTimer kt;
   int graph_iters = 8;
+  bool force_exact_pairs = false;  // always count the kept pairs before writing them
   std::vector<BcTable> bc;
   hipStream_t own = nullptr;
   Arena arena;

@@ -49,7 +49,11 @@ struct PairBufs {
   const uint32_t *cell_of, *cell_start;
   const int32_t *nbr;
   uint32_t *safe_par, *fof_par;          // union-find parents (sorted space)
-  uint32_t *cnt_a, *cnt_f;               // per particle counts
+  uint32_t *cnt_pb, *cnt_pc;             // pass 1: pb and pc pairs of each home particle
+  uint32_t *cnt_a, *cnt_f;               // pass 2: active and forest pairs (exact path);
+                                         // pass 3: filled active slots (slotted path)
+  const uint32_t *cap_f;                 // slotted path: forest slots of each home particle
+  int slotted;                           // pass 3 writes into slots sized by pass 1
   unsigned long long *job_counts;        // [njobs][count_slots][16]: safe, pb, pc partial sums
   int count_slots;                       // power of two
   const uint64_t *off_a, *off_f;         // write offsets
@@ -71,6 +75,14 @@ void plan_pairs(PairPlan &pl, const uint32_t *cell_of, const uint32_t *cell_star
 void launch_pair_pass1(const PairBufs &b, const PairPlan &pl, hipStream_t s);  // classify, hook
 void launch_pair_count(const PairBufs &b, const PairPlan &pl, hipStream_t s);  // filtered counts
 void launch_pair_write(const PairBufs &b, const PairPlan &pl, hipStream_t s);  // filtered writes
+// slot capacities of the slotted write path from pass 1's class counts: HF
+// jobs get pc slots for active pairs and pb slots for forest candidates, VP
+// and SC jobs pb + pc slots for active pairs
+void pair_slot_caps(const PairBufs &b, uint32_t *cap_a, uint32_t *cap_f, hipStream_t s);
+// moves the filled active slots to the front, in home order
+void compact_slots(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t,
+                   const uint64_t *off_slot, const uint32_t *fill, const uint64_t *off_dense,
+                   size_t n, uint32_t *d_i, uint32_t *d_j, uint8_t *d_t, hipStream_t s);
 void launch_flatten(uint32_t *par, size_t n, hipStream_t s);
 void launch_labels(const uint32_t *root, const float4 *pos, const int64_t *p_off, int njobs,
                    size_t n, uint32_t *minid, int32_t *lab_global, hipStream_t s);

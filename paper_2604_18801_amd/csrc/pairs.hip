@@ -166,7 +166,7 @@ struct Home {
   float4 pi, ri;
   uint32_t sk, fk;     // safe and FoF roots (passes 2 and 3); root guesses (pass 1)
   uint64_t wa, wf;     // write cursors (pass 3)
-  uint32_t ca, cf;     // counts (passes 1 and 2)
+  uint32_t ca, cf;     // counts: pass 1 pc and pb pairs, pass 2 active and forest pairs
 };
 
 template <int PASS>
@@ -187,10 +187,25 @@ __device__ inline void home_begin(const PairBufs &B, Home &h, uint32_t k) {
 
 template <int PASS>
 __device__ inline void home_end(const PairBufs &B, const Home &h) {
-  if (PASS == 1) B.cnt_a[h.k] = h.ca;
+  if (PASS == 1) {
+    B.cnt_pb[h.k] = h.cf;  // potentially broken (safe < d <= b)
+    B.cnt_pc[h.k] = h.ca;  // potentially created (b < d <= r_v)
+  }
   if (PASS == 2) {
     B.cnt_a[h.k] = h.ca;
     B.cnt_f[h.k] = h.cf;
+  }
+  if (PASS == 3 && B.slotted) {
+    // slots sized by pass 1's class counts: record the fill of the active
+    // slots; unused forest slots become self-loops of the home's safe
+    // component, which the spanning forest ignores
+    B.cnt_a[h.k] = (uint32_t)(h.wa - B.off_a[h.k]);
+    const uint64_t fend = B.off_f[h.k] + B.cap_f[h.k];
+    for (uint64_t w = h.wf; w < fend; ++w) {
+      B.f_key[w] = ~0ull;
+      B.f_u[w] = h.sk;
+      B.f_v[w] = h.sk;
+    }
   }
 }
 
@@ -216,7 +231,7 @@ __device__ inline void visit(const PairBufs &B, const JobPair &q, Home &h, uint3
       if (B.fof_par[j] != h.fk) h.fk = uf_union(B.fof_par, h.fk, j);
     } else if (cls == kPb) {
       cnt[1]++;
-      h.ca++;
+      h.cf++;
       if (B.fof_par[j] != h.fk) h.fk = uf_union(B.fof_par, h.fk, j);
     } else {
       cnt[2]++;
@@ -433,6 +448,43 @@ void launch_pair_count(const PairBufs &b, const PairPlan &pl, hipStream_t s) {
 }
 void launch_pair_write(const PairBufs &b, const PairPlan &pl, hipStream_t s) {
   launch_pairs<3>(b, pl, s);
+}
+
+__global__ void k_slot_caps(PairBufs B, uint32_t *cap_a, uint32_t *cap_f) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < B.n;
+       k += (size_t)gridDim.x * blockDim.x) {
+    const int j = job_of(B.p_off, B.njobs, (int64_t)k);
+    const bool hf = B.jobs[j].mode == 2;
+    cap_a[k] = hf ? B.cnt_pc[k] : B.cnt_pb[k] + B.cnt_pc[k];
+    cap_f[k] = hf ? B.cnt_pb[k] : 0u;
+  }
+}
+
+void pair_slot_caps(const PairBufs &b, uint32_t *cap_a, uint32_t *cap_f, hipStream_t s) {
+  if (b.n) k_slot_caps<<<blocks_for(b.n, 256, 65536), 256, 0, s>>>(b, cap_a, cap_f);
+}
+
+__global__ void k_compact_slots(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t,
+                                const uint64_t *off_slot, const uint32_t *fill,
+                                const uint64_t *off_dense, size_t n, uint32_t *d_i,
+                                uint32_t *d_j, uint8_t *d_t) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (size_t)gridDim.x * blockDim.x) {
+    const uint64_t s0 = off_slot[k], d0 = off_dense[k];
+    for (uint32_t c = 0; c < fill[k]; ++c) {
+      d_i[d0 + c] = a_i[s0 + c];
+      d_j[d0 + c] = a_j[s0 + c];
+      d_t[d0 + c] = a_t[s0 + c];
+    }
+  }
+}
+
+void compact_slots(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t,
+                   const uint64_t *off_slot, const uint32_t *fill, const uint64_t *off_dense,
+                   size_t n, uint32_t *d_i, uint32_t *d_j, uint8_t *d_t, hipStream_t s) {
+  if (n)
+    k_compact_slots<<<blocks_for(n, 256, 65536), 256, 0, s>>>(a_i, a_j, a_t, off_slot, fill,
+                                                              off_dense, n, d_i, d_j, d_t);
 }
 
 // root of x without writing anything on the way

@@ -183,6 +183,12 @@ __global__ void k_gather_u64(const uint64_t *src, const int64_t *idx, int m, uin
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < m) dst[t] = (idx[t] < (int64_t)n) ? src[idx[t]] : total;
 }
+__global__ void k_add_u32(const uint32_t *a, const uint32_t *b, size_t n, uint32_t *out) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (size_t)gridDim.x * blockDim.x)
+    out[k] = a[k] + b[k];
+}
+
 __global__ void k_gather_u32(const uint32_t *src, const int64_t *idx, int m, uint32_t total,
                              size_t n, uint32_t *dst) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -524,6 +530,8 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
   pb.nbr = nbr;
   pb.safe_par = dev<uint32_t>(ar, n);
   pb.fof_par = dev<uint32_t>(ar, n);
+  pb.cnt_pb = dev<uint32_t>(ar, n);
+  pb.cnt_pc = dev<uint32_t>(ar, n);
   pb.cnt_a = dev<uint32_t>(ar, n);
   pb.cnt_f = dev<uint32_t>(ar, n);
   pb.count_slots = 64;
@@ -580,29 +588,83 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
     all_vp &= h->dev.mode == PCC_MODE_VP;
     any_hf |= h->dev.mode == PCC_MODE_HF;
   }
-  if (!all_vp) {
-    const int at = kt.start(1, s);
-    launch_pair_count(pb, plan, s);
-    kt.stop(at, s);
-  }
-  else fill_u32(pb.cnt_f, 0, n, s);
+  // Slotted path: pass 3 writes each home's pairs into slots sized by its
+  // pass-1 class counts (an upper bound of what the mode keeps), then the
+  // active slots are compacted; used when the slots fit in half the free
+  // device memory.  Otherwise the exact path counts the kept pairs in a
+  // pass of its own first.
+  uint32_t *cap_a = dev<uint32_t>(ar, n), *cap_f = dev<uint32_t>(ar, n);
+  pair_slot_caps(pb, cap_a, cap_f, s);
   uint64_t *off_a = dev<uint64_t>(ar, n), *off_f = dev<uint64_t>(ar, n);
-  uint64_t *tot = dev<uint64_t>(ar, 2);
-  scan_u32_u64(pb.cnt_a, off_a, n, tot, ar, s);
-  scan_u32_u64(pb.cnt_f, off_f, n, tot + 1, ar, s);
-  uint64_t htot[2];
+  uint64_t *tot = dev<uint64_t>(ar, 3);
+  scan_u32_u64(cap_a, off_a, n, tot, ar, s);
+  scan_u32_u64(cap_f, off_f, n, tot + 1, ar, s);
+  uint64_t htot[3];
   st.fetch(htot, tot, 2);
-  const size_t na_direct = htot[0], nf = htot[1];
-  const size_t na_cap = na_direct + (any_hf ? n : 0);
-  pb.off_a = off_a;
-  pb.off_f = off_f;
-  pb.a_i = dev<uint32_t>(ar, na_cap);
-  pb.a_j = dev<uint32_t>(ar, na_cap);
-  pb.a_t = dev<uint8_t>(ar, na_cap);
-  pb.f_key = dev<uint64_t>(ar, nf);
-  pb.f_u = dev<uint32_t>(ar, nf);
-  pb.f_v = dev<uint32_t>(ar, nf);
-  {
+  size_t free_b = 0, total_b = 0;
+  PCC_HIP(hipMemGetInfo(&free_b, &total_b));
+  const double slot_bytes = 9.0 * (double)htot[0] * (all_vp ? 1.0 : 2.0) + 16.0 * (double)htot[1];
+  pb.slotted = slot_bytes <= 0.5 * (double)free_b && !C.force_exact_pairs;
+  size_t na_direct = 0, nf = 0;
+  uint32_t *a_i = nullptr, *a_j = nullptr;
+  uint8_t *a_t = nullptr;
+  if (pb.slotted) {
+    nf = htot[1];
+    const size_t a_slots = htot[0];
+    pb.off_a = off_a;
+    pb.off_f = off_f;
+    pb.cap_f = cap_f;
+    pb.a_i = dev<uint32_t>(ar, a_slots);
+    pb.a_j = dev<uint32_t>(ar, a_slots);
+    pb.a_t = dev<uint8_t>(ar, a_slots);
+    pb.f_key = dev<uint64_t>(ar, nf);
+    pb.f_u = dev<uint32_t>(ar, nf);
+    pb.f_v = dev<uint32_t>(ar, nf);
+    {
+      const int at = kt.start(2, s);
+      launch_pair_write(pb, plan, s);
+      kt.stop(at, s);
+    }
+    uint64_t *off_d = dev<uint64_t>(ar, n);
+    scan_u32_u64(pb.cnt_a, off_d, n, tot + 2, ar, s);
+    st.fetch(&htot[2], tot + 2, 1);
+    na_direct = htot[2];
+    const size_t na_cap = na_direct + (any_hf ? n : 0);
+    if (na_direct == a_slots && na_cap <= a_slots) {
+      // every slot filled: the slots already are the active list
+      a_i = pb.a_i;
+      a_j = pb.a_j;
+      a_t = pb.a_t;
+    } else {
+      a_i = dev<uint32_t>(ar, na_cap);
+      a_j = dev<uint32_t>(ar, na_cap);
+      a_t = dev<uint8_t>(ar, na_cap);
+      compact_slots(pb.a_i, pb.a_j, pb.a_t, off_a, pb.cnt_a, off_d, n, a_i, a_j, a_t, s);
+    }
+  } else {
+    if (!all_vp) {
+      const int at = kt.start(1, s);
+      launch_pair_count(pb, plan, s);
+      kt.stop(at, s);
+    } else {
+      // VP keeps every vulnerable pair and no forest candidate
+      k_add_u32<<<blocks_for(n, 256, 65536), 256, 0, s>>>(pb.cnt_pb, pb.cnt_pc, n, pb.cnt_a);
+      fill_u32(pb.cnt_f, 0, n, s);
+    }
+    scan_u32_u64(pb.cnt_a, off_a, n, tot, ar, s);
+    scan_u32_u64(pb.cnt_f, off_f, n, tot + 1, ar, s);
+    st.fetch(htot, tot, 2);
+    na_direct = htot[0];
+    nf = htot[1];
+    const size_t na_cap = na_direct + (any_hf ? n : 0);
+    pb.off_a = off_a;
+    pb.off_f = off_f;
+    a_i = pb.a_i = dev<uint32_t>(ar, na_cap);
+    a_j = pb.a_j = dev<uint32_t>(ar, na_cap);
+    a_t = pb.a_t = dev<uint8_t>(ar, na_cap);
+    pb.f_key = dev<uint64_t>(ar, nf);
+    pb.f_u = dev<uint32_t>(ar, nf);
+    pb.f_v = dev<uint32_t>(ar, nf);
     const int at = kt.start(2, s);
     launch_pair_write(pb, plan, s);
     kt.stop(at, s);
@@ -616,7 +678,7 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
     PCC_HIP(hipMemcpyAsync(bpar, pb.safe_par, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     const int at = kt.start(7, s);
     na += (size_t)boruvka(pb.f_key, pb.f_u, pb.f_v, nf, bpar, n, inv_perm, d_poff, J,
-                          pb.a_i + na_direct, pb.a_j + na_direct, pb.a_t + na_direct, ar, s);
+                          a_i + na_direct, a_j + na_direct, a_t + na_direct, ar, s);
     kt.stop(at, s);
   }
   PCC_HIP(hipEventRecord(C.ev[5], s));
@@ -628,13 +690,13 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
     int64_t nmax = 1;
     for (auto *h : act) nmax = std::max(nmax, h->n);
     const int at = kt.start(6, s);
-    sort_pairs(pb.a_i, pb.a_j, pb.a_t, na, pos, bits_for((uint64_t)(nmax - 1)), ar, s);
+    sort_pairs(a_i, a_j, a_t, na, pos, bits_for((uint64_t)(nmax - 1)), ar, s);
     kt.stop(at, s);
   }
   uint8_t *is_e = dev<uint8_t>(ar, n);
   uint32_t *eid = dev<uint32_t>(ar, n);
   uint32_t *ne_dev = dev<uint32_t>(ar, 1);
-  mark_editable(pb.a_i, pb.a_j, na, n, is_e, eid, ne_dev, ar, s);
+  mark_editable(a_i, a_j, na, n, is_e, eid, ne_dev, ar, s);
   uint32_t ne = 0;
   st.fetch(&ne, ne_dev, 1);
   uint32_t *e_list = dev<uint32_t>(ar, ne);
@@ -646,7 +708,7 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
   {
     const int at = kt.start(6, s);
     order_rows(e_list, ne, eid, pos, d_jobs, d_poff, J, ar, s);
-    build_csr(pb.a_i, pb.a_j, pb.a_t, na, eid, ne, row_ptr, col, ar, s);
+    build_csr(a_i, a_j, a_t, na, eid, ne, row_ptr, col, ar, s);
     kt.stop(at, s);
   }
   std::vector<int64_t> e_off(J + 1);
@@ -938,9 +1000,9 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
   C.last.n = n;
   C.last.na = na;
   C.last.ne = ne;
-  C.last.a_i = pb.a_i;
-  C.last.a_j = pb.a_j;
-  C.last.a_t = pb.a_t;
+  C.last.a_i = a_i;
+  C.last.a_j = a_j;
+  C.last.a_t = a_t;
   C.last.safe_root = pb.safe_par;
   C.last.pos = pos;
   C.last.e_list = e_list;

@@ -237,3 +237,29 @@ def test_active_set_steps_are_exact(ctx, k):
     assert 2 * st["n_active"] <= st["pgd_incidences_evaluated"] <= steps * 2 * st["n_active"]
     if k == 0:
         assert st["pgd_rows_evaluated"] < steps * ne
+
+
+@pytest.mark.parametrize("mode", ["vp", "sc", "hf"])
+def test_slotted_and_exact_pair_paths_agree(ctx, mode):
+    # the write pass either fills slots sized by the pair classes (then
+    # compacts them) or writes at offsets counted in a pass of its own
+    import paper_2604_18801_amd as pcc
+    w = synth.cosmology(24, seed=9, xi=0.05)
+    print("case slotted vs exact", mode, flush=True)
+    ex = pcc.Context(0)
+    try:
+        ex.set_option("exact_pairs", 1)
+        s1, l1, st1 = ctx.correct(_dev(w.orig), _dev(w.recon), w.b, w.xi, mode=mode, box=w.box,
+                                  debug_xyz=True, max_iters=40)
+        p1 = _pairs(ctx)
+        s2, l2, st2 = ex.correct(_dev(w.orig), _dev(w.recon), w.b, w.xi, mode=mode, box=w.box,
+                                 debug_xyz=True, max_iters=40)
+        p2 = _pairs(ex)
+    finally:
+        ex.close()
+    assert s1 == s2
+    np.testing.assert_array_equal(l1.cpu().numpy(), l2.cpu().numpy())
+    np.testing.assert_array_equal(st1["debug_xyz"], st2["debug_xyz"])
+    for a, b in zip(p1, p2):
+        np.testing.assert_array_equal(a, b)
+    assert st1["iters"] == st2["iters"] and st1["n_active"] == st2["n_active"]
