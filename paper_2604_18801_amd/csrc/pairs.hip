@@ -277,8 +277,26 @@ __device__ inline void visit(const PairBufs &B, const JobPair &q, Home &h, uint3
 }
 
 // Sparse cells: one thread per particle (list of particles of cells with
-// fewer than kDenseCell members).  Partners: later particles of its own cell,
-// then every particle of the 13 forward cells, in index order.
+// fewer than kDenseCell members, ordered by the candidate count of their
+// cell).  Partners: later particles of its own cell, then every particle of
+// the 13 forward cells, in index order.  The walk over those ranges is one
+// flat loop, one candidate per lane per iteration, so a lane stays busy until
+// its own candidates run out (nested loops over the ranges would idle every
+// lane whose current range is shorter than the longest one in the wave); the
+// next candidate's position is loaded before the current one is examined.
+// moves (j, e) to the next non-empty candidate range when the current one is
+// exhausted; s counts the forward cells entered so far
+__device__ inline void next_range(const uint32_t *cs, const int32_t *nbr, uint32_t &j,
+                                  uint32_t &e, int &s) {
+  while (j >= e && s < 13) {
+    const int32_t nb = nbr[s++];
+    if (nb >= 0) {
+      j = cs[nb];
+      e = cs[nb + 1];
+    }
+  }
+}
+
 template <int PASS>
 __global__ void __launch_bounds__(256) k_pairs_sparse(PairBufs B, const uint32_t *list, size_t m) {
   unsigned long long cnt[3] = {0ull, 0ull, 0ull};  // safe, pb, pc
@@ -290,18 +308,23 @@ __global__ void __launch_bounds__(256) k_pairs_sparse(PairBufs B, const uint32_t
     Home h;
     home_begin<PASS>(B, h, k);
     const uint32_t cell = B.cell_of[k];
-    for (int s = 0; s < 14; ++s) {
-      uint32_t j0, j1;
-      if (s == 0) {
-        j0 = k + 1;
-        j1 = B.cell_start[cell + 1];
-      } else {
-        const int32_t nb = B.nbr[(size_t)cell * 13 + s - 1];
-        if (nb < 0) continue;
-        j0 = B.cell_start[nb];
-        j1 = B.cell_start[nb + 1];
-      }
-      for (uint32_t j = j0; j < j1; ++j) visit<PASS>(B, q, h, j, B.pos[j], cnt);
+    const int32_t *nbr = B.nbr + (size_t)cell * 13;
+    const uint32_t *cs = B.cell_start;
+    // (j, e): the current range; s: forward cells entered so far
+    int s = 0;
+    uint32_t j = k + 1, e = cs[cell + 1];
+    next_range(cs, nbr, j, e, s);
+    float4 pj = B.pos[j < e ? j : k];  // (index k: any valid load)
+    while (j < e) {
+      uint32_t jn = j + 1, en = e;
+      int sn = s;
+      next_range(cs, nbr, jn, en, sn);
+      const float4 pn = B.pos[jn < en ? jn : k];
+      visit<PASS>(B, q, h, j, pj, cnt);
+      j = jn;
+      e = en;
+      s = sn;
+      pj = pn;
     }
     home_end<PASS>(B, h);
   }
@@ -380,6 +403,22 @@ __global__ void k_sparse_list(const uint8_t *flag, const uint32_t *pos32, size_t
        k += (size_t)gridDim.x * blockDim.x)
     if (flag[k]) list[pos32[k]] = (uint32_t)k;
 }
+// 65535 minus the number of particles in a sparse particle's cell and its 13
+// forward cells (capped): ascending keys put the heaviest cells first
+__global__ void k_sparse_keys(const uint32_t *list, size_t m, const uint32_t *cell_of,
+                              const uint32_t *cell_start, const int32_t *nbr, uint32_t *key) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t c = cell_of[list[i]];
+    uint32_t cost = cell_start[c + 1] - cell_start[c];
+    for (int s = 0; s < 13; ++s) {
+      const int32_t nb = nbr[(size_t)c * 13 + s];
+      if (nb >= 0) cost += cell_start[nb + 1] - cell_start[nb];
+    }
+    key[i] = 65535u - (cost < 65535u ? cost : 65535u);
+  }
+}
+
 __global__ void k_unit_counts(const uint32_t *cell_start, const uint32_t *n_cells, size_t max_cells,
                               uint32_t *units) {
   const uint32_t U = *n_cells;
@@ -404,7 +443,7 @@ __global__ void k_unit_list(const uint32_t *units, const uint32_t *uoff, size_t 
 }
 
 void plan_pairs(PairPlan &pl, const uint32_t *cell_of, const uint32_t *cell_start,
-                const uint32_t *n_cells, size_t n, Arena &ar, hipStream_t s) {
+                const int32_t *nbr, const uint32_t *n_cells, size_t n, Arena &ar, hipStream_t s) {
   uint8_t *flag = ar.get<uint8_t>(n ? n : 1);
   uint32_t *pos32 = ar.get<uint32_t>(n ? n : 1);
   uint32_t *cnt = ar.get<uint32_t>(2);
@@ -417,6 +456,16 @@ void plan_pairs(PairPlan &pl, const uint32_t *cell_of, const uint32_t *cell_star
     k_sparse_flags<<<nb, 256, 0, s>>>(cell_of, cell_start, n, flag);
     scan_u8_u32(flag, pos32, n, cnt, ar, s);
     k_sparse_list<<<nb, 256, 0, s>>>(flag, pos32, n, pl.sparse);
+    // heaviest cells first, a cell's particles together and in index order
+    uint32_t ns = 0;
+    PCC_HIP(hipMemcpyAsync(&ns, cnt, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    PCC_HIP(hipStreamSynchronize(s));
+    if (ns > 1) {
+      uint32_t *key = ar.get<uint32_t>(ns);
+      k_sparse_keys<<<blocks_for(ns, 256, 65536), 256, 0, s>>>(pl.sparse, ns, cell_of, cell_start,
+                                                               nbr, key);
+      radix_sort_u32(key, pl.sparse, ns, 16, ar, s);
+    }
     k_unit_counts<<<nb, 256, 0, s>>>(cell_start, n_cells, n, units);
     scan_u32_u32(units, uoff, n, cnt + 1, ar, s);
     k_unit_list<<<nb, 256, 0, s>>>(units, uoff, n, pl.ucell, pl.uchunk);

@@ -341,7 +341,9 @@ __device__ inline uint64_t dbits(double x) { return (uint64_t)__double_as_longlo
 #define PCC_PGD_MIN_WAVES 4
 #endif
 __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(PgdBufs B) {
-  __shared__ double4 s_self[kPgdWaves][64];
+  // positions of the tile's rows, one array per axis: lanes read rows at
+  // random, and 8-byte entries spread them over the LDS banks
+  __shared__ double s_px[kPgdWaves][64], s_py[kPgdWaves][64], s_pz[kPgdWaves][64];
   __shared__ double s_term[kPgdWaves][3][64];
   __shared__ uint32_t s_rp[kPgdWaves][64];  // first incidence of each row in the CSR
   __shared__ uint32_t s_vb[kPgdWaves][64];  // first slot of each row in the tile's work list
@@ -390,7 +392,9 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
       if (lane >= d) incl += y;
     }
     const uint32_t vb = incl - len, total = __shfl(incl, 63, kWave);
-    s_self[w][lane] = pe;
+    s_px[w][lane] = pe.x;
+    s_py[w][lane] = pe.y;
+    s_pz[w][lane] = pe.z;
     s_rp[w][lane] = q0;
     s_vb[w][lane] = vb;
     s_e[w][lane] = (uint32_t)e;
@@ -427,10 +431,9 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
       if (q < total) {
         const uint32_t o = col & 0x7fffffffu;
         const uint32_t er = s_e[w][r];
-        const double4 me = s_self[w][r];
-        const double dx = wrapd(me.x - po.x, L0, h0);
-        const double dy = wrapd(me.y - po.y, L1, h1);
-        const double dz = wrapd(me.z - po.z, L2, h2);
+        const double dx = wrapd(s_px[w][r] - po.x, L0, h0);
+        const double dy = wrapd(s_py[w][r] - po.y, L1, h1);
+        const double dz = wrapd(s_pz[w][r] - po.z, L2, h2);
         const double d2 = (dx * dx + dy * dy) + dz * dz;
         double h = 0.0;
         if (!(col >> 31)) {
@@ -504,8 +507,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
       }
       const double bc1 = B.loop[job].bc1, bc2 = B.loop[job].bc2;
       const double g[3] = {gx, gy, gz};
-      pe = s_self[w][lane];
-      const double p[3] = {pe.x, pe.y, pe.z};
+      const double p[3] = {s_px[w][lane], s_py[w][lane], s_pz[w][lane]};
       const double xs[3] = {(double)x.x, (double)x.y, (double)x.z};
       double np[3];
       uint64_t state = 0;

@@ -512,7 +512,7 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
   int32_t *nbr = dev<int32_t>(ar, n * 13);
   launch_neighbors(d_jobs, d_cbase, J, cell_key, n_cells, n, nbr, s);
   PairPlan plan;
-  plan_pairs(plan, cell_of, cell_start, n_cells, n, ar, s);
+  plan_pairs(plan, cell_of, cell_start, nbr, n_cells, n, ar, s);
   PCC_HIP(hipEventRecord(C.ev[2], s));
 
   // ------------------------------------------------------------------
