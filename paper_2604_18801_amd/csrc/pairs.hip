@@ -588,28 +588,31 @@ void launch_labels(const uint32_t *root, const float4 *pos, const int64_t *p_off
 // With distinct keys the minimum spanning forest is unique, so this equals
 // Kruskal's forest in ascending key order.
 // ----------------------------------------------------------------------------
-// Each alive edge offers its key to the best (smallest) edge of both of its
+// At the start of a round every candidate holds the current roots of its two
+// ends (safe roots in the first round, relabelled ones after), so no find is
+// needed until the round's unions.  A candidate whose ends share a root is
+// dead (the first round's unused slots are such self-loops).
+//
+// Each live edge offers its key to the best (smallest) edge of both of its
 // components.  Edges of one home particle sit in consecutive lanes and share
 // their first component: a segmented minimum over such runs leaves one
 // atomic per run; a read of the current best skips atomics that cannot win.
 __global__ void __launch_bounds__(256) k_bor_min(const uint64_t *key, const uint32_t *u,
-                                                 const uint32_t *v, size_t m, uint32_t *bpar,
-                                                 unsigned long long *best, uint8_t *alive) {
+                                                 const uint32_t *v, size_t m,
+                                                 unsigned long long *best) {
   const int lane = threadIdx.x & 63;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   // the loop runs the same number of times in every lane of a wave
   const size_t base0 = (size_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
   for (size_t b0 = base0; b0 < m; b0 += stride) {
     const size_t c = b0 + lane;
-    const bool in = c < m;
     uint32_t cu = 0xffffffffu, cv = 0xffffffffu;
     unsigned long long k = ~0ull;
     bool live = false;
-    if (in) {
-      cu = uf_find(bpar, u[c]);
-      cv = uf_find(bpar, v[c]);
+    if (c < m) {
+      cu = u[c];
+      cv = v[c];
       live = cu != cv;
-      alive[c] = live ? 1 : 0;
       k = key[c];
     }
     // segmented minimum over runs of equal cu among live lanes
@@ -628,26 +631,18 @@ __global__ void __launch_bounds__(256) k_bor_min(const uint64_t *key, const uint
   }
 }
 
-__global__ void k_bor_mark(const uint64_t *key, const uint32_t *u, const uint32_t *v, size_t m,
-                           uint32_t *bpar, const unsigned long long *best, uint8_t *alive,
-                           uint8_t *sel) {
+// the best edge of either end's component is a forest edge: mark it and
+// hook its two components together
+__global__ void k_bor_select(const uint64_t *key, const uint32_t *u, const uint32_t *v, size_t m,
+                             const unsigned long long *best, uint32_t *bpar, uint8_t *sel) {
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < m;
        c += (size_t)gridDim.x * blockDim.x) {
-    uint8_t s = 0;
-    if (alive[c]) {
-      const uint32_t cu = uf_find(bpar, u[c]), cv = uf_find(bpar, v[c]);
-      s = (best[cu] == key[c] || best[cv] == key[c]) ? 1 : 0;
-      if (s) alive[c] = 0;
-    }
-    sel[c] = s;
+    const uint32_t cu = u[c], cv = v[c];
+    const uint64_t k = key[c];
+    const bool s = cu != cv && (best[cu] == k || best[cv] == k);
+    sel[c] = s ? 1 : 0;
+    if (s) uf_union(bpar, cu, cv);
   }
-}
-
-__global__ void k_bor_union(const uint32_t *u, const uint32_t *v, size_t m, const uint8_t *sel,
-                            uint32_t *bpar) {
-  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < m;
-       c += (size_t)gridDim.x * blockDim.x)
-    if (sel[c]) uf_union(bpar, u[c], v[c]);
 }
 
 // forest edges of this round -> active pairs (sorted particle indices)
@@ -667,18 +662,18 @@ __global__ void k_bor_emit(const uint64_t *key, const uint32_t *u, size_t m, con
   }
 }
 
-// After the round's unions: candidates that were not selected are kept only
-// if their ends are still in different components, and carry the current
-// roots, so the next round's finds end at once.
+// After the round's unions (and a flatten of the parents): candidates that
+// were not selected are kept only if their ends are still in different
+// components, and carry the new roots.
 __global__ void k_bor_relabel(const uint32_t *u, const uint32_t *v, size_t m, const uint8_t *sel,
-                              uint32_t *bpar, uint32_t *ru, uint32_t *rv, uint8_t *alive) {
+                              const uint32_t *root, uint32_t *ru, uint32_t *rv, uint8_t *alive) {
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < m;
        c += (size_t)gridDim.x * blockDim.x) {
     uint8_t a = 0;
     uint32_t cu = 0, cv = 0;
     if (!sel[c]) {
-      cu = uf_find(bpar, u[c]);
-      cv = uf_find(bpar, v[c]);
+      cu = root[u[c]];
+      cv = root[v[c]];
       a = cu != cv ? 1 : 0;
     }
     alive[c] = a;
@@ -722,12 +717,12 @@ int64_t boruvka(uint64_t *key, uint32_t *u, uint32_t *v, size_t ncand, uint32_t 
     while (m > 0) {
       const int nb = blocks_for(m, 256, 65536);
       fill_u64((uint64_t *)best, ~0ull, n, s);
-      k_bor_min<<<nb, 256, 0, s>>>(key, u, v, m, bpar, best, alive);
-      k_bor_mark<<<nb, 256, 0, s>>>(key, u, v, m, bpar, best, alive, sel);
-      k_bor_union<<<nb, 256, 0, s>>>(u, v, m, sel, bpar);
+      k_bor_min<<<nb, 256, 0, s>>>(key, u, v, m, best);
+      k_bor_select<<<nb, 256, 0, s>>>(key, u, v, m, best, bpar, sel);
       scan_u8_u32(sel, pos32, m, cnt, ar, s);
       k_bor_emit<<<nb, 256, 0, s>>>(key, u, m, sel, pos32, inv_perm, p_off, njobs,
                                     out_i + emitted, out_j + emitted, out_t + emitted);
+      launch_flatten(bpar, n, s);
       k_bor_relabel<<<nb, 256, 0, s>>>(u, v, m, sel, bpar, ru, rv, alive);
       scan_u8_u32(alive, pos32, m, cnt + 1, ar, s);
       k_bor_compact<<<nb, 256, 0, s>>>(key, ru, rv, m, alive, pos32, key2, u2, v2);
