@@ -384,6 +384,123 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense(PairBufs B, con
   if (PASS == 1) job_add<3>(B.job_counts, B.count_slots, job, valid, cnt);
 }
 
+// Mode filter of one partner j of a home particle in the write pass (the
+// exact class first): to_a for the active list, to_f for HF's forest
+// candidates.
+__device__ inline void write_filter(const PairBufs &B, const JobPair &q, const Home &h, uint32_t j,
+                                    const float4 &pj, int &cls, bool &to_a, bool &to_f) {
+  to_a = to_f = false;
+  cls = kNone;
+  const float dx = wrap_f(h.pi.x - pj.x, q.Lf[0], q.hLf[0]);
+  const float dy = wrap_f(h.pi.y - pj.y, q.Lf[1], q.hLf[1]);
+  const float dz = wrap_f(h.pi.z - pj.z, q.Lf[2], q.hLf[2]);
+  if ((dx * dx + dy * dy) + dz * dz > q.rv2f) return;
+  const double d2 = dist2_exact(h.pi, pj, q);
+  if (d2 > q.rv2 || d2 <= q.rs2) return;
+  cls = d2 <= q.b2 ? kPb : kPc;
+  if (q.mode == 0) {
+    to_a = true;
+  } else if (q.mode == 1) {
+    to_a = B.safe_par[j] != h.sk;
+  } else if (cls == kPc) {
+    to_a = B.fof_par[j] != h.fk;
+  } else {
+    to_f = B.safe_par[j] != h.sk;
+  }
+}
+
+// Forest key of a candidate: links already broken in the reconstruction
+// last, then the pair of job-local indices.
+__device__ inline uint64_t forest_key(const PairBufs &B, const JobPair &q, const Home &h, uint32_t j,
+                                      const float4 &pj) {
+  const float4 rj = B.rec[j];
+  const double ex = wrap_d((double)h.ri.x - (double)rj.x, q.L[0], q.hL[0]);
+  const double ey = wrap_d((double)h.ri.y - (double)rj.y, q.L[1], q.hL[1]);
+  const double ez = wrap_d((double)h.ri.z - (double)rj.z, q.L[2], q.hL[2]);
+  const uint64_t viol0 = ((ex * ex + ey * ey) + ez * ez) > q.bm2 ? 1ull : 0ull;
+  const uint32_t li = __float_as_uint(h.pi.w), lj = __float_as_uint(pj.w);
+  const uint64_t lo = li < lj ? li : lj, hi = li < lj ? lj : li;
+  return (viol0 << 62) | (lo << 31) | hi;
+}
+
+// Write pass over dense cells.  The 64 home particles of a unit are
+// consecutive, so their slots form one block; the kept pairs are appended
+// to that block at a wave-wide cursor (ballot and prefix count), in the
+// order (partner, home lane), which turns the stores into contiguous runs.
+// The first home of the unit records the block's fill; unused forest slots
+// at the block's end become self-loops.
+__global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense_write(PairBufs B,
+                                                                       const uint32_t *ucell,
+                                                                       const uint32_t *uchunk,
+                                                                       size_t m) {
+  __shared__ float4 stage[kPairWaves][64];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const size_t unit = (size_t)blockIdx.x * kPairWaves + w;
+  if (unit >= m) return;  // the whole wave leaves together
+  const uint32_t cell = ucell[unit];
+  const uint32_t cs = B.cell_start[cell], ce = B.cell_start[cell + 1];
+  const uint32_t k0 = cs + 64u * uchunk[unit];
+  const uint32_t nh = (ce - k0) < 64u ? (ce - k0) : 64u;
+  const bool valid = (uint32_t)lane < nh;
+  const int job = __builtin_amdgcn_readfirstlane(job_of(B.p_off, B.njobs, (int64_t)k0));
+  const JobPair q = load_job(B.jobs[job]);
+  Home h;
+  home_begin<3>(B, h, valid ? k0 + lane : k0);
+  const uint64_t a0 = B.off_a[k0], f0 = B.off_f[k0];
+  uint64_t wa = a0, wf = f0;
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (int s = 0; s < 14; ++s) {
+    uint32_t j0, j1;
+    if (s == 0) {
+      j0 = k0 + 1;  // later particles of the home cell
+      j1 = ce;
+    } else {
+      const int32_t nb = B.nbr[(size_t)cell * 13 + s - 1];
+      if (nb < 0) continue;
+      j0 = B.cell_start[nb];
+      j1 = B.cell_start[nb + 1];
+    }
+    for (uint32_t t0 = j0; t0 < j1; t0 += 64) {
+      const uint32_t cnt_t = (j1 - t0) < 64u ? (j1 - t0) : 64u;
+      if ((uint32_t)lane < cnt_t) stage[w][lane] = B.pos[t0 + lane];
+      wave_sync();
+      for (uint32_t t = 0; t < cnt_t; ++t) {
+        const uint32_t j = t0 + t;
+        const float4 pj = stage[w][t];
+        int cls = kNone;
+        bool ta = false, tf = false;
+        if (valid && !(s == 0 && j <= h.k)) write_filter(B, q, h, j, pj, cls, ta, tf);
+        const uint64_t ba = __ballot(ta), bf = __ballot(tf);
+        if (ta) {
+          const uint64_t d = wa + (uint64_t)__popcll(ba & below);
+          B.a_i[d] = h.k;
+          B.a_j[d] = j;
+          B.a_t[d] = (uint8_t)cls;
+        }
+        if (tf) {
+          const uint64_t d = wf + (uint64_t)__popcll(bf & below);
+          B.f_key[d] = forest_key(B, q, h, j, pj);
+          B.f_u[d] = h.sk;
+          B.f_v[d] = B.safe_par[j];
+        }
+        wa += (uint64_t)__popcll(ba);
+        wf += (uint64_t)__popcll(bf);
+      }
+      wave_sync();
+    }
+  }
+  if (B.slotted) {
+    if (valid) B.cnt_a[h.k] = lane == 0 ? (uint32_t)(wa - a0) : 0u;
+    const uint32_t last = k0 + nh - 1;
+    const uint64_t fend = B.off_f[last] + B.cap_f[last];
+    for (uint64_t x = wf + lane; x < fend; x += 64) {
+      B.f_key[x] = ~0ull;
+      B.f_u[x] = k0;
+      B.f_v[x] = k0;
+    }
+  }
+}
+
 #ifndef PCC_DENSE_CELL
 #define PCC_DENSE_CELL 32
 #endif
@@ -484,9 +601,13 @@ static void launch_pairs(const PairBufs &b, const PairPlan &pl, hipStream_t s) {
   if (pl.n_sparse)
     k_pairs_sparse<PASS><<<blocks_for(pl.n_sparse, 256, 1 << 30), 256, 0, s>>>(b, pl.sparse,
                                                                                 pl.n_sparse);
-  if (pl.n_units)
-    k_pairs_dense<PASS><<<(unsigned)((pl.n_units + kPairWaves - 1) / kPairWaves), 64 * kPairWaves,
-                          0, s>>>(b, pl.ucell, pl.uchunk, pl.n_units);
+  if (pl.n_units) {
+    const unsigned nb = (unsigned)((pl.n_units + kPairWaves - 1) / kPairWaves);
+    if (PASS == 3)
+      k_pairs_dense_write<<<nb, 64 * kPairWaves, 0, s>>>(b, pl.ucell, pl.uchunk, pl.n_units);
+    else
+      k_pairs_dense<PASS><<<nb, 64 * kPairWaves, 0, s>>>(b, pl.ucell, pl.uchunk, pl.n_units);
+  }
 }
 
 void launch_pair_pass1(const PairBufs &b, const PairPlan &pl, hipStream_t s) {
@@ -615,19 +736,21 @@ __global__ void __launch_bounds__(256) k_bor_min(const uint64_t *key, const uint
       live = cu != cv;
       k = key[c];
     }
-    // segmented minimum over runs of equal cu among live lanes
-    const uint32_t gid = live ? cu : 0xffffffffu;
-    unsigned long long seg = live ? k : ~0ull;
+    // segmented minima over runs of equal cu and of equal cv among live
+    // lanes (a home particle's candidates, or one partner's, sit together)
+    const uint32_t gu = live ? cu : 0xffffffffu, gv = live ? cv : 0xffffffffu;
+    unsigned long long su = live ? k : ~0ull, sv = su;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
-      const unsigned long long o = __shfl_down(seg, d, kWave);
-      const uint32_t og = __shfl_down(gid, d, kWave);
-      if (lane + d < 64 && og == gid && o < seg) seg = o;
+      const unsigned long long ou = __shfl_down(su, d, kWave), ov = __shfl_down(sv, d, kWave);
+      const uint32_t ogu = __shfl_down(gu, d, kWave), ogv = __shfl_down(gv, d, kWave);
+      if (lane + d < 64 && ogu == gu && ou < su) su = ou;
+      if (lane + d < 64 && ogv == gv && ov < sv) sv = ov;
     }
-    const uint32_t prev = __shfl_up(gid, 1, kWave);
-    const bool head = live && (lane == 0 || prev != gid);
-    if (head && best[cu] > seg) atomicMin(best + cu, seg);
-    if (live && best[cv] > k) atomicMin(best + cv, k);
+    const uint32_t pu = __shfl_up(gu, 1, kWave), pv = __shfl_up(gv, 1, kWave);
+    const bool hu = live && (lane == 0 || pu != gu), hv = live && (lane == 0 || pv != gv);
+    if (hu && best[cu] > su) atomicMin(best + cu, su);
+    if (hv && best[cv] > sv) atomicMin(best + cv, sv);
   }
 }
 
