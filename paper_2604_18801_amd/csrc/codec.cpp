@@ -38,10 +38,6 @@ struct Zstd {
   size_t (*compress)(void *, size_t, const void *, size_t, int) = nullptr;
   size_t (*decompress)(void *, size_t, const void *, size_t) = nullptr;
   unsigned (*is_error)(size_t) = nullptr;
-  void *(*create_cctx)() = nullptr;
-  size_t (*free_cctx)(void *) = nullptr;
-  size_t (*set_param)(void *, int, int) = nullptr;
-  size_t (*compress2)(void *, void *, size_t, const void *, size_t) = nullptr;
 };
 
 Zstd &zstd() {
@@ -54,18 +50,14 @@ Zstd &zstd() {
     z.compress = (size_t(*)(void *, size_t, const void *, size_t, int))dlsym(h, "ZSTD_compress");
     z.decompress = (size_t(*)(void *, size_t, const void *, size_t))dlsym(h, "ZSTD_decompress");
     z.is_error = (unsigned (*)(size_t))dlsym(h, "ZSTD_isError");
-    z.create_cctx = (void *(*)())dlsym(h, "ZSTD_createCCtx");
-    z.free_cctx = (size_t(*)(void *))dlsym(h, "ZSTD_freeCCtx");
-    z.set_param = (size_t(*)(void *, int, int))dlsym(h, "ZSTD_CCtx_setParameter");
-    z.compress2 = (size_t(*)(void *, void *, size_t, const void *, size_t))dlsym(h, "ZSTD_compress2");
     z.ok = z.bound && z.compress && z.decompress && z.is_error;
   });
   return z;
 }
 
-// public parameter numbers of ZSTD_CCtx_setParameter
-constexpr int kZstdLevel = 100;
-constexpr int kZstdWorkers = 400;
+// inputs from this size on are split into pieces of at least this size
+constexpr size_t kZstdParallelMin = (size_t)1 << 20;
+constexpr size_t kZstdJob = (size_t)512 << 10;
 // ZSTD level of the stream payload: the payload is mostly Huffman output and
 // a sparse flag mask, for which the fastest level loses little
 constexpr int kZstdLevelDefault = 1;
@@ -90,23 +82,43 @@ uint32_t reverse_bits(uint32_t c, int len) {
 
 bool zstd_available() { return zstd().ok; }
 
+// Inputs from kZstdParallelMin on are cut into pieces compressed on host
+// threads as independent frames; the frames are concatenated, which one
+// ZSTD decompression call reads back as a whole.
 bool zstd_compress(const uint8_t *src, size_t len, std::vector<uint8_t> &dst, int level) {
   Zstd &z = zstd();
   if (!z.ok || len == 0) return false;
-  dst.resize(z.bound(len));
-  size_t got;
   const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-  if (len >= ((size_t)4 << 20) && z.create_cctx && z.set_param && z.compress2 && hw > 1) {
-    void *cc = z.create_cctx();
-    z.set_param(cc, kZstdLevel, level);
-    z.set_param(cc, kZstdWorkers, (int)std::min(16u, hw));
-    got = z.compress2(cc, dst.data(), dst.size(), src, len);
-    z.free_cctx(cc);
+  size_t pieces = 1;
+  if (len >= kZstdParallelMin && hw > 1)
+    pieces = std::min<size_t>(std::min(16u, hw), (len + kZstdJob - 1) / kZstdJob);
+  const size_t step = (len + pieces - 1) / pieces;
+  std::vector<std::vector<uint8_t>> out(pieces);
+  std::vector<size_t> got(pieces, 0);
+  auto work = [&](size_t p) {
+    const size_t a = p * step, b = std::min(len, a + step);
+    out[p].resize(z.bound(b - a));
+    got[p] = z.compress(out[p].data(), out[p].size(), src + a, b - a, level);
+  };
+  if (pieces == 1) {
+    work(0);
   } else {
-    got = z.compress(dst.data(), dst.size(), src, len, level);
+    std::vector<std::thread> th;
+    for (size_t p = 1; p < pieces; ++p) th.emplace_back(work, p);
+    work(0);
+    for (auto &t : th) t.join();
   }
-  if (z.is_error(got)) return false;
-  dst.resize(got);
+  size_t total = 0;
+  for (size_t p = 0; p < pieces; ++p) {
+    if (z.is_error(got[p])) return false;
+    total += got[p];
+  }
+  dst.resize(total);
+  size_t at = 0;
+  for (size_t p = 0; p < pieces; ++p) {
+    std::memcpy(dst.data() + at, out[p].data(), got[p]);
+    at += got[p];
+  }
   return true;
 }
 

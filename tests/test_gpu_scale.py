@@ -100,3 +100,17 @@ def test_vulnerable_sets_of_sampled_particles_are_complete(ctx, snap):
         want = (d2 > c["rs2"]) & (d2 <= c["rv2"])
         want[s] = False
         assert got[s] == set(np.nonzero(want)[0].tolist()), s
+
+
+def test_large_stream_decodes_with_both_decoders(ctx):
+    # a payload of several MB is compressed in pieces (concatenated frames)
+    import paper_2604_18801_amd as pcc
+    w = synth.cosmology(96, seed=6, xi=0.05)
+    print("case cosmology96 vp max_iters=3", flush=True)
+    stream, _, st = ctx.correct(_dev(w.orig), _dev(w.recon), w.b, w.xi, mode="vp", box=w.box,
+                                max_iters=3, labels=False)
+    assert st["bytes_flags"] + st["bytes_codes"] > (1 << 20)
+    x1 = pcc.decode(stream, w.recon)
+    x2 = oracle.decode(stream, w.recon)
+    np.testing.assert_array_equal(x1, x2)
+    assert np.abs(x1.astype(np.float64) - w.orig).max() <= w.xi
