@@ -520,8 +520,10 @@ __global__ void k_sparse_list(const uint8_t *flag, const uint32_t *pos32, size_t
        k += (size_t)gridDim.x * blockDim.x)
     if (flag[k]) list[pos32[k]] = (uint32_t)k;
 }
-// 65535 minus the number of particles in a sparse particle's cell and its 13
-// forward cells (capped): ascending keys put the heaviest cells first
+// Bucket of a sparse particle by the number of particles in its cell and its
+// 13 forward cells (the candidates it examines), doubling ranges, heaviest
+// first: the lanes of a wave then have similar trip counts, while within a
+// bucket the particles keep their (spatial) order for cache reuse.
 __global__ void k_sparse_keys(const uint32_t *list, size_t m, const uint32_t *cell_of,
                               const uint32_t *cell_start, const int32_t *nbr, uint32_t *key) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
@@ -532,7 +534,8 @@ __global__ void k_sparse_keys(const uint32_t *list, size_t m, const uint32_t *ce
       const int32_t nb = nbr[(size_t)c * 13 + s];
       if (nb >= 0) cost += cell_start[nb + 1] - cell_start[nb];
     }
-    key[i] = 65535u - (cost < 65535u ? cost : 65535u);
+    const uint32_t lg = 31u - (uint32_t)__clz(cost | 1u);  // floor(log2), 0 for cost <= 1
+    key[i] = 15u - (lg < 15u ? lg : 15u);
   }
 }
 
@@ -581,7 +584,7 @@ void plan_pairs(PairPlan &pl, const uint32_t *cell_of, const uint32_t *cell_star
       uint32_t *key = ar.get<uint32_t>(ns);
       k_sparse_keys<<<blocks_for(ns, 256, 65536), 256, 0, s>>>(pl.sparse, ns, cell_of, cell_start,
                                                                nbr, key);
-      radix_sort_u32(key, pl.sparse, ns, 16, ar, s);
+      radix_sort_u32(key, pl.sparse, ns, 4, ar, s);
     }
     k_unit_counts<<<nb, 256, 0, s>>>(cell_start, n_cells, n, units);
     scan_u32_u32(units, uoff, n, cnt + 1, ar, s);

@@ -416,18 +416,31 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
       r = lo;
       col = B.col[s_rp[w][lo] + (q - s_vb[w][lo])];
     };
-    int r_nx = 0;
-    uint32_t col_nx = 0;
-    if ((uint32_t)lane < total) locate(lane, r_nx, col_nx);
+    // two-deep pipeline: while chunk c is evaluated, the partner gather of
+    // chunk c + 1 and the column entries of chunk c + 2 are in flight
+    auto gather = [&](uint32_t col) {
+      const double *pp = reinterpret_cast<const double *>(Pc + (col & 0x7fffffffu));
+      return make_double3(pp[0], pp[1], pp[2]);
+    };
+    int r_nx = 0, r_nx2 = 0;
+    uint32_t col_nx = 0, col_nx2 = 0;
+    double3 po_nx = make_double3(0.0, 0.0, 0.0);
+    if ((uint32_t)lane < total) {
+      locate(lane, r_nx, col_nx);
+      po_nx = gather(col_nx);
+    }
+    if ((uint32_t)lane + 64 < total) locate(lane + 64, r_nx2, col_nx2);
     for (uint32_t c0 = 0; c0 < total; c0 += 64) {
       const uint32_t q = c0 + lane;
       double tx = 0.0, ty = 0.0, tz = 0.0;
       bool hit = false, hit_once = false;
       const int r = r_nx;
       const uint32_t col = col_nx;
-      double4 po = make_double4(0.0, 0.0, 0.0, 0.0);
-      if (q < total) po = Pc[col & 0x7fffffffu];
-      if (q + 64 < total) locate(q + 64, r_nx, col_nx);
+      const double3 po = po_nx;
+      r_nx = r_nx2;
+      col_nx = col_nx2;
+      if (q + 64 < total) po_nx = gather(col_nx);
+      if (q + 128 < total) locate(q + 128, r_nx2, col_nx2);
       if (q < total) {
         const uint32_t o = col & 0x7fffffffu;
         const uint32_t er = s_e[w][r];
