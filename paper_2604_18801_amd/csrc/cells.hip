@@ -123,25 +123,34 @@ void launch_cell_keys(const JobDev *jobs, const int64_t *p_off, int njobs, Soa3 
   if (n) k_cell_keys<<<blocks_for(n, 256, 65536), 256, 0, s>>>(jobs, p_off, njobs, o, n, keys, vals);
 }
 
-// sorted structure of arrays: xyz and the job-local original index in w
-__global__ void k_gather(const uint32_t *perm, const int64_t *p_off, int njobs, Soa3 o, Soa3 r,
-                         size_t n, float4 *pos, float4 *rec, uint32_t *inv_perm) {
+// Sorted structure of arrays: xyz and the job-local original index in w.
+// Written as a scatter: each input particle is read in order (coalesced
+// reads of the six coordinate arrays) and its two records go to its sorted
+// slot, rather than six 4-byte gathers per sorted slot.
+__global__ void k_inv_perm(const uint32_t *perm, size_t n, uint32_t *inv_perm) {
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
-       k += (size_t)gridDim.x * blockDim.x) {
-    const uint32_t g = perm[k];
+       k += (size_t)gridDim.x * blockDim.x)
+    inv_perm[perm[k]] = (uint32_t)k;
+}
+
+__global__ void k_scatter_sorted(const uint32_t *inv_perm, const int64_t *p_off, int njobs, Soa3 o,
+                                 Soa3 r, size_t n, float4 *pos, float4 *rec) {
+  for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
+       g += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t k = inv_perm[g];
     const int j = job_of(p_off, njobs, (int64_t)g);
     const uint32_t lid = (uint32_t)((int64_t)g - p_off[j]);
     pos[k] = make_float4(o.a[0][g], o.a[1][g], o.a[2][g], __uint_as_float(lid));
     rec[k] = make_float4(r.a[0][g], r.a[1][g], r.a[2][g], 0.f);
-    inv_perm[g] = (uint32_t)k;
   }
 }
 
 void launch_gather(const uint32_t *perm, const int64_t *p_off, int njobs, Soa3 o, Soa3 r, size_t n,
                    float4 *pos, float4 *rec, uint32_t *inv_perm, hipStream_t s) {
-  if (n)
-    k_gather<<<blocks_for(n, 256, 65536), 256, 0, s>>>(perm, p_off, njobs, o, r, n, pos, rec,
-                                                       inv_perm);
+  if (!n) return;
+  const int nb = blocks_for(n, 256, 65536);
+  k_inv_perm<<<nb, 256, 0, s>>>(perm, n, inv_perm);
+  k_scatter_sorted<<<nb, 256, 0, s>>>(inv_perm, p_off, njobs, o, r, n, pos, rec);
 }
 
 __global__ void k_cell_flags(const uint32_t *keys, size_t n, uint8_t *flag) {
