@@ -212,6 +212,17 @@ pcc_status pcc_decode(const uint8_t *stream, size_t len, const pcc_particles *re
                       float *out_x, float *out_y, float *out_z);
 
 /*
+ * The same decoding with device arrays (recon and out on the context's GPU):
+ * the stream (a host buffer) is parsed on the host -- ZSTD, then the one
+ * sequential Huffman bitstream -- and a kernel applies the edits; the output
+ * equals pcc_decode's bit for bit.  Work is queued on hip_stream and the call
+ * returns when it is done.  Invalidates the context's retained debug data.
+ */
+pcc_status pcc_decode_device(pcc_context *ctx, const uint8_t *stream, size_t len,
+                             const pcc_particles *recon, float *out_x, float *out_y,
+                             float *out_z, void *hip_stream);
+
+/*
  * Friends-of-friends labels (Sec. 2.4) of a point set at linking length b:
  * labels[k] is the smallest index in k's cluster.  box as in pcc_params.
  * labels has the memspace of pts.

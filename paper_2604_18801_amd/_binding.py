@@ -111,6 +111,8 @@ def lib() -> C.CDLL:
         L.pcc_context_set.argtypes = [C.c_void_p, C.c_int32, C.c_int64]
         L.pcc_debug_fetch.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int64,
                                       C.POINTER(C.c_int64)]
+        L.pcc_decode_device.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(Particles),
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.pcc_server_create.argtypes = [C.c_void_p, C.POINTER(ServerConfig),
                                         C.POINTER(C.c_void_p)]
         L.pcc_server_submit.argtypes = [C.c_void_p, C.POINTER(Job), C.POINTER(C.c_uint64)]
@@ -121,7 +123,7 @@ def lib() -> C.CDLL:
         L.pcc_server_destroy.argtypes = [C.c_void_p]
         for name in ("pcc_context_create", "pcc_context_destroy", "pcc_correct",
                      "pcc_correct_batch", "pcc_decode", "pcc_fof_labels", "pcc_debug_fetch",
-                     "pcc_context_set", "pcc_server_create", "pcc_server_submit",
+                     "pcc_context_set", "pcc_decode_device", "pcc_server_create", "pcc_server_submit",
                      "pcc_server_poll", "pcc_server_wait", "pcc_server_cancel",
                      "pcc_server_drain", "pcc_server_destroy"):
             getattr(L, name).restype = C.c_int32
@@ -304,6 +306,20 @@ class Context:
         res = (JobResult * len(jobs))()
         lib().pcc_correct_batch(self._h, cj, len(jobs), res, _stream_handle(on_dev))
         return [h.result(res[k]) for k, h in enumerate(held)]
+
+    def decode_device(self, stream: bytes, recon):
+        """Apply an edit stream to a (3, N) float32 reconstruction on this
+        GPU; returns a new (3, N) device tensor (bitwise equal to decode())."""
+        import torch
+        pr, kr = _view(recon)
+        if pr.memspace != MEM_DEVICE:
+            raise ValueError("decode_device takes a device tensor; use decode() for host arrays")
+        out = torch.empty((3, max(pr.n, 1)), dtype=torch.float32, device=kr.device)
+        buf = np.frombuffer(stream, dtype=np.uint8).copy()
+        _check(lib().pcc_decode_device(self._h, buf.ctypes.data, len(buf), C.byref(pr),
+                                       out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(),
+                                       _stream_handle(True)))
+        return out[:, : pr.n]
 
     def fof_labels(self, pts, b: float, box=None):
         p, keep = _view(pts)

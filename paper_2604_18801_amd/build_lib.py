@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build", "pcc")
 LIB = os.path.join(HERE, "libpcc.so")
-SOURCES = ["prims.hip", "cells.hip", "pairs.hip", "pgd.hip", "encode.hip", "pipeline.hip",
+SOURCES = ["prims.hip", "cells.hip", "pairs.hip", "pgd.hip", "encode.hip", "decode.hip", "pipeline.hip",
            "codec.cpp", "capi.cpp", "server.cpp"]
 ARCH = os.environ.get("PCC_OFFLOAD_ARCH", "gfx950")
 

@@ -185,6 +185,30 @@ pcc_status pcc_decode(const uint8_t *stream, size_t len, const pcc_particles *re
   });
 }
 
+pcc_status pcc_decode_device(pcc_context *ctx, const uint8_t *stream, size_t len,
+                             const pcc_particles *recon, float *out_x, float *out_y, float *out_z,
+                             void *hip_stream) {
+  if (!ctx || !stream || !recon) return fail(PCC_E_INVALID_ARG, "NULL argument");
+  if (recon->memspace != PCC_MEM_DEVICE)
+    return fail(PCC_E_INVALID_ARG, "pcc_decode_device takes device arrays (pcc_decode: host)");
+  if (recon->n < 0) return fail(PCC_E_INVALID_ARG, "n < 0");
+  if (recon->n > 0 && (!recon->x || !recon->y || !recon->z || !out_x || !out_y || !out_z))
+    return fail(PCC_E_INVALID_ARG, "NULL coordinate pointer");
+  return guarded([&]() -> pcc_status {
+    std::string err;
+    pcc::ParsedStream ps;
+    const pcc_status st = pcc::parse_stream(stream, len, recon->n, ps, err);
+    if (st != PCC_OK) return fail(st, err);
+    PCC_HIP(hipSetDevice(ctx->c.device));
+    ctx->c.arena.reset();
+    ctx->c.last.valid = false;  // the arena's contents of the last correction are gone
+    const float *rin[3] = {recon->x, recon->y, recon->z};
+    float *rout[3] = {out_x, out_y, out_z};
+    pcc::apply_edits_device(ps, rin, rout, ctx->c.arena, pick(ctx, hip_stream));
+    return PCC_OK;
+  });
+}
+
 pcc_status pcc_fof_labels(pcc_context *ctx, const pcc_particles *pts, double b,
                           const double box[3], int32_t *labels, void *hip_stream) {
   if (!ctx || !pts || !labels) return fail(PCC_E_INVALID_ARG, "NULL argument");

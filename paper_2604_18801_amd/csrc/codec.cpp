@@ -244,8 +244,8 @@ void assemble_stream(int64_t n, int m_bits, int64_t nflagged, double qstep, doub
   if (!stored.empty()) std::memcpy(out.data() + kHeader, stored.data(), stored.size());
 }
 
-pcc_status decode_stream(const uint8_t *s, size_t len, int64_t n, const float *rx, const float *ry,
-                         const float *rz, float *ox, float *oy, float *oz, std::string &err) {
+pcc_status parse_stream(const uint8_t *s, size_t len, int64_t n, ParsedStream &out,
+                        std::string &err) {
   if (len < kHeader || get<uint32_t>(s) != kMagic || get<uint16_t>(s + 4) != 1)
     return err = "not an edit stream", PCC_E_INVALID_ARG;
   const int m = s[6], fl = s[7];
@@ -257,7 +257,8 @@ pcc_status decode_stream(const uint8_t *s, size_t len, int64_t n, const float *r
   if (stored != len - kHeader || !(m == 8 || m == 16 || m == 32) || !(symbits == 8 || symbits == 16) ||
       nf > (uint64_t)n)
     return err = "corrupt stream header", PCC_E_INVALID_ARG;
-  std::vector<uint8_t> pay(raw);
+  std::vector<uint8_t> &pay = out.payload;
+  pay.assign(raw, 0);
   if (fl & 1) {
     if (!zstd_available()) return err = "stream needs libzstd.so.1", PCC_E_UNSUPPORTED;
     if (!zstd_decompress(s + kHeader, stored, pay.data(), raw)) return err = "ZSTD frame is corrupt", PCC_E_INVALID_ARG;
@@ -269,7 +270,8 @@ pcc_status decode_stream(const uint8_t *s, size_t len, int64_t n, const float *r
   if (raw < nb) return err = "payload too short", PCC_E_INVALID_ARG;
   const int per = m == 32 ? 2 : 1;
   const size_t nsym = (size_t)nf * 3 * per;
-  std::vector<uint32_t> sym(nsym);
+  std::vector<uint32_t> &sym = out.sym;
+  sym.assign(nsym, 0);
   const uint8_t *p = pay.data() + nb, *end = pay.data() + raw;
   if (nsym && (fl & 2)) {
     if (end - p < 4) return err = "payload too short", PCC_E_INVALID_ARG;
@@ -323,6 +325,30 @@ pcc_status decode_stream(const uint8_t *s, size_t len, int64_t n, const float *r
       sym[t] = v;
     }
   }
+  out.n = n;
+  out.nflagged = nf;
+  out.per = per;
+  out.step = step;
+  out.offset = offset;
+  out.flag_bytes = nb;
+  // the flag count must match the header
+  uint64_t cnt = 0;
+  for (size_t b = 0; b < nb; ++b) cnt += (uint64_t)__builtin_popcount(pay[b]);
+  if (n % 8 && nb) cnt -= (uint64_t)__builtin_popcount(pay[nb - 1] >> (n % 8));
+  if (cnt != nf) return err = "flag count differs from the header", PCC_E_INVALID_ARG;
+  return PCC_OK;
+}
+
+pcc_status decode_stream(const uint8_t *s, size_t len, int64_t n, const float *rx, const float *ry,
+                         const float *rz, float *ox, float *oy, float *oz, std::string &err) {
+  ParsedStream ps;
+  const pcc_status st = parse_stream(s, len, n, ps, err);
+  if (st != PCC_OK) return st;
+  const std::vector<uint8_t> &pay = ps.payload;
+  const std::vector<uint32_t> &sym = ps.sym;
+  const uint64_t nf = ps.nflagged;
+  const int per = ps.per;
+  const double step = ps.step, offset = ps.offset;
   const float *rin[3] = {rx, ry, rz};
   float *rout[3] = {ox, oy, oz};
   for (int a = 0; a < 3; ++a)
@@ -332,7 +358,6 @@ pcc_status decode_stream(const uint8_t *s, size_t len, int64_t n, const float *r
   ids.reserve(nf);
   for (int64_t k = 0; k < n; ++k)
     if ((pay[k >> 3] >> (k & 7)) & 1) ids.push_back(k);
-  if (ids.size() != nf) return err = "flag count differs from the header", PCC_E_INVALID_ARG;
   for (int a = 0; a < 3; ++a)
     for (size_t r = 0; r < ids.size(); ++r) {
       const size_t base = ((size_t)a * nf + r) * per;

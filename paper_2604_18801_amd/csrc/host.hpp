@@ -87,6 +87,23 @@ void assemble_stream(int64_t n, int m_bits, int64_t nflagged, double qstep, doub
                      const uint8_t *flags, size_t nflag_bytes, const HuffTable *ht,
                      const uint32_t *words, uint64_t nbits, std::vector<uint8_t> &out,
                      size_t *payload_raw);
+// a stream's flags (first flag_bytes bytes of payload, bit k of byte k/8)
+// and its symbols (planes x, y, z over the flagged particles in increasing
+// index; m = 32 codes are a low then a high 16-bit symbol)
+struct ParsedStream {
+  int64_t n = 0;
+  uint64_t nflagged = 0;
+  int per = 1;
+  double step = 0.0, offset = 0.0;
+  size_t flag_bytes = 0;
+  std::vector<uint8_t> payload;
+  std::vector<uint32_t> sym;
+};
+pcc_status parse_stream(const uint8_t *stream, size_t len, int64_t n, ParsedStream &out,
+                        std::string &err);
+// applies a parsed stream to a device reconstruction (decode.hip)
+void apply_edits_device(const ParsedStream &ps, const float *const rin[3], float *const rout[3],
+                        Arena &ar, hipStream_t s);
 pcc_status decode_stream(const uint8_t *stream, size_t len, int64_t n, const float *rx,
                          const float *ry, const float *rz, float *ox, float *oy, float *oz,
                          std::string &err);
