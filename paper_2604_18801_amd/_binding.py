@@ -88,6 +88,13 @@ def lib() -> C.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError("libpcc.so is not built (run __graft_entry__.build())")
+        # PyTorch ships its own HIP runtime under the same soname as the
+        # system's; loading torch first makes libpcc.so bind to that one, so
+        # the process has a single HIP runtime whatever the import order
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         L.pcc_version.restype = C.c_int
         L.pcc_status_string.restype = C.c_char_p

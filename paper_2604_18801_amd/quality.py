@@ -7,7 +7,7 @@ with those of the original positions.  Cap 0 is the raw reconstruction
 (no correction); cap "full" runs to convergence.
 
     python -m paper_2604_18801_amd.quality --workload cosmo128 --modes hf,sc \\
-        --caps 0,1,3,10,30,100,full
+        --caps 0,1,3,10,30,100,1000,full
 
 prints one JSON line per (mode, cap).
 """
@@ -30,18 +30,18 @@ def _volume(w) -> float:
 
 def study(ctx, w, modes=("hf",), caps=(0, 1, 3, 10, 30, 100, None), bins=50, min_members=20,
           **opts):
-    """Rows of metrics for every (mode, cap); cap None = to convergence."""
+    """Yields a row of metrics for every (mode, cap) as it is measured;
+    cap None = to convergence (or the library's safety cap)."""
     import torch
     o = torch.from_numpy(np.ascontiguousarray(w.orig)).cuda()
     r = torch.from_numpy(np.ascontiguousarray(w.recon)).cuda()
     vol = _volume(w)
     lab0 = ctx.fof_labels(o, w.b, w.box).cpu().numpy()
-    rows = []
     if 0 in caps:
         lab = ctx.fof_labels(r, w.b, w.box).cpu().numpy()
         row = {"mode": "none", "cap": 0, "iters": 0, "status": None}
         row.update(metrics.all_metrics(lab0, lab, vol, bins, min_members))
-        rows.append(row)
+        yield row
     for mode in modes:
         for cap in caps:
             if cap == 0:
@@ -63,8 +63,7 @@ def study(ctx, w, modes=("hf",), caps=(0, 1, 3, 10, 30, 100, None), bins=50, min
                    "n_active": st["n_active"], "stream_bytes": len(stream),
                    "ms": round(1e3 * dt, 2), "box_violations": box_viol}
             row.update(metrics.all_metrics(lab0, lab, vol, bins, min_members))
-            rows.append(row)
-    return rows
+            yield row
 
 
 def _workload(name):
@@ -85,7 +84,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--workload", default="cosmo128")
     ap.add_argument("--modes", default="hf,sc,vp")
-    ap.add_argument("--caps", default="0,1,3,10,30,100,full")
+    ap.add_argument("--caps", default="0,1,3,10,30,100,300,1000",
+                    help="comma-separated caps; 0 = raw reconstruction, full = no cap")
     ap.add_argument("--bins", type=int, default=50)
     ap.add_argument("--min-members", type=int, default=20)
     ap.add_argument("--optimizer", default="adam", choices=("adam", "sgd"))

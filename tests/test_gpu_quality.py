@@ -44,7 +44,7 @@ def test_quality_study_rows(ctx):
     from paper_2604_18801_amd import quality
     w = synth.cosmology(32, seed=23, xi=0.05)
     print("case quality study cosmology32", flush=True)
-    rows = quality.study(ctx, w, modes=("hf",), caps=(0, 1, None))
+    rows = list(quality.study(ctx, w, modes=("hf",), caps=(0, 1, None)))
     raw, capped, full = rows
     assert raw["mode"] == "none" and raw["membership_errors"] > 0 and raw["ari"] < 1.0
     assert full["status"] == 0 and full["membership_errors"] == 0
