@@ -64,6 +64,7 @@ class _Result(C.Structure):
                 ("labels", C.POINTER(C.c_int32)), ("safe_labels", C.POINTER(C.c_int32)),
                 ("n_a", C.c_int64), ("a_i", C.POINTER(C.c_uint32)),
                 ("a_j", C.POINTER(C.c_uint32)), ("a_type", C.POINTER(C.c_uint8)),
+                ("a_thr", C.POINTER(C.c_uint8)),
                 ("n_e", C.c_int64), ("e_ids", C.POINTER(C.c_uint32)),
                 ("p", C.POINTER(C.c_double)), ("loss_hist", C.POINTER(C.c_double)),
                 ("viol_hist", C.POINTER(C.c_int64)), ("stream", C.POINTER(C.c_uint8)),
@@ -99,6 +100,10 @@ def _load():
         lib.orc_select.restype = C.c_int64
         lib.orc_correct.argtypes = [C.c_int64, _F3, _F3, C.POINTER(_Params), C.POINTER(_Result)]
         lib.orc_correct.restype = C.c_int
+        lib.orc_correct_multi.argtypes = [C.c_int64, _F3, _F3, C.POINTER(_Params),
+                                          C.POINTER(C.c_double), C.c_int32,
+                                          C.POINTER(C.c_int32), C.POINTER(_Result)]
+        lib.orc_correct_multi.restype = C.c_int
         lib.orc_result_free.argtypes = [C.POINTER(_Result)]
         lib.orc_decode.argtypes = [C.POINTER(C.c_uint8), C.c_int64, C.c_int64, _F3, _F3]
         lib.orc_decode.restype = C.c_int
@@ -228,6 +233,7 @@ class OracleResult:
     a_i: np.ndarray
     a_j: np.ndarray
     a_type: np.ndarray
+    a_thr: np.ndarray       # threshold index of each active pair
     e_ids: np.ndarray
     p: np.ndarray           # (3, N) float64
     loss_hist: np.ndarray
@@ -242,13 +248,24 @@ def _arr(ptr, n, dtype):
 
 
 def correct(orig, recon, b, xi, mode=MODE_HF, box=None, **kw) -> OracleResult:
+    """The correction at one linking length b, or at several (b a sequence:
+    the union of every threshold's constraints); with several, the result's
+    labels_all holds the FoF labels at each b."""
     lib = _load()
     orig, optr = _soa(orig)
     recon, rptr = _soa(recon)
     n = orig.shape[1]
-    p = _params(b, xi, mode=mode, box=box, **kw)
+    multi = isinstance(b, (list, tuple, np.ndarray))
+    p = _params(b[0] if multi else b, xi, mode=mode, box=box, **kw)
     r = _Result()
-    st = lib.orc_correct(n, optr, rptr, C.byref(p), C.byref(r))
+    labels_all = None
+    if multi:
+        bl = (C.c_double * len(b))(*[float(v) for v in b])
+        labels_all = np.zeros((len(b), max(n, 1)), dtype=np.int32)
+        st = lib.orc_correct_multi(n, optr, rptr, C.byref(p), bl, len(b),
+                                   labels_all.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(r))
+    else:
+        st = lib.orc_correct(n, optr, rptr, C.byref(p), C.byref(r))
     try:
         if st < 0:
             raise ValueError("oracle rejected the input: status %d" % st)
@@ -259,13 +276,16 @@ def correct(orig, recon, b, xi, mode=MODE_HF, box=None, **kw) -> OracleResult:
             status=r.status, iters=r.iters, stats=stats,
             labels=_arr(r.labels, n, np.int32), safe_labels=_arr(r.safe_labels, n, np.int32),
             a_i=_arr(r.a_i, r.n_a, np.uint32), a_j=_arr(r.a_j, r.n_a, np.uint32),
-            a_type=_arr(r.a_type, r.n_a, np.uint8), e_ids=_arr(r.e_ids, r.n_e, np.uint32),
+            a_type=_arr(r.a_type, r.n_a, np.uint8), a_thr=_arr(r.a_thr, r.n_a, np.uint8),
+            e_ids=_arr(r.e_ids, r.n_e, np.uint32),
             p=_arr(r.p, 3 * n, np.float64).reshape(3, n),
             loss_hist=_arr(r.loss_hist, r.iters + 1, np.float64),
             viol_hist=_arr(r.viol_hist, r.iters + 1, np.int64),
             stream=bytes(_arr(r.stream, r.stream_len, np.uint8).tobytes()))
     finally:
         lib.orc_result_free(C.byref(r))
+    if multi:
+        res.labels_all = labels_all[:, :n]
     return res
 
 

@@ -433,13 +433,14 @@ typedef struct {
  * here takes the direction of the original positions.
  */
 static orc_eval evaluate(int64_t na, const uint32_t *a_i, const uint32_t *a_j,
-                         const uint8_t *a_type, const int64_t *eidx,
+                         const uint8_t *a_type, const uint8_t *a_thr, const int64_t *eidx,
                          double *const q[3], double *const g[3], int64_t ne,
                          const float *const xyz[3], const double box[3],
-                         const orc_consts *c) {
+                         const orc_consts *cs) {
   orc_eval ev = {0.0, 0};
   for (int a = 0; a < 3; a++) memset(g[a], 0, sizeof(double) * (size_t)ne);
   for (int64_t k = 0; k < na; k++) {
+    const orc_consts *c = cs + a_thr[k]; /* the pair's own threshold */
     int64_t ei = eidx[a_i[k]], ej = eidx[a_j[k]];
     double dv[3];
     for (int a = 0; a < 3; a++) dv[a] = axis_diff(q[a][ei] - q[a][ej], box[a]);
@@ -494,10 +495,10 @@ static orc_eval evaluate(int64_t na, const uint32_t *a_i, const uint32_t *a_j,
  * Returns the number of steps; q holds the final coordinates.
  */
 static int64_t pgd(int64_t na, const uint32_t *a_i, const uint32_t *a_j,
-                   const uint8_t *a_type, int64_t ne, const uint32_t *e_ids,
-                   int64_t n, const float *const xyz[3], const double box[3],
-                   const orc_consts *c, const orc_params *p, double *const q[3],
-                   orc_result *r) {
+                   const uint8_t *a_type, const uint8_t *a_thr, int64_t ne,
+                   const uint32_t *e_ids, int64_t n, const float *const xyz[3],
+                   const double box[3], const orc_consts *c, const orc_params *p,
+                   double *const q[3], orc_result *r) {
   int64_t *eidx = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)(n ? n : 1));
   for (int64_t k = 0; k < n; k++) eidx[k] = -1;
   for (int64_t e = 0; e < ne; e++) eidx[e_ids[e]] = e;
@@ -520,7 +521,7 @@ static int64_t pgd(int64_t na, const uint32_t *a_i, const uint32_t *a_j,
   r->viol_hist = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)cap);
   int64_t t = 0;
   for (;;) {
-    orc_eval ev = evaluate(na, a_i, a_j, a_type, eidx, q, g, ne, xyz, box, c);
+    orc_eval ev = evaluate(na, a_i, a_j, a_type, a_thr, eidx, q, g, ne, xyz, box, c);
     if (t + 1 > cap) {
       cap *= 2;
       r->loss_hist = (double *)realloc(r->loss_hist, sizeof(double) * (size_t)cap);
@@ -992,15 +993,45 @@ int orc_decode(const uint8_t *stream, int64_t len, int64_t n,
 /* ------------------------------------------------------------------------ */
 /* the whole correction                                                     */
 /* ------------------------------------------------------------------------ */
-int orc_correct(int64_t n, const float *const xyz[3], const float *const rec[3],
-                const orc_params *p, orc_result *r) {
+/* union of the per-threshold active lists, ordered by (i, j, threshold) */
+typedef struct {
+  uint32_t i, j;
+  uint8_t type, thr;
+} orc_tagged;
+
+static int cmp_tagged(const void *a, const void *b) {
+  const orc_tagged *x = (const orc_tagged *)a, *y = (const orc_tagged *)b;
+  if (x->i != y->i) return x->i < y->i ? -1 : 1;
+  if (x->j != y->j) return x->j < y->j ? -1 : 1;
+  return (int)x->thr - (int)y->thr;
+}
+
+/*
+ * The correction for one or more linking lengths b_list[0..nb).  Every
+ * threshold's constraints are selected exactly as for a single one (its own
+ * pair classes, safe components, halos and forest); the active list is their
+ * union, each pair tagged with its threshold (a pair selected for two
+ * thresholds is two constraints), and the tightened loss sums every
+ * constraint with its own b -+ delta_t.  The margins (delta_q, xi', delta_t)
+ * depend on xi, m and the coordinates only, so they are shared.  labels_all,
+ * if not NULL, receives the FoF labels at every b ([nb][n]); r->labels and
+ * r->safe_labels are those of b_list[0].
+ */
+static int correct_impl(int64_t n, const float *const xyz[3], const float *const rec[3],
+                        const orc_params *p, const double *b_list, int nb,
+                        int32_t *labels_all, orc_result *r) {
   memset(r, 0, sizeof(*r));
-  if (n < 0 || !(p->b > 0.0) || !(p->xi >= 0.0) ||
+  if (n < 0 || nb < 1 || nb > ORC_MAX_THRESHOLDS || !(p->xi >= 0.0) ||
       !(p->m_bits == 8 || p->m_bits == 16 || p->m_bits == 32))
     return r->status = ORC_E_INVALID;
+  double bmax = 0.0;
+  for (int k = 0; k < nb; k++) {
+    if (!(b_list[k] > 0.0)) return r->status = ORC_E_INVALID;
+    if (b_list[k] > bmax) bmax = b_list[k];
+  }
   for (int a = 0; a < 3; a++) {
     if (!(p->box[a] >= 0.0)) return r->status = ORC_E_INVALID;
-    if (p->box[a] > 0.0 && !(p->box[a] > 2.0 * (p->b + 2.0 * sqrt(3.0) * p->xi)))
+    if (p->box[a] > 0.0 && !(p->box[a] > 2.0 * (bmax + 2.0 * sqrt(3.0) * p->xi)))
       return r->status = ORC_E_INVALID;
   }
   for (int a = 0; a < 3; a++)
@@ -1010,26 +1041,68 @@ int orc_correct(int64_t n, const float *const xyz[3], const float *const rec[3],
       if (fabs((double)rec[a][k] - (double)xyz[a][k]) > p->xi)
         return r->status = ORC_E_INPUT_BOUND;
     }
-  orc_consts c;
-  orc_constants(p, orc_max_abs(n, xyz, rec), &c);
-
-  orc_pair *pairs = NULL;
-  int64_t np = orc_pairs(n, xyz, p->box, c.rv2, &pairs);
-  r->n_pairs = np;
-  for (int64_t k = 0; k < np; k++) {
-    int cls = orc_classify(pairs[k].d2, &c);
-    r->n_safe += cls == ORC_SAFE;
-    r->n_pb += cls == ORC_PB;
-    r->n_pc += cls == ORC_PC;
+  const double maxabs = orc_max_abs(n, xyz, rec);
+  orc_consts cs[ORC_MAX_THRESHOLDS];
+  orc_tagged *all = NULL;
+  int64_t n_all = 0;
+  int32_t *lab = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+  int32_t *safe = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+  for (int t = 0; t < nb; t++) {
+    orc_params pt = *p;
+    pt.b = b_list[t];
+    orc_constants(&pt, maxabs, &cs[t]);
+    orc_pair *pairs = NULL;
+    int64_t np = orc_pairs(n, xyz, p->box, cs[t].rv2, &pairs);
+    if (t == 0) {
+      r->n_pairs = np;
+      for (int64_t k = 0; k < np; k++) {
+        int cls = orc_classify(pairs[k].d2, &cs[0]);
+        r->n_safe += cls == ORC_SAFE;
+        r->n_pb += cls == ORC_PB;
+        r->n_pc += cls == ORC_PC;
+      }
+    }
+    orc_components(n, pairs, np, &cs[t], 1, lab);
+    orc_components(n, pairs, np, &cs[t], 0, safe);
+    if (labels_all) memcpy(labels_all + (size_t)t * (size_t)n, lab, sizeof(int32_t) * (size_t)n);
+    if (t == 0) {
+      r->labels = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+      r->safe_labels = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+      memcpy(r->labels, lab, sizeof(int32_t) * (size_t)n);
+      memcpy(r->safe_labels, safe, sizeof(int32_t) * (size_t)n);
+    }
+    uint32_t *ai = NULL, *aj = NULL;
+    uint8_t *at = NULL;
+    int64_t na = orc_select(p->mode, n, pairs, np, &cs[t], safe, lab, rec, p->box, &ai, &aj, &at);
+    free(pairs);
+    all = (orc_tagged *)realloc(all, sizeof(orc_tagged) * (size_t)(n_all + na + 1));
+    for (int64_t k = 0; k < na; k++) {
+      all[n_all + k].i = ai[k];
+      all[n_all + k].j = aj[k];
+      all[n_all + k].type = at[k];
+      all[n_all + k].thr = (uint8_t)t;
+    }
+    n_all += na;
+    free(ai);
+    free(aj);
+    free(at);
   }
-  r->labels = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(n ? n : 1));
-  r->safe_labels = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(n ? n : 1));
-  orc_components(n, pairs, np, &c, 1, r->labels);
-  orc_components(n, pairs, np, &c, 0, r->safe_labels);
-  r->n_a = orc_select(p->mode, n, pairs, np, &c, r->safe_labels, r->labels, rec,
-                      p->box, &r->a_i, &r->a_j, &r->a_type);
+  free(lab);
+  free(safe);
+  qsort(all, (size_t)n_all, sizeof(orc_tagged), cmp_tagged);
+  r->n_a = n_all;
+  r->a_i = (uint32_t *)xmalloc(sizeof(uint32_t) * (size_t)(n_all ? n_all : 1));
+  r->a_j = (uint32_t *)xmalloc(sizeof(uint32_t) * (size_t)(n_all ? n_all : 1));
+  r->a_type = (uint8_t *)xmalloc((size_t)(n_all ? n_all : 1));
+  r->a_thr = (uint8_t *)xmalloc((size_t)(n_all ? n_all : 1));
+  for (int64_t k = 0; k < n_all; k++) {
+    r->a_i[k] = all[k].i;
+    r->a_j[k] = all[k].j;
+    r->a_type[k] = all[k].type;
+    r->a_thr[k] = all[k].thr;
+  }
+  free(all);
   r->n_active = r->n_a;
-  free(pairs);
 
   /* E = endpoints(A), ascending */
   uint8_t *is_e = (uint8_t *)xcalloc((size_t)(n ? n : 1), 1);
@@ -1048,8 +1121,8 @@ int orc_correct(int64_t n, const float *const xyz[3], const float *const rec[3],
     q[a] = (double *)xmalloc(sizeof(double) * (size_t)(r->n_e ? r->n_e : 1));
     for (int64_t e = 0; e < r->n_e; e++) q[a][e] = (double)rec[a][r->e_ids[e]];
   }
-  r->iters = pgd(r->n_a, r->a_i, r->a_j, r->a_type, r->n_e, r->e_ids, n, xyz,
-                 p->box, &c, p, q, r);
+  r->iters = pgd(r->n_a, r->a_i, r->a_j, r->a_type, r->a_thr, r->n_e, r->e_ids, n, xyz,
+                 p->box, cs, p, q, r);
   r->p = (double *)xmalloc(sizeof(double) * (size_t)(3 * n + 1));
   double *pp[3] = {r->p, r->p + n, r->p + 2 * n};
   for (int a = 0; a < 3; a++) {
@@ -1057,8 +1130,19 @@ int orc_correct(int64_t n, const float *const xyz[3], const float *const rec[3],
     for (int64_t e = 0; e < r->n_e; e++) pp[a][r->e_ids[e]] = q[a][e];
     free(q[a]);
   }
-  r->stream_len = encode(n, rec, pp, p, &c, &r->stream, &r->n_flagged);
+  r->stream_len = encode(n, rec, pp, p, &cs[0], &r->stream, &r->n_flagged);
   return r->status;
+}
+
+int orc_correct(int64_t n, const float *const xyz[3], const float *const rec[3],
+                const orc_params *p, orc_result *r) {
+  return correct_impl(n, xyz, rec, p, &p->b, 1, NULL, r);
+}
+
+int orc_correct_multi(int64_t n, const float *const xyz[3], const float *const rec[3],
+                      const orc_params *p, const double *b_list, int32_t nb,
+                      int32_t *labels_all, orc_result *r) {
+  return correct_impl(n, xyz, rec, p, b_list, nb, labels_all, r);
 }
 
 void orc_result_free(orc_result *r) {
@@ -1067,6 +1151,7 @@ void orc_result_free(orc_result *r) {
   free(r->a_i);
   free(r->a_j);
   free(r->a_type);
+  free(r->a_thr);
   free(r->e_ids);
   free(r->p);
   free(r->loss_hist);

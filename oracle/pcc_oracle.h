@@ -47,6 +47,8 @@ enum { ORC_MARGIN_SAFE = 0, ORC_MARGIN_PAPER = 1 };
 enum { ORC_NONE = 0, ORC_SAFE = 1, ORC_PB = 2, ORC_PC = 3 };
 /* status */
 enum { ORC_OK = 0, ORC_NOT_CONVERGED = 1, ORC_E_INVALID = -1, ORC_E_INPUT_BOUND = -5 };
+/* linking lengths of one multi-threshold correction, at most */
+#define ORC_MAX_THRESHOLDS 8
 
 typedef struct {
   double b;            /* linking length */
@@ -88,8 +90,9 @@ typedef struct {
   int32_t *labels;                /* [n] FoF labels (minimum member index) */
   int32_t *safe_labels;           /* [n] safe-component labels */
   int64_t n_a;
-  uint32_t *a_i, *a_j;            /* active pairs, i < j, sorted by (i, j) */
+  uint32_t *a_i, *a_j;            /* active pairs, i < j, sorted by (i, j, threshold) */
   uint8_t *a_type;                /* ORC_PB or ORC_PC */
+  uint8_t *a_thr;                 /* threshold index of each active pair */
   int64_t n_e;
   uint32_t *e_ids;                /* editable particles, ascending */
   double *p;                      /* [3*n] planar x|y|z, final float64 coords */
@@ -127,6 +130,16 @@ int64_t orc_select(int mode, int64_t n, const orc_pair *pairs, int64_t np,
 int orc_correct(int64_t n, const float *const xyz[3], const float *const rec[3],
                 const orc_params *p, orc_result *r);
 void orc_result_free(orc_result *r);
+
+/* The correction for several linking lengths at once (Sec. 1 notes the
+   extension: the union of the selected pair sets of every threshold).
+   b_list[0..nb) replaces p->b (nb <= ORC_MAX_THRESHOLDS); every threshold's
+   constraints are selected as in orc_correct and each keeps its own
+   b -+ delta_t in the loss; the active list is sorted by (i, j, threshold).
+   labels_all, if not NULL, receives the FoF labels at every b ([nb][n]). */
+int orc_correct_multi(int64_t n, const float *const xyz[3], const float *const rec[3],
+                      const orc_params *p, const double *b_list, int32_t nb,
+                      int32_t *labels_all, orc_result *r);
 
 /* Decode an edit stream and apply it to the reconstruction (Sec. 3.3). */
 int orc_decode(const uint8_t *stream, int64_t len, int64_t n,
