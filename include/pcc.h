@@ -194,6 +194,27 @@ pcc_status pcc_correct(pcc_context *ctx, const pcc_particles *orig,
                        pcc_outputs *out, pcc_stats *stats, void *hip_stream);
 
 /*
+ * One snapshot corrected for several linking lengths at once (the extension
+ * the conclusion names, Sec. 5 under Limitations: the constraints of every
+ * threshold are selected as in pcc_correct, with that threshold's
+ * b -+ delta_t, and the loss of Eq. 3 sums over their union; a pair selected
+ * by two thresholds counts twice).
+ * b_list[0 .. nb) (1 <= nb <= PCC_MAX_THRESHOLDS, each finite and > 0)
+ * replaces params->b; every other parameter applies to all thresholds.
+ * out->labels, if not NULL, receives the FoF labels of the originals at every
+ * linking length, [nb][n] row-major, in the memspace of orig; the stream,
+ * debug_xyz and stats are those of the one corrected snapshot (the pair
+ * counts in stats are those at b_list[0]).  The PGD row of a particle sums
+ * its constraints in increasing partner index, then threshold index.
+ * Returns as pcc_correct.
+ */
+#define PCC_MAX_THRESHOLDS 8
+pcc_status pcc_correct_multi(pcc_context *ctx, const pcc_particles *orig,
+                             const pcc_particles *recon, const pcc_params *params,
+                             const double *b_list, int32_t nb, pcc_outputs *out,
+                             pcc_stats *stats, void *hip_stream);
+
+/*
  * Many independent snapshots in one pass: every stage is one launch over all
  * jobs, the PGD iterations of all jobs run together and a job that has
  * converged is masked out.  Each job's results equal those of pcc_correct on
@@ -239,6 +260,9 @@ pcc_status pcc_fof_labels(pcc_context *ctx, const pcc_particles *pts, double b,
  *                                              3 = potentially created
  *   PCC_DBG_SAFE_LABELS     int32  [n]         safe-component labels
  *   PCC_DBG_EDITABLE        uint32 [n_editable] editable particles, unsorted
+ *   PCC_DBG_ACTIVE_THR      uint8  [n_active]  linking-length index of each
+ *                                              active pair (0 outside
+ *                                              pcc_correct_multi)
  * *count receives the element count; nothing is copied if cap < count.
  */
 enum {
@@ -246,7 +270,8 @@ enum {
   PCC_DBG_ACTIVE_J = 2,
   PCC_DBG_ACTIVE_TYPE = 3,
   PCC_DBG_SAFE_LABELS = 4,
-  PCC_DBG_EDITABLE = 5
+  PCC_DBG_EDITABLE = 5,
+  PCC_DBG_ACTIVE_THR = 6
 };
 pcc_status pcc_debug_fetch(pcc_context *ctx, int32_t job, int32_t what, void *host_dst,
                            int64_t cap, int64_t *count);

@@ -131,8 +131,9 @@ int orc_correct(int64_t n, const float *const xyz[3], const float *const rec[3],
                 const orc_params *p, orc_result *r);
 void orc_result_free(orc_result *r);
 
-/* The correction for several linking lengths at once (Sec. 1 notes the
-   extension: the union of the selected pair sets of every threshold).
+/* The correction for several linking lengths at once (the extension the
+   conclusion, Sec. 5 under Limitations, notes: the union of the selected
+   pair sets of every threshold).
    b_list[0..nb) replaces p->b (nb <= ORC_MAX_THRESHOLDS); every threshold's
    constraints are selected as in orc_correct and each keeps its own
    b -+ delta_t in the loss; the active list is sorted by (i, j, threshold).

@@ -109,6 +109,9 @@ def lib() -> C.CDLL:
         L.pcc_correct.argtypes = [C.c_void_p, C.POINTER(Particles), C.POINTER(Particles),
                                   C.POINTER(Params), C.POINTER(Outputs), C.POINTER(Stats),
                                   C.c_void_p]
+        L.pcc_correct_multi.argtypes = [C.c_void_p, C.POINTER(Particles), C.POINTER(Particles),
+                                        C.POINTER(Params), C.POINTER(C.c_double), C.c_int32,
+                                        C.POINTER(Outputs), C.POINTER(Stats), C.c_void_p]
         L.pcc_correct_batch.argtypes = [C.c_void_p, C.POINTER(Job), C.c_int32,
                                         C.POINTER(JobResult), C.c_void_p]
         L.pcc_decode.argtypes = [C.c_void_p, C.c_size_t, C.POINTER(Particles), C.c_void_p,
@@ -129,7 +132,7 @@ def lib() -> C.CDLL:
         L.pcc_server_drain.argtypes = [C.c_void_p]
         L.pcc_server_destroy.argtypes = [C.c_void_p]
         for name in ("pcc_context_create", "pcc_context_destroy", "pcc_correct",
-                     "pcc_correct_batch", "pcc_decode", "pcc_fof_labels", "pcc_debug_fetch",
+                     "pcc_correct_multi", "pcc_correct_batch", "pcc_decode", "pcc_fof_labels", "pcc_debug_fetch",
                      "pcc_context_set", "pcc_decode_device", "pcc_server_create", "pcc_server_submit",
                      "pcc_server_poll", "pcc_server_wait", "pcc_server_cancel",
                      "pcc_server_drain", "pcc_server_destroy"):
@@ -299,6 +302,47 @@ class Context:
             stats["debug_xyz"] = dbg[:, :n]
         return bytes(sbuf[: slen.value]), res_lab, stats
 
+    def correct_multi(self, orig, recon, b_list: Sequence[float], xi: float, mode="hf",
+                      box=None, labels=True, debug_xyz=False, **opts):
+        """One snapshot corrected for every linking length in b_list at once.
+        Returns (stream bytes, labels (len(b_list), N) or None, stats)."""
+        if not 1 <= len(b_list) <= 8:
+            raise ValueError("correct_multi takes 1 to 8 linking lengths")
+        po, ko = _view(orig)
+        pr, kr = _view(recon)
+        n, nb = po.n, len(b_list)
+        params = make_params(float(b_list[0]), xi, mode=mode, box=box, **opts)
+        cap = lib().pcc_stream_bound(n, C.byref(params))
+        sbuf = np.zeros(max(cap, 1), dtype=np.uint8)
+        slen = C.c_size_t(0)
+        lab = None
+        lab_ptr = None
+        if labels:
+            if po.memspace == MEM_DEVICE:
+                import torch
+                lab = torch.empty((nb, max(n, 1)), dtype=torch.int32, device=ko.device)
+                lab_ptr = lab.data_ptr()
+            else:
+                lab = np.zeros((nb, max(n, 1)), dtype=np.int32)
+                lab_ptr = lab.ctypes.data
+            if n == 0:
+                lab_ptr = None
+        dbg = np.zeros((3, max(n, 1)), dtype=np.float64) if debug_xyz else None
+        out = Outputs(lab_ptr, sbuf.ctypes.data, cap, C.pointer(slen),
+                      dbg.ctypes.data if dbg is not None else None)
+        bl = (C.c_double * max(nb, 1))(*[float(v) for v in b_list])
+        st = Stats()
+        status = lib().pcc_correct_multi(self._h, C.byref(po), C.byref(pr), C.byref(params), bl,
+                                         nb, C.byref(out), C.byref(st),
+                                         _stream_handle(po.memspace == MEM_DEVICE))
+        _check(status)
+        stats = stats_dict(st)
+        stats["status"] = status
+        if dbg is not None:
+            stats["debug_xyz"] = dbg[:, :n]
+        res_lab = lab[:, :n] if lab is not None else None
+        return bytes(sbuf[: slen.value]), res_lab, stats
+
     def correct_batch(self, jobs: Sequence[Dict]):
         """jobs: dicts with orig, recon, b, xi and optional mode, box, opts.
         Returns a list of (status, stream bytes, labels, stats)."""
@@ -345,8 +389,9 @@ class Context:
 
     def debug_fetch(self, job: int, what: str):
         code = {"active_i": 1, "active_j": 2, "active_type": 3, "safe_labels": 4,
-                "editable": 5}[what]
-        dtype = {1: np.uint32, 2: np.uint32, 3: np.uint8, 4: np.int32, 5: np.uint32}[code]
+                "editable": 5, "active_thr": 6}[what]
+        dtype = {1: np.uint32, 2: np.uint32, 3: np.uint8, 4: np.int32, 5: np.uint32,
+                 6: np.uint8}[code]
         cnt = C.c_int64(0)
         _check(lib().pcc_debug_fetch(self._h, int(job), code, None, 0, C.byref(cnt)))
         buf = np.zeros(max(cnt.value, 1), dtype=dtype)

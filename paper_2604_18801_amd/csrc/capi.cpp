@@ -1,5 +1,6 @@
 // C ABI of include/pcc.h: argument checks, context management, error
 // reporting; every entry point catches all exceptions at this boundary.
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -160,6 +161,45 @@ pcc_status pcc_correct(pcc_context *ctx, const pcc_particles *orig, const pcc_pa
   });
 }
 
+pcc_status pcc_correct_multi(pcc_context *ctx, const pcc_particles *orig,
+                             const pcc_particles *recon, const pcc_params *params,
+                             const double *b_list, int32_t nb, pcc_outputs *out, pcc_stats *stats,
+                             void *hip_stream) {
+  if (!ctx || !orig || !recon || !params || !out || !b_list)
+    return fail(PCC_E_INVALID_ARG, "NULL argument");
+  if (nb < 1 || nb > PCC_MAX_THRESHOLDS)
+    return fail(PCC_E_INVALID_ARG, "the number of linking lengths must be 1 .. 8");
+  for (int32_t k = 0; k < nb; ++k)
+    if (!(b_list[k] > 0.0) || !std::isfinite(b_list[k]))
+      return fail(PCC_E_INVALID_ARG, "every linking length must be finite and > 0");
+  return guarded([&]() -> pcc_status {
+    std::vector<pcc_job> jobs(nb);
+    for (int32_t k = 0; k < nb; ++k) {
+      pcc_job &j = jobs[k];
+      j.orig = *orig;
+      j.recon = *recon;
+      j.params = *params;
+      j.params.b = b_list[k];
+      std::memset(&j.out, 0, sizeof j.out);
+      if (out->labels) j.out.labels = out->labels + (size_t)k * (size_t)(orig->n > 0 ? orig->n : 0);
+    }
+    // job 0 carries the corrected particles: its stream and coordinates
+    jobs[0].out.stream = out->stream;
+    jobs[0].out.stream_cap = out->stream_cap;
+    jobs[0].out.stream_len = out->stream_len;
+    jobs[0].out.debug_xyz = out->debug_xyz;
+    std::vector<pcc_job_result> r(nb);
+    for (auto &x : r) std::memset(&x, 0, sizeof x);
+    pcc::run_batch(ctx->c, jobs.data(), nb, r.data(), pick(ctx, hip_stream), false, true);
+    pcc_status st = r[0].status;
+    for (int32_t k = 1; k < nb; ++k)
+      if (r[k].status < 0 && st >= 0) st = r[k].status;
+    if (stats) *stats = r[0].stats;
+    if (st < 0 && g_err.empty()) g_err = pcc_status_string(st);
+    return st;
+  });
+}
+
 pcc_status pcc_correct_batch(pcc_context *ctx, const pcc_job *jobs, int32_t njobs,
                              pcc_job_result *results, void *hip_stream) {
   if (!ctx || njobs < 0 || (njobs > 0 && (!jobs || !results)))
@@ -238,9 +278,10 @@ pcc_status pcc_fof_labels(pcc_context *ctx, const pcc_particles *pts, double b,
 // ---------------------------------------------------------------------------
 namespace pcc {
 namespace {
-__global__ void k_dbg_pairs(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t, size_t na,
-                            const float4 *pos, const int64_t *p_off, int njobs, int32_t *job,
-                            uint32_t *lo, uint32_t *hi, uint8_t *t) {
+__global__ void k_dbg_pairs(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t,
+                            const uint8_t *a_k, size_t na, const float4 *pos, const int64_t *p_off,
+                            int njobs, int32_t *job, uint32_t *lo, uint32_t *hi, uint8_t *t,
+                            uint8_t *k) {
   for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < na;
        p += (size_t)gridDim.x * blockDim.x) {
     const uint32_t i = __float_as_uint(pos[a_i[p]].w), j = __float_as_uint(pos[a_j[p]].w);
@@ -248,6 +289,7 @@ __global__ void k_dbg_pairs(const uint32_t *a_i, const uint32_t *a_j, const uint
     lo[p] = i < j ? i : j;
     hi[p] = i < j ? j : i;
     t[p] = a_t[p];
+    k[p] = a_k ? a_k[p] : 0;
   }
 }
 __global__ void k_dbg_safe(const uint32_t *root, const float4 *pos, size_t n, int32_t *lab_sorted_root) {
@@ -326,22 +368,25 @@ extern "C" pcc_status pcc_debug_fetch(pcc_context *ctx, int32_t job, int32_t wha
       if (host_dst && cap >= *count) std::memcpy(host_dst, sel.data(), sel.size() * 4);
       return PCC_OK;
     }
-    if (what == PCC_DBG_ACTIVE_I || what == PCC_DBG_ACTIVE_J || what == PCC_DBG_ACTIVE_TYPE) {
+    if (what == PCC_DBG_ACTIVE_I || what == PCC_DBG_ACTIVE_J || what == PCC_DBG_ACTIVE_TYPE ||
+        what == PCC_DBG_ACTIVE_THR) {
       const size_t na = L.na ? L.na : 1;
       int32_t *jb = scratch.get<int32_t>(na);
       uint32_t *lo = scratch.get<uint32_t>(na), *hi = scratch.get<uint32_t>(na);
-      uint8_t *t = scratch.get<uint8_t>(na);
+      uint8_t *t = scratch.get<uint8_t>(na), *tk = scratch.get<uint8_t>(na);
       if (L.na)
-        k_dbg_pairs<<<blocks_for(L.na, 256, 65536), 256, 0, s>>>(L.a_i, L.a_j, L.a_t, L.na, L.pos,
-                                                                 d_poff, L.njobs, jb, lo, hi, t);
+        k_dbg_pairs<<<blocks_for(L.na, 256, 65536), 256, 0, s>>>(L.a_i, L.a_j, L.a_t, L.a_k, L.na,
+                                                                 L.pos, d_poff, L.njobs, jb, lo,
+                                                                 hi, t, tk);
       std::vector<int32_t> hj(L.na);
       std::vector<uint32_t> hl(L.na), hh(L.na);
-      std::vector<uint8_t> ht(L.na);
+      std::vector<uint8_t> ht(L.na), hk(L.na);
       if (L.na) {
         PCC_HIP(hipMemcpyAsync(hj.data(), jb, L.na * 4, hipMemcpyDeviceToHost, s));
         PCC_HIP(hipMemcpyAsync(hl.data(), lo, L.na * 4, hipMemcpyDeviceToHost, s));
         PCC_HIP(hipMemcpyAsync(hh.data(), hi, L.na * 4, hipMemcpyDeviceToHost, s));
         PCC_HIP(hipMemcpyAsync(ht.data(), t, L.na, hipMemcpyDeviceToHost, s));
+        PCC_HIP(hipMemcpyAsync(hk.data(), tk, L.na, hipMemcpyDeviceToHost, s));
       }
       PCC_HIP(hipStreamSynchronize(s));
       int64_t c = 0;
@@ -354,6 +399,7 @@ extern "C" pcc_status pcc_debug_fetch(pcc_context *ctx, int32_t job, int32_t wha
         if (what == PCC_DBG_ACTIVE_I) ((uint32_t *)host_dst)[w] = hl[p];
         if (what == PCC_DBG_ACTIVE_J) ((uint32_t *)host_dst)[w] = hh[p];
         if (what == PCC_DBG_ACTIVE_TYPE) ((uint8_t *)host_dst)[w] = ht[p];
+        if (what == PCC_DBG_ACTIVE_THR) ((uint8_t *)host_dst)[w] = hk[p];
         ++w;
       }
       return PCC_OK;

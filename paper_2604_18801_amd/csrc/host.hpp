@@ -20,6 +20,7 @@ struct LastCall {
   size_t n = 0, na = 0, ne = 0;
   const uint32_t *a_i = nullptr, *a_j = nullptr;
   const uint8_t *a_t = nullptr;
+  const uint8_t *a_k = nullptr;    // threshold index per pair (multi-threshold calls)
   const uint32_t *safe_root = nullptr;
   const float4 *pos = nullptr;
   const uint32_t *e_list = nullptr;
@@ -67,8 +68,10 @@ const double2 *bc_table(Context &C, double beta1, double beta2, int64_t len);
 // message returned by pcc_last_error on the calling thread
 void set_last_error(const std::string &m);
 
+// multi: the jobs are one snapshot at several linking lengths, corrected
+// together into job 0's particles (job 0's stream; every job's labels)
 pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs, pcc_job_result *res,
-                     hipStream_t s, bool labels_only);
+                     hipStream_t s, bool labels_only, bool multi = false);
 
 // codec.cpp
 struct HuffTable {

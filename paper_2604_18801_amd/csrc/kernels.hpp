@@ -123,8 +123,14 @@ struct PgdBufs {
   unsigned long long *acc;  // [njobs][acc_slots][16]
   int acc_slots;            // power of two
 };
-void sort_pairs(uint32_t *a_i, uint32_t *a_j, uint8_t *a_t, size_t na, const float4 *pos,
-                int id_bits, Arena &ar, hipStream_t s);
+// a_k (threshold index per pair) may be NULL; when set it is the last key
+void sort_pairs(uint32_t *a_i, uint32_t *a_j, uint8_t *a_t, uint8_t *a_k, size_t na,
+                const float4 *pos, int id_bits, Arena &ar, hipStream_t s);
+// multi-threshold calls: pairs of job k > 0 move to job 0's particle with the
+// same job-local index; a_k[p] receives the job index
+void remap_thresholds(uint32_t *a_i, uint32_t *a_j, size_t na, const float4 *pos,
+                      const uint32_t *inv_perm, const int64_t *p_off, int njobs, uint8_t *a_k,
+                      hipStream_t s);
 void mark_editable(const uint32_t *a_i, const uint32_t *a_j, size_t na, size_t n, uint8_t *is_e,
                    uint32_t *eid, uint32_t *ne_dev, Arena &ar, hipStream_t s);
 void list_editable(const uint8_t *is_e, const uint32_t *eid, size_t n, uint32_t *e_list,
@@ -133,9 +139,10 @@ void list_editable(const uint8_t *is_e, const uint32_t *eid, size_t n, uint32_t 
 // e_list and eid are updated in place
 void order_rows(uint32_t *e_list, size_t ne, uint32_t *eid, const float4 *pos, const JobDev *jobs,
                 const int64_t *p_off, int njobs, Arena &ar, hipStream_t s);
-void build_csr(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t, size_t na,
-               const uint32_t *eid, uint32_t ne, uint32_t *row_ptr, uint32_t *col, Arena &ar,
-               hipStream_t s);
+// col entries: partner row | kColPc for created pairs | threshold << kColThrShift
+void build_csr(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t, const uint8_t *a_k,
+               size_t na, const uint32_t *eid, uint32_t ne, uint32_t *row_ptr, uint32_t *col,
+               Arena &ar, hipStream_t s);
 void launch_pgd_init(const uint32_t *e_list, size_t ne, const float4 *pos, const float4 *rec,
                      double4 *P0, float4 *xo, double *m, double *v, hipStream_t s);
 // worklist of the first step: every row; no row hot yet

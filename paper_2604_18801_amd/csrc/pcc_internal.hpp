@@ -31,6 +31,13 @@ void hip_fail(hipError_t e, const char *what, const char *file, int line);
   } while (0)
 
 // Per-job constants read by the kernels (one entry per job, device memory).
+// linking lengths of one multi-threshold correction, at most
+constexpr int kMaxThresholds = 8;
+// column word of an incidence: partner row | threshold index << 28 | pc bit
+constexpr uint32_t kColRow = 0x0fffffffu;
+constexpr int kColThrShift = 28;
+constexpr uint32_t kColPc = 0x80000000u;
+
 struct JobDev {
   int64_t p_off;        // first particle of the job in the global arrays
   int64_t n;            // particles
@@ -59,6 +66,12 @@ struct JobDev {
   // quantiser of the edits
   double qstep, qoffset;       // edit = code * qstep - qoffset
   double qmax;                 // 2^m - 1
+  // tightened bounds b_k -+ delta_t of every linking length of a
+  // multi-threshold correction (entry 0 = this job's own b); an incidence's
+  // threshold index sits in its column word
+  int32_t nthr;
+  double thr_bm[kMaxThresholds], thr_bp[kMaxThresholds];
+  double thr_bm2[kMaxThresholds], thr_bp2[kMaxThresholds];
 };
 
 // Mutable per-job state of the correction loop (device memory).

@@ -41,12 +41,14 @@ __global__ void k_e_list(const uint8_t *is_e, const uint32_t *eid, size_t n, uin
     if (is_e[k]) e_list[eid[k]] = (uint32_t)k;
 }
 
-__global__ void k_incid(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t, size_t na,
-                        const uint32_t *eid, uint32_t *keys, uint32_t *vals) {
+__global__ void k_incid(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t,
+                        const uint8_t *a_k, size_t na, const uint32_t *eid, uint32_t *keys,
+                        uint32_t *vals) {
   for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < na;
        p += (size_t)gridDim.x * blockDim.x) {
     const uint32_t ri = eid[a_i[p]], rj = eid[a_j[p]];
-    const uint32_t t = a_t[p] == 3 ? 0x80000000u : 0u;
+    const uint32_t t = (a_t[p] == 3 ? kColPc : 0u) |
+                       (a_k ? (uint32_t)a_k[p] << kColThrShift : 0u);
     keys[2 * p] = ri;
     vals[2 * p] = rj | t;
     keys[2 * p + 1] = rj;
@@ -84,37 +86,77 @@ __global__ void k_take_u32(const uint32_t *src, const uint32_t *idx, size_t m, u
        p += (size_t)gridDim.x * blockDim.x)
     dst[p] = src[idx[p]];
 }
+__global__ void k_take_u8_as_u32(const uint8_t *src, const uint32_t *idx, size_t m, uint32_t *dst) {
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < m;
+       p += (size_t)gridDim.x * blockDim.x)
+    dst[p] = src[idx[p]];
+}
 __global__ void k_take_pairs(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t,
-                             const uint32_t *idx, size_t na, uint32_t *b_i, uint32_t *b_j,
-                             uint8_t *b_t) {
+                             const uint8_t *a_k, const uint32_t *idx, size_t na, uint32_t *b_i,
+                             uint32_t *b_j, uint8_t *b_t, uint8_t *b_k) {
   for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < na;
        p += (size_t)gridDim.x * blockDim.x) {
     const uint32_t q = idx[p];
     b_i[p] = a_i[q];
     b_j[p] = a_j[q];
     b_t[p] = a_t[q];
+    if (a_k) b_k[p] = a_k[q];
   }
 }
 
-// Orders the active pairs by (smaller job-local index, larger one) with two
-// stable radix sorts.  The stable sort of their incidences by row that
-// follows then leaves every row in increasing partner index: the order in
-// which the gradient of each particle is summed.
-void sort_pairs(uint32_t *a_i, uint32_t *a_j, uint8_t *a_t, size_t na, const float4 *pos,
-                int id_bits, Arena &ar, hipStream_t s) {
+// Orders the active pairs by (smaller job-local index, larger one, threshold
+// index) with stable radix sorts, least significant key first.  The stable
+// sort of their incidences by row that follows then leaves every row in
+// increasing partner index (then threshold): the order in which the gradient
+// of each particle is summed.
+void sort_pairs(uint32_t *a_i, uint32_t *a_j, uint8_t *a_t, uint8_t *a_k, size_t na,
+                const float4 *pos, int id_bits, Arena &ar, hipStream_t s) {
   if (na < 2) return;
   uint32_t *lo = ar.get<uint32_t>(na), *hi = ar.get<uint32_t>(na), *idx = ar.get<uint32_t>(na);
+  uint32_t *key = ar.get<uint32_t>(na);
   const int nb = blocks_for(na, 256, 65536);
   k_pair_keys<<<nb, 256, 0, s>>>(a_i, a_j, na, pos, lo, hi, idx);
-  radix_sort_u32(hi, idx, na, id_bits, ar, s);
-  k_take_u32<<<nb, 256, 0, s>>>(lo, idx, na, hi);
-  radix_sort_u32(hi, idx, na, id_bits, ar, s);
+  if (a_k) {
+    k_take_u8_as_u32<<<nb, 256, 0, s>>>(a_k, idx, na, key);
+    radix_sort_u32(key, idx, na, 3, ar, s);
+  }
+  k_take_u32<<<nb, 256, 0, s>>>(hi, idx, na, key);
+  radix_sort_u32(key, idx, na, id_bits, ar, s);
+  k_take_u32<<<nb, 256, 0, s>>>(lo, idx, na, key);
+  radix_sort_u32(key, idx, na, id_bits, ar, s);
   uint32_t *b_i = ar.get<uint32_t>(na), *b_j = ar.get<uint32_t>(na);
-  uint8_t *b_t = ar.get<uint8_t>(na);
-  k_take_pairs<<<nb, 256, 0, s>>>(a_i, a_j, a_t, idx, na, b_i, b_j, b_t);
+  uint8_t *b_t = ar.get<uint8_t>(na), *b_k = a_k ? ar.get<uint8_t>(na) : nullptr;
+  k_take_pairs<<<nb, 256, 0, s>>>(a_i, a_j, a_t, a_k, idx, na, b_i, b_j, b_t, b_k);
   PCC_HIP(hipMemcpyAsync(a_i, b_i, na * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
   PCC_HIP(hipMemcpyAsync(a_j, b_j, na * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
   PCC_HIP(hipMemcpyAsync(a_t, b_t, na, hipMemcpyDeviceToDevice, s));
+  if (a_k) PCC_HIP(hipMemcpyAsync(a_k, b_k, na, hipMemcpyDeviceToDevice, s));
+}
+
+// Multi-threshold correction: the jobs of the call are the thresholds of one
+// snapshot.  Pairs selected for threshold k > 0 are moved into threshold 0's
+// particles (same original index) and tagged with k.
+__global__ void k_thr_remap(uint32_t *a_i, uint32_t *a_j, size_t na, const float4 *pos,
+                            const uint32_t *inv_perm, const int64_t *p_off, int njobs,
+                            uint8_t *a_k) {
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < na;
+       p += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t i = a_i[p], j = a_j[p];
+    const int k = job_of(p_off, njobs, (int64_t)i);
+    a_k[p] = (uint8_t)k;
+    if (k > 0) {
+      a_i[p] = inv_perm[p_off[0] + __float_as_uint(pos[i].w)];
+      a_j[p] = inv_perm[p_off[0] + __float_as_uint(pos[j].w)];
+    }
+  }
+}
+
+void remap_thresholds(uint32_t *a_i, uint32_t *a_j, size_t na, const float4 *pos,
+                      const uint32_t *inv_perm, const int64_t *p_off, int njobs, uint8_t *a_k,
+                      hipStream_t s) {
+  if (na)
+    k_thr_remap<<<blocks_for(na, 256, 65536), 256, 0, s>>>(a_i, a_j, na, pos, inv_perm, p_off,
+                                                           njobs, a_k);
 }
 
 void list_editable(const uint8_t *is_e, const uint32_t *eid, size_t n, uint32_t *e_list,
@@ -196,9 +238,10 @@ void order_rows(uint32_t *e_list, size_t ne, uint32_t *eid, const float4 *pos, c
   k_row_apply<<<nb, 256, 0, s>>>(old, order, ne, e_list, eid);
 }
 
-void build_csr(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t, size_t na,
-               const uint32_t *eid, uint32_t ne, uint32_t *row_ptr, uint32_t *col, Arena &ar,
-               hipStream_t s) {
+void build_csr(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t, const uint8_t *a_k,
+               size_t na, const uint32_t *eid, uint32_t ne, uint32_t *row_ptr, uint32_t *col,
+               Arena &ar, hipStream_t s) {
+  if (ne > kColRow) throw Error(-6, "more than 2^28 editable particles in one call");
   if (!na) {
     PCC_HIP(hipMemsetAsync(row_ptr, 0, sizeof(uint32_t) * ((size_t)ne + 1), s));
     return;
@@ -206,7 +249,7 @@ void build_csr(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t, siz
   const size_t m = 2 * na;
   if (m > 0xffffffffull) throw Error(-6, "more than 2^31 active pairs in one call");
   uint32_t *keys = ar.get<uint32_t>(m);
-  k_incid<<<blocks_for(na, 256, 65536), 256, 0, s>>>(a_i, a_j, a_t, na, eid, keys, col);
+  k_incid<<<blocks_for(na, 256, 65536), 256, 0, s>>>(a_i, a_j, a_t, a_k, na, eid, keys, col);
   radix_sort_u32(keys, col, m, bits_for(ne ? ne - 1 : 0), ar, s);
   k_row_ptr<<<blocks_for(m, 256, 65536), 256, 0, s>>>(keys, m, ne, row_ptr);
 }
@@ -270,26 +313,6 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-struct RowConst {
-  double L0, L1, L2, h0, h1, h2, bm, bp, bm2, bp2, scale;
-};
-
-__device__ inline RowConst row_const(const JobDev &J) {
-  RowConst c;
-  c.L0 = J.L[0];
-  c.L1 = J.L[1];
-  c.L2 = J.L[2];
-  c.h0 = J.hL[0];
-  c.h1 = J.hL[1];
-  c.h2 = J.hL[2];
-  c.bm = J.bm;
-  c.bp = J.bp;
-  c.bm2 = J.bm2;
-  c.bp2 = J.bp2;
-  c.scale = J.loss_scale;
-  return c;
 }
 
 constexpr int kPgdWaves = 4;
@@ -419,7 +442,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
     // two-deep pipeline: while chunk c is evaluated, the partner gather of
     // chunk c + 1 and the column entries of chunk c + 2 are in flight
     auto gather = [&](uint32_t col) {
-      const double *pp = reinterpret_cast<const double *>(Pc + (col & 0x7fffffffu));
+      const double *pp = reinterpret_cast<const double *>(Pc + (col & kColRow));
       return make_double3(pp[0], pp[1], pp[2]);
     };
     int r_nx = 0, r_nx2 = 0;
@@ -442,27 +465,37 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
       if (q + 64 < total) po_nx = gather(col_nx);
       if (q + 128 < total) locate(q + 128, r_nx2, col_nx2);
       if (q < total) {
-        const uint32_t o = col & 0x7fffffffu;
+        const uint32_t o = col & kColRow;
         const uint32_t er = s_e[w][r];
         const double dx = wrapd(s_px[w][r] - po.x, L0, h0);
         const double dy = wrapd(s_py[w][r] - po.y, L1, h1);
         const double dz = wrapd(s_pz[w][r] - po.z, L2, h2);
         const double d2 = (dx * dx + dy * dy) + dz * dz;
+        // thresholds of the constraint: the job's own, or those of its
+        // linking length when several are corrected at once
+        double cbm = bm, cbm2 = bm2, cbp = bp, cbp2 = bp2;
+        const uint32_t kk = (col >> kColThrShift) & 7u;
+        if (kk) {
+          cbm = J.thr_bm[kk];
+          cbm2 = J.thr_bm2[kk];
+          cbp = J.thr_bp[kk];
+          cbp2 = J.thr_bp2[kk];
+        }
         double h = 0.0;
-        if (!(col >> 31)) {
+        if (!(col & kColPc)) {
           // potentially broken: an original link pulled back inside b - delta_t
-          if (d2 > bm2) {
+          if (d2 > cbm2) {
             const double d = sqrt(d2);
-            h = d - bm;
+            h = d - cbm;
             tx = 2.0 * h * (dx / d);
             ty = 2.0 * h * (dy / d);
             tz = 2.0 * h * (dz / d);
             hit = true;
           }
-        } else if (d2 <= bp2) {
+        } else if (d2 <= cbp2) {
           // potentially created: an original non-link pushed beyond b + delta_t
           const double d = sqrt(d2);
-          h = bp - d;
+          h = cbp - d;
           double ux, uy, uz;
           if (d > 0.0) {
             ux = dx / d;
@@ -569,7 +602,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
               hi = mid - 1;
           }
           if (s_mk[w][lo]) {
-            o = B.col[s_rp[w][lo] + (q - s_vb[w][lo])] & 0x7fffffffu;
+            o = B.col[s_rp[w][lo] + (q - s_vb[w][lo])] & kColRow;
             uint32_t cold = 0u;
             // the first marking of a cold row appends it to the worklist
             // (after the first step, which lists every row and is followed
@@ -680,7 +713,7 @@ __global__ void k_permute_cols(const uint32_t *new_id, const uint32_t *row_ptr, 
     const uint32_t a = row_ptr[e], b = row_ptr[e + 1], d = nrow_ptr[new_id[e]];
     for (uint32_t q = a; q < b; ++q) {
       const uint32_t c = col[q];
-      ncol[d + (q - a)] = new_id[c & 0x7fffffffu] | (c & 0x80000000u);
+      ncol[d + (q - a)] = new_id[c & kColRow] | (c & ~kColRow);
     }
   }
 }

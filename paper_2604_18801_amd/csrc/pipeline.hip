@@ -102,6 +102,11 @@ int job_constants(const pcc_params &p, const ScanPart &agg, int64_t n, JobDev &J
   J.one_m_beta1 = 1.0 - p.beta1;
   J.one_m_beta2 = 1.0 - p.beta2;
   J.loss_scale = std::ldexp(1.0, 32) / J.b2;
+  J.nthr = 1;
+  J.thr_bm[0] = J.bm;
+  J.thr_bp[0] = J.bp;
+  J.thr_bm2[0] = J.bm2;
+  J.thr_bp2[0] = J.bp2;
   J.max_iters = p.max_iters > 0 ? p.max_iters : 100000;
   J.loss_tol = p.loss_tol;
   J.optimizer = p.optimizer;
@@ -288,7 +293,7 @@ const double2 *bc_table(Context &C, double beta1, double beta2, int64_t len) {
 }
 
 pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_result *res,
-                     hipStream_t s, bool labels_only) {
+                     hipStream_t s, bool labels_only, bool multi) {
   const auto t_wall0 = std::chrono::steady_clock::now();
   PCC_HIP(hipSetDevice(C.device));
   PCC_HIP(hipStreamSynchronize(s));
@@ -419,6 +424,20 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
       act[q]->ncell = nc;
       keep.push_back(act[q]);
       kagg.push_back(agg[q]);
+    }
+    if (multi && keep.size() != act.size())
+      throw Error(PCC_E_INVALID_ARG, "a linking length of the multi-threshold call is invalid");
+    if (multi && !act.empty()) {
+      // one snapshot, several linking lengths: job 0 carries the loss
+      // thresholds of every job (Sec. 5, Limitations: the multi-threshold extension)
+      JobDev &J0 = act[0]->dev;
+      J0.nthr = (int32_t)act.size();
+      for (size_t q = 0; q < act.size(); ++q) {
+        J0.thr_bm[q] = act[q]->dev.bm;
+        J0.thr_bp[q] = act[q]->dev.bp;
+        J0.thr_bm2[q] = act[q]->dev.bm2;
+        J0.thr_bp2[q] = act[q]->dev.bp2;
+      }
     }
     if (keep.size() != act.size()) {
       // rare: rebuild the index space without the rejected jobs
@@ -681,6 +700,13 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
                           a_i + na_direct, a_j + na_direct, a_t + na_direct, ar, s);
     kt.stop(at, s);
   }
+  // multi-threshold call: every selected pair moves to job 0's particles,
+  // tagged with the index of the linking length that selected it
+  uint8_t *a_k = nullptr;
+  if (multi && J > 1) {
+    a_k = dev<uint8_t>(ar, na ? na : 1);
+    remap_thresholds(a_i, a_j, na, pos, inv_perm, d_poff, J, a_k, s);
+  }
   PCC_HIP(hipEventRecord(C.ev[5], s));
 
   // ------------------------------------------------------------------
@@ -690,7 +716,7 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
     int64_t nmax = 1;
     for (auto *h : act) nmax = std::max(nmax, h->n);
     const int at = kt.start(6, s);
-    sort_pairs(a_i, a_j, a_t, na, pos, bits_for((uint64_t)(nmax - 1)), ar, s);
+    sort_pairs(a_i, a_j, a_t, a_k, na, pos, bits_for((uint64_t)(nmax - 1)), ar, s);
     kt.stop(at, s);
   }
   uint8_t *is_e = dev<uint8_t>(ar, n);
@@ -708,7 +734,7 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
   {
     const int at = kt.start(6, s);
     order_rows(e_list, ne, eid, pos, d_jobs, d_poff, J, ar, s);
-    build_csr(a_i, a_j, a_t, na, eid, ne, row_ptr, col, ar, s);
+    build_csr(a_i, a_j, a_t, a_k, na, eid, ne, row_ptr, col, ar, s);
     kt.stop(at, s);
   }
   std::vector<int64_t> e_off(J + 1);
@@ -954,14 +980,15 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
     for (int q = 0; q < J; ++q) {
       HostJob &h = *act[q];
       const pcc_job &j = *h.in;
+      h.st.bytes_flags = (int64_t)(fb[q + 1] - fb[q]);
+      h.st.bytes_codes = (int64_t)((jb[q + 1] - jb[q] + 7) / 8);
+      if (!j.out.stream && !j.out.stream_len && !j.out.stream_cap) continue;  // no stream wanted
       std::vector<uint8_t> strm;
       size_t raw = 0;
       assemble_stream(h.n, j.params.m_bits, h.st.n_flagged, h.dev.qstep, h.dev.qoffset,
                       hflags.data() + fb[q], fb[q + 1] - fb[q],
                       h.st.n_flagged ? &ht[q] : nullptr, hwords.data() + w0[q], jb[q + 1] - jb[q],
                       strm, &raw);
-      h.st.bytes_flags = (int64_t)(fb[q + 1] - fb[q]);
-      h.st.bytes_codes = (int64_t)((jb[q + 1] - jb[q] + 7) / 8);
       h.st.bytes_stream = (int64_t)strm.size();
       if (j.out.stream_len) *j.out.stream_len = strm.size();
       if (j.out.stream && j.out.stream_cap >= strm.size())
@@ -1003,6 +1030,7 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
   C.last.a_i = a_i;
   C.last.a_j = a_j;
   C.last.a_t = a_t;
+  C.last.a_k = a_k;
   C.last.safe_root = pb.safe_par;
   C.last.pos = pos;
   C.last.e_list = e_list;
