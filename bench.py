@@ -76,27 +76,37 @@ def recorded_traffic(kernel):
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
-def verify(ctx, w, stream, labels):
+def verify(ctx, w, stream, labels, bs=None):
+    """Membership errors of the decoded stream (summed over the linking
+    lengths bs when several were corrected; labels then has one row each)
+    and box violations."""
     import numpy as np
     import torch
     import paper_2604_18801_amd as pcc
     x = pcc.decode(stream, w.recon)
     box_viol = int(np.count_nonzero(np.abs(x.astype(np.float64) - w.orig.astype(np.float64)) > w.xi))
-    lab2 = ctx.fof_labels(torch.from_numpy(x).cuda(), w.b, w.box)
-    memb = int((lab2 != labels).sum().item())
+    xd = torch.from_numpy(x).cuda()
+    if bs is None:
+        return int((ctx.fof_labels(xd, w.b, w.box) != labels).sum().item()), box_viol
+    memb = 0
+    for k, b in enumerate(bs):
+        memb += int((ctx.fof_labels(xd, b, w.box) != labels[k]).sum().item())
     return memb, box_viol
 
 
-def cpu_baseline(w, side, mode):
+def cpu_baseline(w, side, mode, bs=None):
     import oracle
     import synth
     sub = synth.sub_box(w, side)
     t0 = time.perf_counter()
-    r = oracle.correct(sub.orig, sub.recon, sub.b, sub.xi, mode=mode, box=sub.box)
+    r = oracle.correct(sub.orig, sub.recon, list(bs) if bs else sub.b, sub.xi, mode=mode,
+                       box=sub.box)
     dt = time.perf_counter() - t0
+    thr = (" at linking lengths %s" % ",".join("%g" % v for v in bs)) if bs else ""
     return {"value": sub.n / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
             "sample": "%d particles in a %g^3 sub-box of the same snapshot (open boundaries), "
-                      "mode %s, %d iterations, %.2f s single-threaded" % (sub.n, side, mode, r.iters, dt)}
+                      "mode %s%s, %d iterations, %.2f s single-threaded" % (
+                          sub.n, side, mode, thr, r.iters, dt)}
 
 
 def _percentile(xs, q):
@@ -302,6 +312,9 @@ def main():
     ap.add_argument("--detail", default="", help="served: write one JSON row per job here")
     ap.add_argument("--served-modes", default="hf", choices=("hf", "spec"),
                     help="served: every job in HF mode, or the stream's own VP/SC/HF draw")
+    ap.add_argument("--thresholds", default="",
+                    help="comma-separated linking lengths: correct the snapshot for all of "
+                         "them at once (pcc_correct_multi)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the correction pass is built and measured on a "
@@ -341,7 +354,13 @@ def main():
         del src, dst
         log("copy probe: %s" % probe)
 
+    bs = [float(v) for v in args.thresholds.split(",")] if args.thresholds else None
+    if bs:
+        desc += "; corrected at linking lengths %s at once" % ",".join("%g" % v for v in bs)
+
     def step(mode=args.mode, **kw):
+        if bs:
+            return ctx.correct_multi(o, r, bs, w.xi, mode=mode, box=w.box, **kw)
         return ctx.correct(o, r, w.b, w.xi, mode=mode, box=w.box, **kw)
 
     for k in range(args.warmup):
@@ -392,7 +411,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded generator; no dataset)",
-        "config": {"workload": desc, "n": w.n, "mode": args.mode, "b": w.b, "xi": w.xi,
+        "config": {"workload": desc, "n": w.n, "mode": args.mode, "b": bs or w.b, "xi": w.xi,
                    "parallelism": "single GPU"},
         "status": last["status"], "iters": last["iters"], "n_active": last["n_active"],
         "n_editable": last["n_editable"], "n_flagged": last["n_flagged"],
@@ -406,7 +425,7 @@ def main():
     if probe:
         out["copy_probe"] = probe
     if not args.no_verify:
-        memb, boxv = verify(ctx, w, stream, labels)
+        memb, boxv = verify(ctx, w, stream, labels, bs)
         out["membership_errors"] = memb
         out["box_violations"] = boxv
         if memb or boxv or last["status"] != 0:
@@ -426,13 +445,13 @@ def main():
                  "viol_final": st2["viol_final"], "ms": round(1e3 * dt, 2),
                  "particles_per_s": round(w.n / dt, 1)}
             if not args.no_verify:
-                e["membership_errors"], e["box_violations"] = verify(ctx, w, s2, l2)
+                e["membership_errors"], e["box_violations"] = verify(ctx, w, s2, l2, bs)
             extra[m] = e
             log("mode %s capped at 100 iterations: %s" % (m, e))
         out["modes_capped_100"] = extra
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) on a %g^3 sub-box" % args.cpu_side)
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_side, args.mode)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_side, args.mode, bs)
     ctx.close()
     print(json.dumps(out), flush=True)
 
