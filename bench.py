@@ -127,6 +127,24 @@ def _verify_many(ctx, ws, results):
     return memb, boxv
 
 
+def tune(ctx, jobs, args):
+    """Autotuner (outside the timed region): the chosen scheduling knobs and
+    the spread of the trials, or None with --no-autotune."""
+    if args.no_autotune:
+        return None
+    t = time.perf_counter()
+    rep = ctx.autotune(jobs)
+    pair = [x["ms"] for x in rep["trials"] if x["kind"] == "pre_pgd_stages"]
+    full = [x["ms"] for x in rep["trials"] if x["kind"] == "correction"]
+    out = {"cell_pct": rep["cell_pct"], "dense_cell": rep["dense_cell"],
+           "graph_iters": rep["graph_iters"],
+           "pre_pgd_stages_ms": [round(min(pair), 2), round(max(pair), 2)] if pair else None,
+           "correction_ms": [round(min(full), 2), round(max(full), 2)] if full else None,
+           "trials": len(rep["trials"]), "s": round(time.perf_counter() - t, 2)}
+    log("autotune: %s" % out)
+    return out
+
+
 def bench_md_batch(args):
     """Batched MD (the first K blocks of the 256-block batch): one
     pcc_correct_batch call over all blocks is a step."""
@@ -143,6 +161,7 @@ def bench_md_batch(args):
     jobs = [dict(orig=torch.from_numpy(w.orig).cuda(), recon=torch.from_numpy(w.recon).cuda(),
                  b=w.b, xi=w.xi, mode=args.mode, box=w.box, opts=kw) for w in ws]
     torch.cuda.synchronize()
+    tuned = tune(ctx, jobs, args)
     for k in range(args.warmup):
         ctx.correct_batch(jobs)
     torch.cuda.synchronize()
@@ -163,6 +182,7 @@ def bench_md_batch(args):
                                "xi=0.05, non-periodic" % (len(ws) - 1),
                    "blocks": len(ws), "atoms": total, "mode": args.mode,
                    "parallelism": "single GPU, one batched call"},
+        "autotune": tuned,
         "iters_max": int(max(r[3]["iters"] for r in res)),
         "not_converged": int(sum(1 for s in statuses if s == 1)),
         "failed": int(sum(1 for s in statuses if s < 0)),
@@ -312,6 +332,8 @@ def main():
     ap.add_argument("--detail", default="", help="served: write one JSON row per job here")
     ap.add_argument("--served-modes", default="hf", choices=("hf", "spec"),
                     help="served: every job in HF mode, or the stream's own VP/SC/HF draw")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default scheduling knobs instead of autotuning them first")
     ap.add_argument("--thresholds", default="",
                     help="comma-separated linking lengths: correct the snapshot for all of "
                          "them at once (pcc_correct_multi)")
@@ -363,6 +385,8 @@ def main():
             return ctx.correct_multi(o, r, bs, w.xi, mode=mode, box=w.box, **kw)
         return ctx.correct(o, r, w.b, w.xi, mode=mode, box=w.box, **kw)
 
+    tjob = dict(orig=o, recon=r, b=w.b, xi=w.xi, mode=args.mode, box=w.box)
+    tuned = tune(ctx, [tjob], args) if not bs else None
     for k in range(args.warmup):
         t = time.perf_counter()
         _, _, st = step()
@@ -418,6 +442,7 @@ def main():
         "pgd_rows_evaluated": last["pgd_rows_evaluated"],
         "pgd_incidences_evaluated": last["pgd_incidences_evaluated"],
         "stream_bytes": last["bytes_stream"],
+        "autotune": tuned,
         "stage_ms": {k: round(v, 3) for k, v in last["t_stage_ms"].items()},
         "kernel_ms_per_step": {k: round(v / len(stats), 3) for k, v in kms.items()},
         "roofline": roofline,

@@ -162,9 +162,12 @@ pcc_status pcc_context_destroy(pcc_context *ctx);
 /*
  * Context options.
  *   PCC_CTX_KERNEL_TIMING  0/1: bracket the main kernels with HIP events and
- *                          report their device time in pcc_stats.kernel_ms;
- *                          the PGD iterations are then launched one by one
- *                          instead of as a captured graph.  Default 0.
+ *                          report their device time in pcc_stats.kernel_ms.
+ *                          A captured PGD graph is timed as a whole and its
+ *                          time split evenly over its steps: kernel_ms of
+ *                          the PGD step then includes the finalize launch of
+ *                          those steps, whose own count and time cover only
+ *                          the first (direct) step.  Default 0.
  *   PCC_CTX_GRAPH_ITERS    PGD iterations per captured graph launch (1..64,
  *                          default 8); one small readback follows each launch.
  *   PCC_CTX_EXACT_PAIRS    0/1: always count the pairs a mode keeps in a pass
@@ -173,8 +176,55 @@ pcc_status pcc_context_destroy(pcc_context *ctx);
  *                          would not fit in half the free device memory).
  *                          Results are the same either way.  Default 0.
  */
-enum { PCC_CTX_KERNEL_TIMING = 1, PCC_CTX_GRAPH_ITERS = 2, PCC_CTX_EXACT_PAIRS = 3 };
+enum {
+  PCC_CTX_KERNEL_TIMING = 1,
+  PCC_CTX_GRAPH_ITERS = 2,
+  PCC_CTX_EXACT_PAIRS = 3,
+  PCC_CTX_CELL_PCT = 4,
+  PCC_CTX_DENSE_CELL = 5
+};
+/*
+ * Scheduling knobs (no result depends on them; pcc_autotune sets them):
+ *   PCC_CTX_CELL_PCT       side of the cell-list cells as a percentage of
+ *                          r_v = b + 2 sqrt(3) xi, 100 .. 400 (default 100).
+ *                          Cells are never smaller than r_v, so the 13
+ *                          forward neighbour cells hold every partner; a
+ *                          periodic axis keeps at least three cells.
+ *   PCC_CTX_DENSE_CELL     cells with at least this many particles are
+ *                          searched by whole waves (64 home particles per
+ *                          wave, partners staged through LDS), the others by
+ *                          one thread per particle; 1 .. 4096 (default 32).
+ */
 pcc_status pcc_context_set(pcc_context *ctx, int32_t key, int64_t value);
+/* Reads a context option (any key above) into *value. */
+pcc_status pcc_context_get(pcc_context *ctx, int32_t key, int64_t *value);
+
+/*
+ * Autotuner: corrects the jobs (the same list pcc_correct_batch takes;
+ * their outputs are not written) under candidate scheduling knobs on this
+ * context's device and leaves the fastest on the context.  First the cell
+ * side (PCC_CTX_CELL_PCT 100, 125, 150, 200) and the dense-cell threshold
+ * (16, 32, 64, 128), each pair scored by the device time of the stages they
+ * act on (cell build, pair passes, labels, selection, CSR); then, unless
+ * flags has PCC_TUNE_NO_GRAPH, the PGD graph length (PCC_CTX_GRAPH_ITERS 4,
+ * 8, 16, 32) scored by the wall time of the call.  Every trial is recorded
+ * in rep (may be NULL).
+ * Work is queued on hip_stream; the call returns when it is done.  The jobs'
+ * results do not depend on the knobs, only their speed.
+ */
+#define PCC_TUNE_MAX_TRIALS 32
+enum { PCC_TUNE_NO_GRAPH = 1 };
+typedef struct {
+  int32_t cell_pct, dense_cell, graph_iters;  /* chosen (now set on the context) */
+  int32_t n_trials;
+  int32_t trial_kind[PCC_TUNE_MAX_TRIALS];    /* 0 stages before PGD, 1 whole call */
+  int32_t trial_cell_pct[PCC_TUNE_MAX_TRIALS];
+  int32_t trial_dense_cell[PCC_TUNE_MAX_TRIALS];
+  int32_t trial_graph_iters[PCC_TUNE_MAX_TRIALS];
+  double trial_ms[PCC_TUNE_MAX_TRIALS];       /* its score in ms */
+} pcc_tune_report;
+pcc_status pcc_autotune(pcc_context *ctx, const pcc_job *jobs, int32_t njobs, int32_t flags,
+                        pcc_tune_report *rep, void *hip_stream);
 
 void pcc_params_init(pcc_params *p);
 

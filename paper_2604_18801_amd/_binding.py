@@ -76,6 +76,18 @@ class ServerConfig(C.Structure):
     _fields_ = [("hbm_budget", C.c_size_t), ("max_inflight", C.c_int32), ("n_streams", C.c_int32)]
 
 
+_TUNE_MAX = 32
+
+
+class TuneReport(C.Structure):
+    _fields_ = [("cell_pct", C.c_int32), ("dense_cell", C.c_int32), ("graph_iters", C.c_int32),
+                ("n_trials", C.c_int32), ("trial_kind", C.c_int32 * _TUNE_MAX),
+                ("trial_cell_pct", C.c_int32 * _TUNE_MAX),
+                ("trial_dense_cell", C.c_int32 * _TUNE_MAX),
+                ("trial_graph_iters", C.c_int32 * _TUNE_MAX),
+                ("trial_ms", C.c_double * _TUNE_MAX)]
+
+
 PENDING = 2
 
 
@@ -119,6 +131,9 @@ def lib() -> C.CDLL:
         L.pcc_fof_labels.argtypes = [C.c_void_p, C.POINTER(Particles), C.c_double,
                                      C.POINTER(C.c_double), C.c_void_p, C.c_void_p]
         L.pcc_context_set.argtypes = [C.c_void_p, C.c_int32, C.c_int64]
+        L.pcc_context_get.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]
+        L.pcc_autotune.argtypes = [C.c_void_p, C.POINTER(Job), C.c_int32, C.c_int32,
+                                   C.POINTER(TuneReport), C.c_void_p]
         L.pcc_debug_fetch.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int64,
                                       C.POINTER(C.c_int64)]
         L.pcc_decode_device.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(Particles),
@@ -133,7 +148,7 @@ def lib() -> C.CDLL:
         L.pcc_server_destroy.argtypes = [C.c_void_p]
         for name in ("pcc_context_create", "pcc_context_destroy", "pcc_correct",
                      "pcc_correct_multi", "pcc_correct_batch", "pcc_decode", "pcc_fof_labels", "pcc_debug_fetch",
-                     "pcc_context_set", "pcc_decode_device", "pcc_server_create", "pcc_server_submit",
+                     "pcc_context_set", "pcc_context_get", "pcc_autotune", "pcc_decode_device", "pcc_server_create", "pcc_server_submit",
                      "pcc_server_poll", "pcc_server_wait", "pcc_server_cancel",
                      "pcc_server_drain", "pcc_server_destroy"):
             getattr(L, name).restype = C.c_int32
@@ -261,9 +276,38 @@ class Context:
         except Exception:
             pass
 
+    _OPTIONS = {"kernel_timing": 1, "graph_iters": 2, "exact_pairs": 3, "cell_pct": 4,
+                "dense_cell": 5}
+
     def set_option(self, key: str, value: int):
-        code = {"kernel_timing": 1, "graph_iters": 2, "exact_pairs": 3}[key]
-        _check(lib().pcc_context_set(self._h, code, int(value)))
+        _check(lib().pcc_context_set(self._h, self._OPTIONS[key], int(value)))
+
+    def get_option(self, key: str) -> int:
+        v = C.c_int64(0)
+        _check(lib().pcc_context_get(self._h, self._OPTIONS[key], C.byref(v)))
+        return v.value
+
+    def autotune(self, jobs: Sequence[Dict], graph: bool = True) -> Dict:
+        """Times the jobs (dicts as for correct_batch) under candidate
+        scheduling knobs and keeps the fastest on this context; returns the
+        choice and every trial."""
+        cj = (Job * len(jobs))()
+        held = []
+        on_dev = False
+        for k, jd in enumerate(jobs):
+            h = _JobBuffers(jd)
+            cj[k] = h.job
+            on_dev |= h.on_device
+            held.append(h)
+        rep = TuneReport()
+        _check(lib().pcc_autotune(self._h, cj, len(jobs), 0 if graph else 1, C.byref(rep),
+                                  _stream_handle(on_dev)))
+        trials = [{"kind": ("pre_pgd_stages", "correction")[rep.trial_kind[t]],
+                   "cell_pct": rep.trial_cell_pct[t], "dense_cell": rep.trial_dense_cell[t],
+                   "graph_iters": rep.trial_graph_iters[t], "ms": rep.trial_ms[t]}
+                  for t in range(rep.n_trials)]
+        return {"cell_pct": rep.cell_pct, "dense_cell": rep.dense_cell,
+                "graph_iters": rep.graph_iters, "trials": trials}
 
     # ------------------------------------------------------------------
     def correct(self, orig, recon, b: float, xi: float, mode="hf", box=None, labels=True,

@@ -81,7 +81,40 @@ pcc_status pcc_context_set(pcc_context *ctx, int32_t key, int64_t value) {
     ctx->c.force_exact_pairs = value != 0;
     return PCC_OK;
   }
+  if (key == PCC_CTX_CELL_PCT) {
+    if (value < 100 || value > 400) return fail(PCC_E_INVALID_ARG, "cell side lies in 100..400 %");
+    ctx->c.cell_pct = (int)value;
+    return PCC_OK;
+  }
+  if (key == PCC_CTX_DENSE_CELL) {
+    if (value < 1 || value > 4096) return fail(PCC_E_INVALID_ARG, "dense-cell threshold lies in 1..4096");
+    ctx->c.dense_cell = (int)value;
+    return PCC_OK;
+  }
   return fail(PCC_E_INVALID_ARG, "unknown context option");
+}
+
+pcc_status pcc_context_get(pcc_context *ctx, int32_t key, int64_t *value) {
+  if (!ctx || !value) return fail(PCC_E_INVALID_ARG, "NULL argument");
+  switch (key) {
+    case PCC_CTX_KERNEL_TIMING: *value = ctx->c.kt.on ? 1 : 0; return PCC_OK;
+    case PCC_CTX_GRAPH_ITERS: *value = ctx->c.graph_iters; return PCC_OK;
+    case PCC_CTX_EXACT_PAIRS: *value = ctx->c.force_exact_pairs ? 1 : 0; return PCC_OK;
+    case PCC_CTX_CELL_PCT: *value = ctx->c.cell_pct; return PCC_OK;
+    case PCC_CTX_DENSE_CELL: *value = ctx->c.dense_cell; return PCC_OK;
+    default: return fail(PCC_E_INVALID_ARG, "unknown context option");
+  }
+}
+
+pcc_status pcc_autotune(pcc_context *ctx, const pcc_job *jobs, int32_t njobs, int32_t flags,
+                        pcc_tune_report *rep, void *hip_stream) {
+  if (!ctx || njobs < 1 || !jobs) return fail(PCC_E_INVALID_ARG, "NULL argument or no job");
+  return guarded([&]() -> pcc_status {
+    pcc_tune_report r;
+    pcc::autotune(ctx->c, jobs, njobs, pick(ctx, hip_stream), flags, r);
+    if (rep) *rep = r;
+    return PCC_OK;
+  });
 }
 
 void pcc_params_init(pcc_params *p) {

@@ -40,9 +40,23 @@ struct KernelTimer {
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<int, int>> marks;  // (kernel id, first event index)
   size_t used = 0;
-  void begin_call() { marks.clear(); used = 0; }
+  double acc_ms[PCC_NKERNELS] = {};  // times of graph replays already read
+  int64_t acc_n[PCC_NKERNELS] = {};
+  void begin_call() {
+    marks.clear();
+    used = 0;
+    for (int k = 0; k < PCC_NKERNELS; ++k) acc_ms[k] = 0.0, acc_n[k] = 0;
+  }
+  void reserve(size_t n);  // at least n unused events in the pool
+  void record(hipEvent_t e, hipStream_t s);
   int start(int id, hipStream_t s);
   void stop(int at, hipStream_t s);
+  // an event pair around a graph replay (reused by the next replay, after
+  // add_split has read it): the replay's time counts as k launches of id
+  int bracket_begin(hipStream_t s);
+  void bracket_end(int at, hipStream_t s);
+  void add_split(int id, int at, int k);
+  // per kernel id: the accumulators plus the marks of direct launches
   void collect(double *ms, int64_t *count);
   ~KernelTimer();
 };
@@ -52,6 +66,9 @@ struct Context {
   KernelTimer kt;
   int graph_iters = 8;
   bool force_exact_pairs = false;  // always count the kept pairs before writing them
+  // scheduling knobs (results do not depend on them; pcc_autotune picks them)
+  int cell_pct = 100;    // cell side as a percentage of r_v (>= 100)
+  int dense_cell = 32;   // cells with at least this many particles take the dense pair path
   std::vector<BcTable> bc;
   hipStream_t own = nullptr;
   Arena arena;
@@ -67,6 +84,11 @@ const double2 *bc_table(Context &C, double beta1, double beta2, int64_t len);
 
 // message returned by pcc_last_error on the calling thread
 void set_last_error(const std::string &m);
+
+// tune.cpp: times the jobs under candidate scheduling knobs and leaves the
+// fastest on the context
+void autotune(Context &C, const pcc_job *jobs, int njobs, hipStream_t s, int32_t flags,
+              pcc_tune_report &rep);
 
 // multi: the jobs are one snapshot at several linking lengths, corrected
 // together into job 0's particles (job 0's stream; every job's labels)

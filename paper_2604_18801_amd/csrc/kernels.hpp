@@ -70,8 +70,11 @@ struct PairPlan {
   uint32_t *ucell = nullptr, *uchunk = nullptr;
   size_t n_units = 0;
 };
+// dense: cells with at least this many particles take the dense path (one
+// wave per 64 home particles), the others the sparse one (a thread each)
 void plan_pairs(PairPlan &pl, const uint32_t *cell_of, const uint32_t *cell_start,
-                const int32_t *nbr, const uint32_t *n_cells, size_t n, Arena &ar, hipStream_t s);
+                const int32_t *nbr, const uint32_t *n_cells, size_t n, uint32_t dense, Arena &ar,
+                hipStream_t s);
 void launch_pair_pass1(const PairBufs &b, const PairPlan &pl, hipStream_t s);  // classify, hook
 void launch_pair_count(const PairBufs &b, const PairPlan &pl, hipStream_t s);  // filtered counts
 void launch_pair_write(const PairBufs &b, const PairPlan &pl, hipStream_t s);  // filtered writes

@@ -276,9 +276,9 @@ __device__ inline void visit(const PairBufs &B, const JobPair &q, Home &h, uint3
   }
 }
 
-// Sparse cells: one thread per particle (list of particles of cells with
-// fewer than kDenseCell members, ordered by the candidate count of their
-// cell).  Partners: later particles of its own cell, then every particle of
+// Sparse cells: one thread per particle (list of particles of cells below
+// the dense-cell threshold, ordered by the candidate count of their cell).
+// Partners: later particles of its own cell, then every particle of
 // the 13 forward cells, in index order.  The walk over those ranges is one
 // flat loop, one candidate per lane per iteration, so a lane stays busy until
 // its own candidates run out (nested loops over the ranges would idle every
@@ -501,18 +501,13 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense_write(PairBufs 
   }
 }
 
-#ifndef PCC_DENSE_CELL
-#define PCC_DENSE_CELL 32
-#endif
-constexpr int kDenseCell = PCC_DENSE_CELL;  // cells with at least this many particles go dense
-
 // particles of sparse cells, and (cell, 64-chunk) units of dense cells
 __global__ void k_sparse_flags(const uint32_t *cell_of, const uint32_t *cell_start, size_t n,
-                               uint8_t *flag) {
+                               uint32_t dense, uint8_t *flag) {
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
        k += (size_t)gridDim.x * blockDim.x) {
     const uint32_t c = cell_of[k];
-    flag[k] = (cell_start[c + 1] - cell_start[c]) < (uint32_t)kDenseCell ? 1 : 0;
+    flag[k] = (cell_start[c + 1] - cell_start[c]) < dense ? 1 : 0;
   }
 }
 __global__ void k_sparse_list(const uint8_t *flag, const uint32_t *pos32, size_t n, uint32_t *list) {
@@ -540,14 +535,14 @@ __global__ void k_sparse_keys(const uint32_t *list, size_t m, const uint32_t *ce
 }
 
 __global__ void k_unit_counts(const uint32_t *cell_start, const uint32_t *n_cells, size_t max_cells,
-                              uint32_t *units) {
+                              uint32_t dense, uint32_t *units) {
   const uint32_t U = *n_cells;
   for (size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x; u < max_cells;
        u += (size_t)gridDim.x * blockDim.x) {
     uint32_t c = 0;
     if (u < U) {
       const uint32_t nu = cell_start[u + 1] - cell_start[u];
-      c = nu >= (uint32_t)kDenseCell ? (nu + 63u) / 64u : 0u;
+      c = nu >= dense ? (nu + 63u) / 64u : 0u;
     }
     units[u] = c;
   }
@@ -563,7 +558,9 @@ __global__ void k_unit_list(const uint32_t *units, const uint32_t *uoff, size_t 
 }
 
 void plan_pairs(PairPlan &pl, const uint32_t *cell_of, const uint32_t *cell_start,
-                const int32_t *nbr, const uint32_t *n_cells, size_t n, Arena &ar, hipStream_t s) {
+                const int32_t *nbr, const uint32_t *n_cells, size_t n, uint32_t dense, Arena &ar,
+                hipStream_t s) {
+  if (dense < 1) dense = 1;
   uint8_t *flag = ar.get<uint8_t>(n ? n : 1);
   uint32_t *pos32 = ar.get<uint32_t>(n ? n : 1);
   uint32_t *cnt = ar.get<uint32_t>(2);
@@ -573,7 +570,7 @@ void plan_pairs(PairPlan &pl, const uint32_t *cell_of, const uint32_t *cell_star
   pl.uchunk = ar.get<uint32_t>(n ? n : 1);
   const int nb = blocks_for(n, 256, 65536);
   if (n) {
-    k_sparse_flags<<<nb, 256, 0, s>>>(cell_of, cell_start, n, flag);
+    k_sparse_flags<<<nb, 256, 0, s>>>(cell_of, cell_start, n, dense, flag);
     scan_u8_u32(flag, pos32, n, cnt, ar, s);
     k_sparse_list<<<nb, 256, 0, s>>>(flag, pos32, n, pl.sparse);
     // heaviest cells first, a cell's particles together and in index order
@@ -586,7 +583,7 @@ void plan_pairs(PairPlan &pl, const uint32_t *cell_of, const uint32_t *cell_star
                                                                nbr, key);
       radix_sort_u32(key, pl.sparse, ns, 4, ar, s);
     }
-    k_unit_counts<<<nb, 256, 0, s>>>(cell_start, n_cells, n, units);
+    k_unit_counts<<<nb, 256, 0, s>>>(cell_start, n_cells, n, dense, units);
     scan_u32_u32(units, uoff, n, cnt + 1, ar, s);
     k_unit_list<<<nb, 256, 0, s>>>(units, uoff, n, pl.ucell, pl.uchunk);
   } else {

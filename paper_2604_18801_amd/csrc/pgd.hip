@@ -471,50 +471,48 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
         const double dy = wrapd(s_py[w][r] - po.y, L1, h1);
         const double dz = wrapd(s_pz[w][r] - po.z, L2, h2);
         const double d2 = (dx * dx + dy * dy) + dz * dz;
-        // thresholds of the constraint: the job's own, or those of its
-        // linking length when several are corrected at once
-        double cbm = bm, cbm2 = bm2, cbp = bp, cbp2 = bp2;
+        // squared threshold of the constraint (b - delta_t for a potentially
+        // broken link, b + delta_t for a potentially created pair): of the
+        // job's linking length, or of the constraint's own when several are
+        // corrected at once
+        const bool created = (col & kColPc) != 0;
         const uint32_t kk = (col >> kColThrShift) & 7u;
-        if (kk) {
-          cbm = J.thr_bm[kk];
-          cbm2 = J.thr_bm2[kk];
-          cbp = J.thr_bp[kk];
-          cbp2 = J.thr_bp2[kk];
-        }
+        double t2 = created ? bp2 : bm2;
+        if (kk) t2 = created ? J.thr_bp2[kk] : J.thr_bm2[kk];
         double h = 0.0;
-        if (!(col & kColPc)) {
-          // potentially broken: an original link pulled back inside b - delta_t
-          if (d2 > cbm2) {
-            const double d = sqrt(d2);
-            h = d - cbm;
+        if (created ? d2 <= t2 : d2 > t2) {
+          double t1 = created ? bp : bm;
+          if (kk) t1 = created ? J.thr_bp[kk] : J.thr_bm[kk];
+          const double d = sqrt(d2);
+          if (!created) {
+            // potentially broken: an original link pulled back inside b - delta_t
+            h = d - t1;
             tx = 2.0 * h * (dx / d);
             ty = 2.0 * h * (dy / d);
             tz = 2.0 * h * (dz / d);
-            hit = true;
-          }
-        } else if (d2 <= cbp2) {
-          // potentially created: an original non-link pushed beyond b + delta_t
-          const double d = sqrt(d2);
-          h = cbp - d;
-          double ux, uy, uz;
-          if (d > 0.0) {
-            ux = dx / d;
-            uy = dy / d;
-            uz = dz / d;
           } else {
-            // coincident points: take the direction of the original pair
-            const float4 a = B.xo[er], b = B.xo[o];
-            const double ox = wrapd((double)a.x - (double)b.x, L0, h0);
-            const double oy = wrapd((double)a.y - (double)b.y, L1, h1);
-            const double oz = wrapd((double)a.z - (double)b.z, L2, h2);
-            const double od = sqrt((ox * ox + oy * oy) + oz * oz);
-            ux = ox / od;
-            uy = oy / od;
-            uz = oz / od;
+            // potentially created: an original non-link pushed beyond b + delta_t
+            h = t1 - d;
+            double ux, uy, uz;
+            if (d > 0.0) {
+              ux = dx / d;
+              uy = dy / d;
+              uz = dz / d;
+            } else {
+              // coincident points: take the direction of the original pair
+              const float4 a = B.xo[er], b = B.xo[o];
+              const double ox = wrapd((double)a.x - (double)b.x, L0, h0);
+              const double oy = wrapd((double)a.y - (double)b.y, L1, h1);
+              const double oz = wrapd((double)a.z - (double)b.z, L2, h2);
+              const double od = sqrt((ox * ox + oy * oy) + oz * oz);
+              ux = ox / od;
+              uy = oy / od;
+              uz = oz / od;
+            }
+            tx = -(2.0 * h * ux);
+            ty = -(2.0 * h * uy);
+            tz = -(2.0 * h * uz);
           }
-          tx = -(2.0 * h * ux);
-          ty = -(2.0 * h * uy);
-          tz = -(2.0 * h * uz);
           hit = true;
         }
         if (hit && o > er) lossq += (unsigned long long)(h * h * scale);

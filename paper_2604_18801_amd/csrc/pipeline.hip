@@ -66,8 +66,8 @@ int check_params(const pcc_job &j, std::string &err) {
 }
 
 // Constants of Alg. 1 and Sec. 3.1-3.3 for one job (library side).
-int job_constants(const pcc_params &p, const ScanPart &agg, int64_t n, JobDev &J, uint64_t &ncell,
-                  std::string &err) {
+int job_constants(const pcc_params &p, const ScanPart &agg, int64_t n, int cell_pct, JobDev &J,
+                  uint64_t &ncell, std::string &err) {
   std::memset(&J, 0, sizeof J);
   const double two_sqrt3 = 2.0 * std::sqrt(3.0);
   const double rs = p.b - two_sqrt3 * p.xi;
@@ -115,8 +115,11 @@ int job_constants(const pcc_params &p, const ScanPart &agg, int64_t n, JobDev &J
   J.qoffset = 2.0 * p.xi;
   J.qmax = levels;
   J.n = n;
-  // periodic axes and the cell grid: cells no smaller than r_v
+  // periodic axes and the cell grid: cells no smaller than r_v (the 13
+  // forward cells then hold every partner within r_v), cell_pct percent of
+  // it when that still leaves three cells on every periodic axis
   const double wmin = rv * (1.0 + std::ldexp(1.0, -20));
+  const double wcell = wmin * (double)std::max(100, cell_pct) / 100.0;
   double lmax = 0.0;
   uint64_t cells = 1;
   for (int a = 0; a < 3; ++a) {
@@ -131,7 +134,8 @@ int job_constants(const pcc_params &p, const ScanPart &agg, int64_t n, JobDev &J
       J.origin[a] = 0.0;
       ext = L;
       lmax = std::max(lmax, L);
-      const double f = std::floor(L / wmin);
+      double f = std::floor(L / wcell);
+      if (!(f >= 3.0)) f = std::min(3.0, std::floor(L / wmin));
       if (!(f >= 3.0)) {
         err = "periodic side must hold at least three cells of side b + 2 sqrt(3) xi";
         return -1;
@@ -144,7 +148,7 @@ int job_constants(const pcc_params &p, const ScanPart &agg, int64_t n, JobDev &J
       J.hLf[a] = std::numeric_limits<float>::infinity();
       J.origin[a] = n > 0 ? (double)agg.mn[a] : 0.0;
       ext = n > 0 ? (double)agg.mx[a] - (double)agg.mn[a] : 0.0;
-      const double f = std::floor(ext / wmin);
+      const double f = std::floor(ext / wcell);
       J.nc[a] = (int32_t)std::max(1.0, std::min(f, 2097152.0));
     }
     J.inv_w[a] = ext > 0 ? (double)J.nc[a] / ext : 0.0;
@@ -237,31 +241,62 @@ struct Staging {
 
 }  // namespace
 
-int KernelTimer::start(int id, hipStream_t s) {
-  if (!on) return -1;
-  while (pool.size() < used + 2) {
+void KernelTimer::reserve(size_t n) {
+  if (!on) return;
+  while (pool.size() < used + n) {
     hipEvent_t e;
     PCC_HIP(hipEventCreate(&e));
     pool.push_back(e);
   }
+}
+
+int KernelTimer::start(int id, hipStream_t s) {
+  if (!on) return -1;
+  reserve(2);
   const int at = (int)used;
   used += 2;
-  PCC_HIP(hipEventRecord(pool[at], s));
+  record(pool[at], s);
   marks.push_back({id, at});
   return at;
 }
 
+void KernelTimer::record(hipEvent_t e, hipStream_t s) { PCC_HIP(hipEventRecord(e, s)); }
+
 void KernelTimer::stop(int at, hipStream_t s) {
-  if (at >= 0) PCC_HIP(hipEventRecord(pool[at + 1], s));
+  if (at >= 0) record(pool[at + 1], s);
+}
+
+int KernelTimer::bracket_begin(hipStream_t s) {
+  if (!on) return -1;
+  reserve(2);
+  const int at = (int)used;  // the pair is reused by the next bracket
+  record(pool[at], s);
+  return at;
+}
+
+void KernelTimer::bracket_end(int at, hipStream_t s) {
+  if (at >= 0) record(pool[at + 1], s);
+}
+
+void KernelTimer::add_split(int id, int at, int k) {
+  float f = 0.f;
+  if (at >= 0 && hipEventElapsedTime(&f, pool[at], pool[at + 1]) == hipSuccess) {
+    acc_ms[id] += f;
+    acc_n[id] += k;
+  }
 }
 
 void KernelTimer::collect(double *ms, int64_t *count) {
   for (auto &m : marks) {
     float f = 0.f;
     if (hipEventElapsedTime(&f, pool[m.second], pool[m.second + 1]) == hipSuccess) {
-      ms[m.first] += f;
-      count[m.first] += 1;
+      acc_ms[m.first] += f;
+      acc_n[m.first] += 1;
     }
+  }
+  for (int k = 0; k < PCC_NKERNELS; ++k) {
+    ms[k] += acc_ms[k];
+    count[k] += acc_n[k];
   }
 }
 
@@ -417,7 +452,7 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
     for (size_t q = 0; q < act.size(); ++q) {
       std::string err;
       uint64_t nc = 0;
-      if (job_constants(act[q]->in->params, agg[q], act[q]->n, act[q]->dev, nc, err)) {
+      if (job_constants(act[q]->in->params, agg[q], act[q]->n, C.cell_pct, act[q]->dev, nc, err)) {
         act[q]->status = PCC_E_INVALID_ARG;
         continue;
       }
@@ -531,7 +566,7 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
   int32_t *nbr = dev<int32_t>(ar, n * 13);
   launch_neighbors(d_jobs, d_cbase, J, cell_key, n_cells, n, nbr, s);
   PairPlan plan;
-  plan_pairs(plan, cell_of, cell_start, nbr, n_cells, n, ar, s);
+  plan_pairs(plan, cell_of, cell_start, nbr, n_cells, n, (uint32_t)C.dense_cell, ar, s);
   PCC_HIP(hipEventRecord(C.ev[2], s));
 
   // ------------------------------------------------------------------
@@ -803,23 +838,11 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
     renumber_hot(gb, e_list, ar, s);
   }
   const int K = std::max(1, std::min(64, C.graph_iters));
-  if (kt.on) {
-    // one launch per kernel, each bracketed by events
-    int32_t *h_act = (int32_t *)st.get(sizeof(int32_t));
-    for (;;) {
-      PCC_HIP(hipMemcpyAsync(h_act, gb.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      PCC_HIP(hipStreamSynchronize(s));
-      if (*h_act <= 0) break;
-      for (int k = 0; k < K; ++k) {
-        int at = kt.start(3, s);
-        launch_pgd_step(gb, s);
-        kt.stop(at, s);
-        at = kt.start(4, s);
-        launch_pgd_finalize(gb, s);
-        kt.stop(at, s);
-      }
-    }
-  } else {
+  {
+    // K steps per captured graph.  With kernel timing on, each replay is
+    // bracketed by two events outside the graph and its time is split evenly
+    // over its K steps (a step launch and its finalize launch together):
+    // event nodes inside the graph would serialise it and slow it down.
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     PCC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -835,11 +858,15 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
     }
     int32_t *h_act = (int32_t *)st.get(sizeof(int32_t));
     try {
+      int at = -1;  // events of the last replay, when timed
       for (;;) {
         PCC_HIP(hipMemcpyAsync(h_act, gb.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         PCC_HIP(hipStreamSynchronize(s));
+        if (at >= 0) kt.add_split(3, at, K);
         if (*h_act <= 0) break;
+        at = kt.bracket_begin(s);
         PCC_HIP(hipGraphLaunch(exec, s));
+        kt.bracket_end(at, s);
       }
     } catch (...) {
       hipGraphExecDestroy(exec);

@@ -205,6 +205,9 @@ pcc_status pcc_server_create(pcc_context *ctx, const pcc_server_config *cfg, pcc
         return st;
       }
       h->c.graph_iters = ctx->c.graph_iters;
+      h->c.cell_pct = ctx->c.cell_pct;
+      h->c.dense_cell = ctx->c.dense_cell;
+      h->c.force_exact_pairs = ctx->c.force_exact_pairs;
       S->ctx.push_back(h);
     }
     for (int w = 0; w < nw; ++w) S->workers.emplace_back(worker_main, S, w);

@@ -58,3 +58,33 @@ def test_context_creation_without_gpu_fails_cleanly():
         pytest.skip("a GPU is present")
     with pytest.raises(pcc.PccError):
         pcc.Context(0)
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    # the ctypes mirrors of the C structs have the header's size and field
+    # offsets (a C program built with the system compiler prints them)
+    import shutil
+    import subprocess
+    from paper_2604_18801_amd import _binding as B
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if not cc:
+        pytest.skip("no C compiler")
+    pairs = [("pcc_params", B.Params), ("pcc_particles", B.Particles), ("pcc_outputs", B.Outputs),
+             ("pcc_stats", B.Stats), ("pcc_job", B.Job), ("pcc_job_result", B.JobResult),
+             ("pcc_server_config", B.ServerConfig), ("pcc_tune_report", B.TuneReport)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pcc.h"', "int main(void) {"]
+    for cname, py in pairs:
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f in py._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, f[0], cname, f[0]))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                 check=True).stdout.splitlines())
+    for cname, py in pairs:
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for f in py._fields_:
+            assert int(got[cname + "." + f[0]]) == getattr(py, f[0]).offset, (cname, f[0])
