@@ -327,13 +327,31 @@ pcc_status pcc_debug_fetch(pcc_context *ctx, int32_t job, int32_t what, void *ho
                            int64_t cap, int64_t *count);
 
 /*
+ * Test hook for failure handling (process-wide, no device call):
+ *   PCC_DEBUG_ALLOC_FAIL_AFTER  value >= 0: after `value` more successful
+ *                               workspace allocations, the next one fails as
+ *                               if the device were out of memory (the call
+ *                               then returns PCC_E_OUT_OF_MEMORY, or a
+ *                               server retries the jobs of that batch one
+ *                               by one); the hook then switches itself off.
+ *                               value -1 switches it off.
+ * pcc_debug_get reads the current value (the allocations left before the
+ * failure, or a negative number when off).
+ */
+enum { PCC_DEBUG_ALLOC_FAIL_AFTER = 1 };
+pcc_status pcc_debug_set(int32_t key, int64_t value);
+pcc_status pcc_debug_get(int32_t key, int64_t *value);
+
+/*
  * Served form: a job queue in front of the batched pass.  Worker threads
  * (n_streams of them, each with its own HIP stream and workspace on the
  * context's device) take the queued jobs in arrival order and run as many
  * of them together as max_inflight and their share of hbm_budget allow
  * (continuous batching: a batch starts as soon as a worker is free and takes
  * whatever has arrived).  Each job's results equal those of pcc_correct on
- * that job alone.  Job buffers are borrowed until the job has finished;
+ * that job alone.  When a batch runs out of device memory its jobs are run
+ * again one at a time, and a job that runs out of memory alone gets one
+ * more try after its worker's workspace is released.  Job buffers are borrowed until the job has finished;
  * device inputs must be ready (their producing stream synchronised) when
  * the job is submitted.  The server's calls are thread-safe; the context is
  * used only to pick the device and its options, and stays the caller's.

@@ -132,6 +132,8 @@ def lib() -> C.CDLL:
                                      C.POINTER(C.c_double), C.c_void_p, C.c_void_p]
         L.pcc_context_set.argtypes = [C.c_void_p, C.c_int32, C.c_int64]
         L.pcc_context_get.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]
+        L.pcc_debug_set.argtypes = [C.c_int32, C.c_int64]
+        L.pcc_debug_get.argtypes = [C.c_int32, C.POINTER(C.c_int64)]
         L.pcc_autotune.argtypes = [C.c_void_p, C.POINTER(Job), C.c_int32, C.c_int32,
                                    C.POINTER(TuneReport), C.c_void_p]
         L.pcc_debug_fetch.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int64,
@@ -148,7 +150,8 @@ def lib() -> C.CDLL:
         L.pcc_server_destroy.argtypes = [C.c_void_p]
         for name in ("pcc_context_create", "pcc_context_destroy", "pcc_correct",
                      "pcc_correct_multi", "pcc_correct_batch", "pcc_decode", "pcc_fof_labels", "pcc_debug_fetch",
-                     "pcc_context_set", "pcc_context_get", "pcc_autotune", "pcc_decode_device", "pcc_server_create", "pcc_server_submit",
+                     "pcc_context_set", "pcc_context_get", "pcc_autotune", "pcc_decode_device",
+                     "pcc_debug_set", "pcc_debug_get", "pcc_server_create", "pcc_server_submit",
                      "pcc_server_poll", "pcc_server_wait", "pcc_server_cancel",
                      "pcc_server_drain", "pcc_server_destroy"):
             getattr(L, name).restype = C.c_int32
@@ -442,6 +445,18 @@ class Context:
         _check(lib().pcc_debug_fetch(self._h, int(job), code, buf.ctypes.data, cnt.value,
                                      C.byref(cnt)))
         return buf[: cnt.value]
+
+
+def inject_alloc_failure(after: int):
+    """Test hook: the workspace allocation after `after` more successful ones
+    fails as if the device were out of memory (-1 switches it off)."""
+    _check(lib().pcc_debug_set(1, int(after)))
+
+
+def alloc_failure_countdown() -> int:
+    v = C.c_int64(0)
+    _check(lib().pcc_debug_get(1, C.byref(v)))
+    return v.value
 
 
 class Server:

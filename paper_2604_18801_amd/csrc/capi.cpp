@@ -106,6 +106,19 @@ pcc_status pcc_context_get(pcc_context *ctx, int32_t key, int64_t *value) {
   }
 }
 
+pcc_status pcc_debug_set(int32_t key, int64_t value) {
+  if (key != PCC_DEBUG_ALLOC_FAIL_AFTER) return fail(PCC_E_INVALID_ARG, "unknown debug key");
+  if (value < -1) return fail(PCC_E_INVALID_ARG, "value must be >= -1");
+  pcc::g_alloc_fail_after.store(value);
+  return PCC_OK;
+}
+
+pcc_status pcc_debug_get(int32_t key, int64_t *value) {
+  if (key != PCC_DEBUG_ALLOC_FAIL_AFTER || !value) return fail(PCC_E_INVALID_ARG, "bad argument");
+  *value = pcc::g_alloc_fail_after.load();
+  return PCC_OK;
+}
+
 pcc_status pcc_autotune(pcc_context *ctx, const pcc_job *jobs, int32_t njobs, int32_t flags,
                         pcc_tune_report *rep, void *hip_stream) {
   if (!ctx || njobs < 1 || !jobs) return fail(PCC_E_INVALID_ARG, "NULL argument or no job");

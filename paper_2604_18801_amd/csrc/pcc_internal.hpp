@@ -12,6 +12,7 @@
 #include <cstdint>
 #include <stdexcept>
 #include <string>
+#include <atomic>
 #include <vector>
 
 namespace pcc {
@@ -104,6 +105,11 @@ __device__ inline int job_of(const int64_t *__restrict__ off, int njobs, int64_t
 // Device memory arena: grow-only chunks, reset per call; after the first
 // call of a given size the steady state allocates nothing.
 // ---------------------------------------------------------------------------
+// Test hook (pcc_debug_set): when >= 0, the number of further arena
+// allocations that succeed before one fails as if the device were out of
+// memory; -1 when off.  Process-wide.
+extern std::atomic<int64_t> g_alloc_fail_after;
+
 class Arena {
  public:
   ~Arena();

@@ -327,8 +327,28 @@ const double2 *bc_table(Context &C, double beta1, double beta2, int64_t len) {
   return d;
 }
 
+namespace {
+pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_result *res,
+                          hipStream_t s, bool labels_only, bool multi);
+}  // namespace
+
 pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_result *res,
                      hipStream_t s, bool labels_only, bool multi) {
+  try {
+    return run_batch_impl(C, jobs, njobs_in, res, s, labels_only, multi);
+  } catch (...) {
+    // nothing the failed call queued may still be running when its error is
+    // reported: the caller may free its buffers and the arena may be released
+    (void)hipStreamSynchronize(s);
+    (void)hipGetLastError();
+    C.last.valid = false;
+    throw;
+  }
+}
+
+namespace {
+pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_result *res,
+                          hipStream_t s, bool labels_only, bool multi) {
   const auto t_wall0 = std::chrono::steady_clock::now();
   PCC_HIP(hipSetDevice(C.device));
   PCC_HIP(hipStreamSynchronize(s));
@@ -846,9 +866,16 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     PCC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < K; ++k) {
-      launch_pgd_step(gb, s);
-      launch_pgd_finalize(gb, s);
+    try {
+      for (int k = 0; k < K; ++k) {
+        launch_pgd_step(gb, s);
+        launch_pgd_finalize(gb, s);
+      }
+    } catch (...) {
+      // leave the stream out of capture mode before reporting the error
+      hipGraph_t partial = nullptr;
+      if (hipStreamEndCapture(s, &partial) == hipSuccess && partial) hipGraphDestroy(partial);
+      throw;
     }
     PCC_HIP(hipStreamEndCapture(s, &graph));
     hipError_t ge = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -1071,5 +1098,7 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
     if (res[k].status < 0 && first == PCC_OK) first = res[k].status;
   return first;
 }
+
+}  // namespace
 
 }  // namespace pcc

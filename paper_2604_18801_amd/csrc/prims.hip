@@ -17,6 +17,8 @@ void hip_fail(hipError_t e, const char *what, const char *file, int line) {
 // ---------------------------------------------------------------------------
 // arena
 // ---------------------------------------------------------------------------
+std::atomic<int64_t> g_alloc_fail_after{-1};
+
 Arena::~Arena() { release(); }
 
 void Arena::release() {
@@ -39,6 +41,8 @@ void Arena::reset() {
 }
 
 void *Arena::alloc(size_t bytes) {
+  if (g_alloc_fail_after.load() >= 0 && g_alloc_fail_after.fetch_sub(1) == 0)
+    throw Error(-2, "device allocation failed (injected by pcc_debug_set)");
   bytes = (bytes + 255) & ~(size_t)255;
   if (bytes == 0) bytes = 256;
   for (auto &c : chunks_) {

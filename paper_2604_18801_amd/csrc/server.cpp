@@ -29,6 +29,7 @@ struct Rec {
   pcc_job_result res;
   int state = kQueued;
   bool solo = false;  // run alone (after its batch ran out of memory)
+  bool retried = false;  // ran out of memory alone once already
   std::string err;
 };
 
@@ -119,12 +120,16 @@ void worker_main(pcc_server *S, int w) {
     }
     if (err == PCC_E_OUT_OF_MEMORY) C.arena.release();  // start the next batch afresh
     std::lock_guard<std::mutex> lk(S->mu);
-    if (err == PCC_E_OUT_OF_MEMORY && batch.size() > 1) {
-      // run each job of the batch on its own, at the head of the queue
+    if (err == PCC_E_OUT_OF_MEMORY && (batch.size() > 1 || !S->recs[batch[0]].retried)) {
+      // run each job of the batch on its own, at the head of the queue; a
+      // job that ran out of memory alone gets one more try with the
+      // worker's workspace released
+      const bool alone = batch.size() == 1;
       for (auto it = batch.rbegin(); it != batch.rend(); ++it) {
         Rec &r = S->recs[*it];
         r.state = kQueued;
         r.solo = true;
+        r.retried |= alone;
         S->queue.push_front(*it);
       }
       S->cv_work.notify_all();

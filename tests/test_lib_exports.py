@@ -88,3 +88,15 @@ def test_binding_structs_match_the_header(tmp_path):
         assert int(got[cname]) == ctypes.sizeof(py), cname
         for f in py._fields_:
             assert int(got[cname + "." + f[0]]) == getattr(py, f[0]).offset, (cname, f[0])
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpcc.so not built")
+def test_alloc_failure_hook_is_host_only():
+    import paper_2604_18801_amd as pcc
+    assert pcc.alloc_failure_countdown() < 0
+    pcc.inject_alloc_failure(7)
+    assert pcc.alloc_failure_countdown() == 7
+    pcc.inject_alloc_failure(-1)
+    assert pcc.alloc_failure_countdown() < 0
+    with pytest.raises(pcc.PccError):
+        pcc.inject_alloc_failure(-5)
