@@ -194,11 +194,16 @@ __constant__ int8_t kFwd[13][3] = {{1, 0, 0},  {-1, 1, 0}, {0, 1, 0},  {1, 1, 0}
                                    {0, -1, 1}, {1, -1, 1}, {-1, 0, 1}, {0, 0, 1},  {1, 0, 1},
                                    {-1, 1, 1}, {0, 1, 1},  {1, 1, 1}};
 
+// One thread per (cell, forward offset): the 13 binary searches of a cell
+// run in parallel threads instead of one after another.
 __global__ void k_neighbors(const JobDev *jobs, const uint32_t *cell_base, int njobs,
                             const uint32_t *cell_key, const uint32_t *n_cells, int32_t *nbr) {
   const uint32_t U = *n_cells;
-  for (size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x; u < U;
-       u += (size_t)gridDim.x * blockDim.x) {
+  const size_t total = (size_t)U * 13;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (size_t)gridDim.x * blockDim.x) {
+    const size_t u = t / 13;
+    const int s = (int)(t - u * 13);
     const uint32_t key = cell_key[u];
     // job whose key range holds this cell
     int lo = 0, hi = njobs - 1;
@@ -214,35 +219,33 @@ __global__ void k_neighbors(const JobDev *jobs, const uint32_t *cell_base, int n
     const int64_t c[3] = {(int64_t)(local % (uint32_t)J.nc[0]),
                           (int64_t)((local / (uint32_t)J.nc[0]) % (uint32_t)J.nc[1]),
                           (int64_t)(local / ((uint32_t)J.nc[0] * (uint32_t)J.nc[1]))};
-    for (int s = 0; s < 13; ++s) {
-      int64_t q[3];
-      bool ok = true;
+    int64_t q[3];
+    bool ok = true;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        q[a] = c[a] + kFwd[s][a];
-        const int nc = J.nc[a];
-        if (q[a] < 0 || q[a] >= nc) {
-          if (((J.periodic >> a) & 1) && nc >= 3)
-            q[a] = (q[a] + nc) % nc;
-          else
-            ok = false;
-        }
+    for (int a = 0; a < 3; ++a) {
+      q[a] = c[a] + kFwd[s][a];
+      const int nc = J.nc[a];
+      if (q[a] < 0 || q[a] >= nc) {
+        if (((J.periodic >> a) & 1) && nc >= 3)
+          q[a] = (q[a] + nc) % nc;
+        else
+          ok = false;
       }
-      int32_t found = -1;
-      if (ok) {
-        const uint32_t want = J.cell_base + (uint32_t)((q[2] * J.nc[1] + q[1]) * J.nc[0] + q[0]);
-        uint32_t a = 0, b = U;
-        while (a < b) {
-          uint32_t m = (a + b) >> 1;
-          if (cell_key[m] < want)
-            a = m + 1;
-          else
-            b = m;
-        }
-        if (a < U && cell_key[a] == want) found = (int32_t)a;
-      }
-      nbr[u * 13 + s] = found;
     }
+    int32_t found = -1;
+    if (ok) {
+      const uint32_t want = J.cell_base + (uint32_t)((q[2] * J.nc[1] + q[1]) * J.nc[0] + q[0]);
+      uint32_t a = 0, b = U;
+      while (a < b) {
+        uint32_t m = (a + b) >> 1;
+        if (cell_key[m] < want)
+          a = m + 1;
+        else
+          b = m;
+      }
+      if (a < U && cell_key[a] == want) found = (int32_t)a;
+    }
+    nbr[t] = found;
   }
 }
 
@@ -250,8 +253,8 @@ void launch_neighbors(const JobDev *jobs, const uint32_t *cell_base, int njobs,
                       const uint32_t *cell_key, const uint32_t *n_cells, size_t max_cells,
                       int32_t *nbr, hipStream_t s) {
   if (max_cells)
-    k_neighbors<<<blocks_for(max_cells, 256, 65536), 256, 0, s>>>(jobs, cell_base, njobs, cell_key,
-                                                                  n_cells, nbr);
+    k_neighbors<<<blocks_for(max_cells * 13, 256, 65536), 256, 0, s>>>(jobs, cell_base, njobs,
+                                                                       cell_key, n_cells, nbr);
 }
 
 }  // namespace pcc

@@ -681,10 +681,30 @@ void launch_flatten(uint32_t *par, size_t n, hipStream_t s) {
 }
 
 // canonical label: the smallest job-local index of the component
+// Smallest job-local index per component.  Sorted neighbours mostly share
+// their root, and many atomics on one address serialise: a segmented
+// minimum over runs of lanes with equal roots leaves one atomic per run (the
+// run's last lane), and a read of the current minimum skips atomics that
+// cannot lower it.
 __global__ void k_minid(const uint32_t *root, const float4 *pos, size_t n, uint32_t *minid) {
-  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
-       k += (size_t)gridDim.x * blockDim.x)
-    atomicMin(minid + root[k], __float_as_uint(pos[k].w));
+  const int lane = threadIdx.x & 63;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  // the loop runs the same number of times in every lane of a wave
+  for (size_t base = (size_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < n;
+       base += stride) {
+    const size_t k = base + lane;
+    const bool valid = k < n;
+    const uint32_t r = valid ? root[k] : 0xffffffffu;
+    uint32_t id = valid ? __float_as_uint(pos[k].w) : 0xffffffffu;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t r2 = __shfl_up(r, d, 64), id2 = __shfl_up(id, d, 64);
+      if (lane >= d && r2 == r) id = id2 < id ? id2 : id;
+    }
+    const uint32_t rn = __shfl_down(r, 1, 64);
+    const bool tail = valid && (lane == 63 || k + 1 >= n || rn != r);
+    if (tail && id < minid[r]) atomicMin(minid + r, id);
+  }
 }
 __global__ void k_labels(const uint32_t *root, const float4 *pos, const int64_t *p_off, int njobs,
                          size_t n, const uint32_t *minid, int32_t *lab) {

@@ -14,7 +14,7 @@ namespace pcc {
 
 namespace {
 
-constexpr int64_t kTileInputs = 1 << 16;
+constexpr int64_t kTileInputs = 1 << 13;  // 2048 blocks for 16.8M inputs
 constexpr int kGraphIters = 8;
 
 double ulp_f32(double a) {
