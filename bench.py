@@ -381,11 +381,14 @@ def main():
         desc += "; corrected at linking lengths %s at once" % ",".join("%g" % v for v in bs)
 
     def step(mode=args.mode, **kw):
+        if args.max_iters and "max_iters" not in kw:
+            kw["max_iters"] = args.max_iters
         if bs:
             return ctx.correct_multi(o, r, bs, w.xi, mode=mode, box=w.box, **kw)
         return ctx.correct(o, r, w.b, w.xi, mode=mode, box=w.box, **kw)
 
-    tjob = dict(orig=o, recon=r, b=w.b, xi=w.xi, mode=args.mode, box=w.box)
+    tjob = dict(orig=o, recon=r, b=w.b, xi=w.xi, mode=args.mode, box=w.box,
+                opts={"max_iters": args.max_iters} if args.max_iters else {})
     tuned = tune(ctx, [tjob], args) if not bs else None
     for k in range(args.warmup):
         t = time.perf_counter()
@@ -436,7 +439,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded generator; no dataset)",
         "config": {"workload": desc, "n": w.n, "mode": args.mode, "b": bs or w.b, "xi": w.xi,
-                   "parallelism": "single GPU"},
+                   "max_iters": args.max_iters or None, "parallelism": "single GPU"},
         "status": last["status"], "iters": last["iters"], "n_active": last["n_active"],
         "n_editable": last["n_editable"], "n_flagged": last["n_flagged"],
         "pgd_rows_evaluated": last["pgd_rows_evaluated"],
@@ -445,6 +448,9 @@ def main():
         "autotune": tuned,
         "stage_ms": {k: round(v, 3) for k, v in last["t_stage_ms"].items()},
         "kernel_ms_per_step": {k: round(v / len(stats), 3) for k, v in kms.items()},
+        # algorithmic GB/s of every kernel whose bytes per unit are defined
+        "kernel_gbs": {k: round(sum(kernel_bytes(k, s, w.n) for s in stats) / (kms[k] / 1e3) / 1e9, 1)
+                       for k in kms if kms[k] > 0 and kernel_bytes(k, stats[0], w.n) is not None},
         "roofline": roofline,
     }
     if probe:

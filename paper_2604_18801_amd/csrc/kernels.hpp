@@ -75,6 +75,9 @@ struct PairPlan {
 void plan_pairs(PairPlan &pl, const uint32_t *cell_of, const uint32_t *cell_start,
                 const int32_t *nbr, const uint32_t *n_cells, size_t n, uint32_t dense, Arena &ar,
                 hipStream_t s);
+// the plan without the sparse homes that found no vulnerable pair in pass 1
+void plan_vulnerable(const PairPlan &pl, const uint32_t *cnt_pb, const uint32_t *cnt_pc,
+                     PairPlan &out, Arena &ar, hipStream_t s);
 void launch_pair_pass1(const PairBufs &b, const PairPlan &pl, hipStream_t s);  // classify, hook
 void launch_pair_count(const PairBufs &b, const PairPlan &pl, hipStream_t s);  // filtered counts
 void launch_pair_write(const PairBufs &b, const PairPlan &pl, hipStream_t s);  // filtered writes

@@ -510,10 +510,12 @@ __global__ void k_sparse_flags(const uint32_t *cell_of, const uint32_t *cell_sta
     flag[k] = (cell_start[c + 1] - cell_start[c]) < dense ? 1 : 0;
   }
 }
-__global__ void k_sparse_list(const uint8_t *flag, const uint32_t *pos32, size_t n, uint32_t *list) {
+// list[pos32[k]] = src ? src[k] : k for every flagged k (order kept)
+__global__ void k_sparse_list(const uint8_t *flag, const uint32_t *pos32, size_t n,
+                              const uint32_t *src, uint32_t *list) {
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
        k += (size_t)gridDim.x * blockDim.x)
-    if (flag[k]) list[pos32[k]] = (uint32_t)k;
+    if (flag[k]) list[pos32[k]] = src ? src[k] : (uint32_t)k;
 }
 // Bucket of a sparse particle by the number of particles in its cell and its
 // 13 forward cells (the candidates it examines), doubling ranges, heaviest
@@ -572,7 +574,7 @@ void plan_pairs(PairPlan &pl, const uint32_t *cell_of, const uint32_t *cell_star
   if (n) {
     k_sparse_flags<<<nb, 256, 0, s>>>(cell_of, cell_start, n, dense, flag);
     scan_u8_u32(flag, pos32, n, cnt, ar, s);
-    k_sparse_list<<<nb, 256, 0, s>>>(flag, pos32, n, pl.sparse);
+    k_sparse_list<<<nb, 256, 0, s>>>(flag, pos32, n, nullptr, pl.sparse);
     // heaviest cells first, a cell's particles together and in index order
     uint32_t ns = 0;
     PCC_HIP(hipMemcpyAsync(&ns, cnt, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -608,6 +610,35 @@ static void launch_pairs(const PairBufs &b, const PairPlan &pl, hipStream_t s) {
     else
       k_pairs_dense<PASS><<<nb, 64 * kPairWaves, 0, s>>>(b, pl.ucell, pl.uchunk, pl.n_units);
   }
+}
+
+// Sparse homes that found a vulnerable pair in pass 1 (the count and write
+// passes see no other pairs, so a home without one writes nothing).
+__global__ void k_vul_flags(const uint32_t *list, size_t m, const uint32_t *cnt_pb,
+                            const uint32_t *cnt_pc, uint8_t *flag) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t k = list[i];
+    flag[i] = (cnt_pb[k] | cnt_pc[k]) != 0u ? 1 : 0;
+  }
+}
+
+void plan_vulnerable(const PairPlan &pl, const uint32_t *cnt_pb, const uint32_t *cnt_pc,
+                     PairPlan &out, Arena &ar, hipStream_t s) {
+  out = pl;
+  if (pl.n_sparse == 0) return;
+  const size_t m = pl.n_sparse;
+  uint8_t *flag = ar.get<uint8_t>(m);
+  uint32_t *pos32 = ar.get<uint32_t>(m), *cnt = ar.get<uint32_t>(1);
+  out.sparse = ar.get<uint32_t>(m);
+  const int nb = blocks_for(m, 256, 65536);
+  k_vul_flags<<<nb, 256, 0, s>>>(pl.sparse, m, cnt_pb, cnt_pc, flag);
+  scan_u8_u32(flag, pos32, m, cnt, ar, s);
+  k_sparse_list<<<nb, 256, 0, s>>>(flag, pos32, m, pl.sparse, out.sparse);
+  uint32_t h = 0;
+  PCC_HIP(hipMemcpyAsync(&h, cnt, sizeof h, hipMemcpyDeviceToHost, s));
+  PCC_HIP(hipStreamSynchronize(s));
+  out.n_sparse = h;
 }
 
 void launch_pair_pass1(const PairBufs &b, const PairPlan &pl, hipStream_t s) {

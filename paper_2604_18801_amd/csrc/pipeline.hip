@@ -360,6 +360,19 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   Staging st{C, s};
   for (int k = 0; k < 12; ++k)
     if (!C.ev[k]) PCC_HIP(hipEventCreate(&C.ev[k]));
+  // stage boundary k; with PCC_VERBOSE set, waits for the stage and prints
+  // the wall time since the call started (diagnostics only)
+  const bool verbose = getenv("PCC_VERBOSE") != nullptr;
+  auto mark = [&](int k, const char *done) {
+    PCC_HIP(hipEventRecord(C.ev[k], s));
+    if (verbose) {
+      PCC_HIP(hipStreamSynchronize(s));
+      fprintf(stderr, "[pcc] %s: %.1f ms\n", done,
+              std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_wall0)
+                  .count());
+      fflush(stderr);
+    }
+  };
 
   std::vector<HostJob> all(njobs_in);
   for (int k = 0; k < njobs_in; ++k) {
@@ -565,7 +578,7 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   PCC_HIP(hipMemcpyAsync(d_poff, p_off.data(), (J + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
   PCC_HIP(hipMemcpyAsync(d_cbase, cbase.data(), (J + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s));
   const size_t n = (size_t)N;
-  PCC_HIP(hipEventRecord(C.ev[1], s));
+  mark(1, "input scan");
 
   // ------------------------------------------------------------------
   // cell build
@@ -587,7 +600,7 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   launch_neighbors(d_jobs, d_cbase, J, cell_key, n_cells, n, nbr, s);
   PairPlan plan;
   plan_pairs(plan, cell_of, cell_start, nbr, n_cells, n, (uint32_t)C.dense_cell, ar, s);
-  PCC_HIP(hipEventRecord(C.ev[2], s));
+  mark(2, "cell build");
 
   // ------------------------------------------------------------------
   // pair pass 1: classify, hook the safe and FoF union-finds, count V
@@ -622,7 +635,7 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   }
   launch_flatten(pb.safe_par, n, s);
   launch_flatten(pb.fof_par, n, s);
-  PCC_HIP(hipEventRecord(C.ev[3], s));
+  mark(3, "pair pass");
 
   // labels in each job's particle order
   int32_t *lab = dev<int32_t>(ar, n);
@@ -647,7 +660,7 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
     S.n_pc = (int64_t)c[2];
     S.n_pairs = S.n_safe + S.n_pb + S.n_pc;
   }
-  PCC_HIP(hipEventRecord(C.ev[4], s));
+  mark(4, "labels");
   if (labels_only) {
     PCC_HIP(hipStreamSynchronize(s));
     for (auto *h : act) res[h->index].stats = h->st;
@@ -669,6 +682,12 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   // pass of its own first.
   uint32_t *cap_a = dev<uint32_t>(ar, n), *cap_f = dev<uint32_t>(ar, n);
   pair_slot_caps(pb, cap_a, cap_f, s);
+  // the count and write passes skip sparse homes without a vulnerable pair;
+  // their fills stay zero
+  PairPlan vplan;
+  plan_vulnerable(plan, pb.cnt_pb, pb.cnt_pc, vplan, ar, s);
+  fill_u32(pb.cnt_a, 0, n, s);
+  fill_u32(pb.cnt_f, 0, n, s);
   uint64_t *off_a = dev<uint64_t>(ar, n), *off_f = dev<uint64_t>(ar, n);
   uint64_t *tot = dev<uint64_t>(ar, 3);
   scan_u32_u64(cap_a, off_a, n, tot, ar, s);
@@ -696,7 +715,7 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
     pb.f_v = dev<uint32_t>(ar, nf);
     {
       const int at = kt.start(2, s);
-      launch_pair_write(pb, plan, s);
+      launch_pair_write(pb, vplan, s);
       kt.stop(at, s);
     }
     uint64_t *off_d = dev<uint64_t>(ar, n);
@@ -718,7 +737,7 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   } else {
     if (!all_vp) {
       const int at = kt.start(1, s);
-      launch_pair_count(pb, plan, s);
+      launch_pair_count(pb, vplan, s);
       kt.stop(at, s);
     } else {
       // VP keeps every vulnerable pair and no forest candidate
@@ -740,7 +759,7 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
     pb.f_u = dev<uint32_t>(ar, nf);
     pb.f_v = dev<uint32_t>(ar, nf);
     const int at = kt.start(2, s);
-    launch_pair_write(pb, plan, s);
+    launch_pair_write(pb, vplan, s);
     kt.stop(at, s);
   }
   if (getenv("PCC_VERBOSE"))
@@ -762,7 +781,7 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
     a_k = dev<uint8_t>(ar, na ? na : 1);
     remap_thresholds(a_i, a_j, na, pos, inv_perm, d_poff, J, a_k, s);
   }
-  PCC_HIP(hipEventRecord(C.ev[5], s));
+  mark(5, "selection");
 
   // ------------------------------------------------------------------
   // editable set and incidence lists
@@ -806,7 +825,7 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
       act[q]->st.n_active = ((int64_t)rp[q + 1] - (int64_t)rp[q]) / 2;
     }
   }
-  PCC_HIP(hipEventRecord(C.ev[6], s));
+  mark(6, "editable set and CSR");
 
   // ------------------------------------------------------------------
   // PGD: K fused iterations per graph launch, then one small readback
@@ -886,11 +905,16 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
     int32_t *h_act = (int32_t *)st.get(sizeof(int32_t));
     try {
       int at = -1;  // events of the last replay, when timed
-      for (;;) {
+      for (int64_t replay = 0;; ++replay) {
         PCC_HIP(hipMemcpyAsync(h_act, gb.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         PCC_HIP(hipStreamSynchronize(s));
         if (at >= 0) kt.add_split(3, at, K);
         if (*h_act <= 0) break;
+        if (verbose && replay > 0 && (replay & (replay - 1)) == 0) {
+          fprintf(stderr, "[pcc] PGD: %lld graph launches of %d steps, %d jobs active\n",
+                  (long long)replay, K, *h_act);
+          fflush(stderr);
+        }
         at = kt.bracket_begin(s);
         PCC_HIP(hipGraphLaunch(exec, s));
         kt.bracket_end(at, s);
@@ -917,7 +941,7 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
     S.pgd_incidences_evaluated = (int64_t)lp[q].inc_eval;
     act[q]->status = lp[q].status ? PCC_NOT_CONVERGED : PCC_OK;
   }
-  PCC_HIP(hipEventRecord(C.ev[7], s));
+  mark(7, "PGD");
 
   // ------------------------------------------------------------------
   // edit encoding on the device
@@ -1011,7 +1035,7 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
       eb.debug = dbg;
       launch_debug_xyz(eb, s);
     }
-    PCC_HIP(hipEventRecord(C.ev[8], s));
+    mark(8, "device encoding");
     // device -> host: flag bytes and bitstreams of all jobs in one copy each
     const size_t fbytes_n = fb[J], words_n = w0[J];
     std::vector<uint8_t> hflags(fbytes_n);

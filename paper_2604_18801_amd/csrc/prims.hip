@@ -30,8 +30,11 @@ void Arena::release() {
 void Arena::reset() {
   size_t total = 0;
   for (auto &c : chunks_) total += c.size;
-  if (chunks_.size() > 1) {
-    // consolidate into one chunk big enough for the previous call
+  // Consolidate into one chunk big enough for the previous call, unless that
+  // is huge: freeing and mapping tens of GB again costs seconds, and a call
+  // of the same size fills the chunks it left behind in the same order
+  // without allocating.
+  if (chunks_.size() > 1 && total <= ((size_t)16 << 30)) {
     release();
     void *p = nullptr;
     if (hipMalloc(&p, total) == hipSuccess) chunks_.push_back({(char *)p, total, 0});
