@@ -372,6 +372,10 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
   __shared__ uint32_t s_vb[kPgdWaves][64];  // first slot of each row in the tile's work list
   __shared__ uint32_t s_e[kPgdWaves][64];   // row index
   __shared__ uint8_t s_mk[kPgdWaves][64];   // the row marks its partners hot
+  // loss thresholds b -+ delta_t and their squares per linking length of a
+  // multi-threshold job (read from LDS: a memory load in the evaluation
+  // would make the gathers already in flight complete first)
+  __shared__ double s_thr[kPgdWaves][4][kMaxThresholds];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t nwaves = (int64_t)gridDim.x * kPgdWaves;
   unsigned long long viol = 0, lossq = 0;
@@ -421,6 +425,11 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
     s_rp[w][lane] = q0;
     s_vb[w][lane] = vb;
     s_e[w][lane] = (uint32_t)e;
+    if (J.nthr > 1 && lane < 4 * kMaxThresholds) {
+      const int a = lane / kMaxThresholds, k = lane % kMaxThresholds;
+      const double *src = a == 0 ? J.thr_bm : a == 1 ? J.thr_bp : a == 2 ? J.thr_bm2 : J.thr_bp2;
+      s_thr[w][a][k] = src[k];
+    }
     wave_sync();
     double gx = 0.0, gy = 0.0, gz = 0.0;
     bool hrow = false;  // some constraint of the row is violated
@@ -478,11 +487,11 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
         const bool created = (col & kColPc) != 0;
         const uint32_t kk = (col >> kColThrShift) & 7u;
         double t2 = created ? bp2 : bm2;
-        if (kk) t2 = created ? J.thr_bp2[kk] : J.thr_bm2[kk];
+        if (kk) t2 = s_thr[w][created ? 3 : 2][kk];
         double h = 0.0;
         if (created ? d2 <= t2 : d2 > t2) {
           double t1 = created ? bp : bm;
-          if (kk) t1 = created ? J.thr_bp[kk] : J.thr_bm[kk];
+          if (kk) t1 = s_thr[w][created ? 1 : 0][kk];
           const double d = sqrt(d2);
           if (!created) {
             // potentially broken: an original link pulled back inside b - delta_t
