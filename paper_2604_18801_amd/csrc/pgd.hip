@@ -559,6 +559,12 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
         vo[k] = B.v[(size_t)k * B.ne + e];
       }
       const double bc1 = B.loop[job].bc1, bc2 = B.loop[job].bc2;
+      // the step's constants, read once: the compiler must assume that the
+      // moment stores below may alias the job table, and would load them
+      // again (and wait for the load) for every coordinate
+      const int opt = J.optimizer;
+      const double lr = J.lr, beta1 = J.beta1, beta2 = J.beta2, omb1 = J.one_m_beta1,
+                   omb2 = J.one_m_beta2, aeps = J.adam_eps, xip = J.xi_p;
       const double g[3] = {gx, gy, gz};
       const double p[3] = {s_px[w][lane], s_py[w][lane], s_pz[w][lane]};
       const double xs[3] = {(double)x.x, (double)x.y, (double)x.z};
@@ -568,20 +574,20 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         double r;
-        if (J.optimizer == 1) {
-          r = p[k] - J.lr * g[k];
+        if (opt == 1) {
+          r = p[k] - lr * g[k];
         } else {
           const size_t ia = (size_t)k * B.ne + e;
-          const double m = J.beta1 * mo[k] + J.one_m_beta1 * g[k];
-          const double v = J.beta2 * vo[k] + J.one_m_beta2 * g[k] * g[k];
+          const double m = beta1 * mo[k] + omb1 * g[k];
+          const double v = beta2 * vo[k] + omb2 * g[k] * g[k];
           B.m[ia] = m;
           B.v[ia] = v;
           state |= dbits(m) | dbits(v);
           const double mh = m / bc1;
           const double vh = v / bc2;
-          r = p[k] - J.lr * mh / (sqrt(vh) + J.adam_eps);
+          r = p[k] - lr * mh / (sqrt(vh) + aeps);
         }
-        np[k] = fmin(fmax(r, xs[k] - J.xi_p), xs[k] + J.xi_p);
+        np[k] = fmin(fmax(r, xs[k] - xip), xs[k] + xip);
         moved |= dbits(np[k]) != dbits(p[k]);
         // one coordinate at a time: interleaving the three divide and
         // square-root sequences costs registers, hence occupancy
