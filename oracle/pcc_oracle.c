@@ -11,6 +11,7 @@
 
 #include <dlfcn.h>
 #include <math.h>
+#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -520,6 +521,11 @@ static int64_t pgd(int64_t na, const uint32_t *a_i, const uint32_t *a_j,
   r->loss_hist = (double *)xmalloc(sizeof(double) * (size_t)cap);
   r->viol_hist = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)cap);
   int64_t t = 0;
+  /* optional plateau rule (not in the paper, whose step size is fixed): the
+     lowest violation count so far, the evaluations since it was reached,
+     and the power-of-two factor applied to alpha */
+  int64_t best = INT64_MAX, stall = 0;
+  double scale = 1.0;
   for (;;) {
     orc_eval ev = evaluate(na, a_i, a_j, a_type, a_thr, eidx, q, g, ne, xyz, box, c);
     if (t + 1 > cap) {
@@ -544,6 +550,16 @@ static int64_t pgd(int64_t na, const uint32_t *a_i, const uint32_t *a_j,
       r->status = ORC_NOT_CONVERGED;
       break;
     }
+    if (p->lr_patience > 0) {
+      if (ev.viol < best) {
+        best = ev.viol;
+        stall = 0;
+      } else if (++stall >= p->lr_patience) {
+        scale *= 0.5;
+        stall = 0;
+      }
+    }
+    const double lr = p->lr * scale;
     t++;
     double bc1 = 1.0 - pow(p->beta1, (double)t);
     double bc2 = 1.0 - pow(p->beta2, (double)t);
@@ -551,13 +567,13 @@ static int64_t pgd(int64_t na, const uint32_t *a_i, const uint32_t *a_j,
       for (int64_t e = 0; e < ne; e++) {
         double gr = g[a][e];
         if (p->optimizer == ORC_SGD) {
-          q[a][e] = q[a][e] - p->lr * gr;
+          q[a][e] = q[a][e] - lr * gr;
         } else {
           m[a][e] = p->beta1 * m[a][e] + (1.0 - p->beta1) * gr;
           v[a][e] = p->beta2 * v[a][e] + (1.0 - p->beta2) * gr * gr;
           double mh = m[a][e] / bc1;
           double vh = v[a][e] / bc2;
-          q[a][e] = q[a][e] - p->lr * mh / (sqrt(vh) + p->adam_eps);
+          q[a][e] = q[a][e] - lr * mh / (sqrt(vh) + p->adam_eps);
         }
         q[a][e] = fmin(fmax(q[a][e], lo[a][e]), hi[a][e]);
       }

@@ -20,7 +20,7 @@ def _two(x0, x1, r0, r1):
 
 
 def _scalar_run(x0, x1, r0, r1, b, xi, kind, steps, opt="adam", lr=1e-3,
-                b1=0.9, b2=0.999, eps=1e-8):
+                b1=0.9, b2=0.999, eps=1e-8, patience=0):
     """1-D, two particles, particle 1 to the right of particle 0.
     kind 'pb': pull together while the gap exceeds b - delta_t;
     kind 'pc': push apart while the gap is at most b + delta_t."""
@@ -32,6 +32,7 @@ def _scalar_run(x0, x1, r0, r1, b, xi, kind, steps, opt="adam", lr=1e-3,
     v = [0.0, 0.0]
     t = 0
     traj = [list(q)]
+    best, stall, scale = None, 0, 1.0
     while t < steps:
         gap = q[1] - q[0]
         if kind == "pb":
@@ -45,16 +46,26 @@ def _scalar_run(x0, x1, r0, r1, b, xi, kind, steps, opt="adam", lr=1e-3,
             h = c["bp"] - abs(gap)
             s = 1.0 if gap > 0 else (-1.0 if gap < 0 else 1.0)
             g = [2.0 * h * s, -2.0 * h * s]
+        # plateau rule: one violated pair per evaluation here, so alpha is
+        # halved after every `patience` evaluations that follow the first
+        if patience > 0:
+            if best is None:
+                best, stall = 1, 0
+            else:
+                stall += 1
+                if stall >= patience:
+                    scale, stall = scale * 0.5, 0
+        step = lr * scale
         t += 1
         for k in range(2):
             if opt == "sgd":
-                q[k] = q[k] - lr * g[k]
+                q[k] = q[k] - step * g[k]
             else:
                 m[k] = b1 * m[k] + (1.0 - b1) * g[k]
                 v[k] = b2 * v[k] + (1.0 - b2) * g[k] * g[k]
                 mh = m[k] / (1.0 - math.pow(b1, t))
                 vh = v[k] / (1.0 - math.pow(b2, t))
-                q[k] = q[k] - lr * mh / (math.sqrt(vh) + eps)
+                q[k] = q[k] - step * mh / (math.sqrt(vh) + eps)
             q[k] = min(max(q[k], lo[k]), hi[k])
         traj.append(list(q))
     return traj, t
@@ -75,6 +86,32 @@ def test_two_particle_pull_together(opt):
     r = oracle.correct(orig, rec, b, xi, mode="vp", optimizer=opt, lr=lr)
     assert r.status == 0 and r.iters == steps
     assert len(r.loss_hist) == steps + 1 and r.viol_hist[-1] == 0
+
+
+@pytest.mark.parametrize("opt", ["adam", "sgd"])
+def test_plateau_rule_halves_the_step(opt):
+    # the optional plateau rule against the scalar recurrence (one violated
+    # pair: alpha halves every `patience` evaluations until it is satisfied);
+    # a patience longer than the run leaves the paper's trajectory unchanged
+    x0, x1, r0, r1 = 0.0, 0.2421875, -0.015625, 0.2578125
+    b, xi = 0.25, 0.02
+    lr = 1e-3 if opt == "adam" else 2e-2
+    plain, psteps = _scalar_run(x0, x1, r0, r1, b, xi, "pb", 20000, opt=opt, lr=lr)
+    patience = 2 * psteps // 3 + 1
+    traj, steps = _scalar_run(x0, x1, r0, r1, b, xi, "pb", 20000, opt=opt, lr=lr,
+                              patience=patience)
+    assert 20000 > steps > psteps > 3
+    orig, rec = _two(x0, x1, r0, r1)
+    for k in sorted({1, patience, patience + 1, steps // 2, steps}):
+        r = oracle.correct(orig, rec, b, xi, mode="vp", max_iters=k, optimizer=opt, lr=lr,
+                           lr_patience=patience)
+        np.testing.assert_allclose(r.p[0], traj[k], rtol=0, atol=1e-15)
+    r = oracle.correct(orig, rec, b, xi, mode="vp", optimizer=opt, lr=lr, lr_patience=patience)
+    assert r.status == 0 and r.iters == steps
+    a = oracle.correct(orig, rec, b, xi, mode="vp", optimizer=opt, lr=lr, lr_patience=10 ** 6)
+    z = oracle.correct(orig, rec, b, xi, mode="vp", optimizer=opt, lr=lr)
+    np.testing.assert_array_equal(a.p, z.p)
+    assert a.iters == z.iters == psteps
 
 
 def test_first_adam_step_closed_form():
