@@ -47,7 +47,9 @@ def _scalar_run(x0, x1, r0, r1, b, xi, kind, steps, opt="adam", lr=1e-3,
             s = 1.0 if gap > 0 else (-1.0 if gap < 0 else 1.0)
             g = [2.0 * h * s, -2.0 * h * s]
         # plateau rule: one violated pair per evaluation here, so alpha is
-        # halved after every `patience` evaluations that follow the first
+        # halved after every `patience` evaluations that follow the first;
+        # the verdict of this evaluation applies from the next step on
+        step = lr * scale
         if patience > 0:
             if best is None:
                 best, stall = 1, 0
@@ -55,7 +57,6 @@ def _scalar_run(x0, x1, r0, r1, b, xi, kind, steps, opt="adam", lr=1e-3,
                 stall += 1
                 if stall >= patience:
                     scale, stall = scale * 0.5, 0
-        step = lr * scale
         t += 1
         for k in range(2):
             if opt == "sgd":
