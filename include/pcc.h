@@ -91,6 +91,11 @@ typedef struct {
                             violated, > 0 stops when the tightened loss of
                             Eq. 3 is <= loss_tol */
   double box[3];         /* periodic side per axis; 0 = open axis (default) */
+  int64_t lr_patience;   /* > 0: halve the step size after this many
+                            consecutive evaluations without a new minimum of
+                            the violation count (a damping of the fixed-step
+                            oscillation at loose bounds; not in the paper);
+                            0 (default): the paper's fixed step */
 } pcc_params;
 
 /* Caller-allocated outputs of one correction. */

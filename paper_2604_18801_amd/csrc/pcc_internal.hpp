@@ -61,6 +61,7 @@ struct JobDev {
   double loss_scale;           // fixed-point scale of the loss accumulator
   const double2 *bc_tab;       // [t] = (1 - beta1^t, 1 - beta2^t), t = 0 .. max_iters + 1
   int64_t max_iters;
+  int64_t lr_patience;  // > 0: halve alpha after this many evaluations without a new minimum
   double loss_tol;
   int32_t optimizer;
   int32_t m_bits;
@@ -85,6 +86,11 @@ struct JobLoop {
   unsigned long long rows_eval, inc_eval;  // rows and incidences evaluated, all steps
   int32_t have0;
   int32_t pad;
+  // plateau rule: factor on alpha, lowest violation count so far and the
+  // evaluations since it was reached
+  double lr_scale;
+  unsigned long long best_viol;
+  int64_t stall;
 };
 
 // Device helper: the job that owns global index g, by binary search in

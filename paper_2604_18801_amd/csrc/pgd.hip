@@ -282,6 +282,8 @@ __global__ void k_loop_init(const JobDev *jobs, JobLoop *loop, int njobs, int32_
   JobLoop L = {};
   L.bc1 = jobs[j].bc_tab[1].x;
   L.bc2 = jobs[j].bc_tab[1].y;
+  L.lr_scale = 1.0;
+  L.best_viol = ~0ull;
   loop[j] = L;
 }
 
@@ -563,7 +565,8 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
       // moment stores below may alias the job table, and would load them
       // again (and wait for the load) for every coordinate
       const int opt = J.optimizer;
-      const double lr = J.lr, beta1 = J.beta1, beta2 = J.beta2, omb1 = J.one_m_beta1,
+      const double lr = J.lr * B.loop[job].lr_scale, beta1 = J.beta1, beta2 = J.beta2,
+                   omb1 = J.one_m_beta1,
                    omb2 = J.one_m_beta2, aeps = J.adam_eps, xip = J.xi_p;
       const double g[3] = {gx, gy, gz};
       const double p[3] = {s_px[w][lane], s_py[w][lane], s_pz[w][lane]};
@@ -825,6 +828,17 @@ __global__ void k_pgd_finalize(PgdBufs B) {
     L.status = conv ? 0 : 1;
     atomicSub(B.n_active, 1);
     return;
+  }
+  // optional plateau rule: halve alpha after lr_patience evaluations
+  // without a new minimum of the violation count
+  if (J.lr_patience > 0) {
+    if (viol < L.best_viol) {
+      L.best_viol = viol;
+      L.stall = 0;
+    } else if (++L.stall >= J.lr_patience) {
+      L.lr_scale *= 0.5;
+      L.stall = 0;
+    }
   }
   // rows that became hot in this step join the next one (the worklist of
   // the first step is replaced by the compaction that follows it)

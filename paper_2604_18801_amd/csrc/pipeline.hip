@@ -52,6 +52,7 @@ int check_params(const pcc_job &j, std::string &err) {
   if (!(p.beta1 >= 0 && p.beta1 < 1 && p.beta2 >= 0 && p.beta2 < 1))
     return err = "Adam betas must lie in [0, 1)", -1;
   if (!(finite(p.loss_tol) && p.loss_tol >= 0)) return err = "loss_tol must be >= 0", -1;
+  if (p.lr_patience < 0) return err = "lr_patience must be >= 0", -1;
   for (int a = 0; a < 3; ++a)
     if (!(finite(p.box[a]) && p.box[a] >= 0)) return err = "box sides must be finite and >= 0", -1;
   if (j.orig.n != j.recon.n) return err = "orig and recon differ in size", -1;
@@ -108,6 +109,7 @@ int job_constants(const pcc_params &p, const ScanPart &agg, int64_t n, int cell_
   J.thr_bm2[0] = J.bm2;
   J.thr_bp2[0] = J.bp2;
   J.max_iters = p.max_iters > 0 ? p.max_iters : 100000;
+  J.lr_patience = p.lr_patience;
   J.loss_tol = p.loss_tol;
   J.optimizer = p.optimizer;
   J.m_bits = p.m_bits;

@@ -263,3 +263,17 @@ def test_slotted_and_exact_pair_paths_agree(ctx, mode):
     for a, b in zip(p1, p2):
         np.testing.assert_array_equal(a, b)
     assert st1["iters"] == st2["iters"] and st1["n_active"] == st2["n_active"]
+
+
+@pytest.mark.parametrize("patience", [4, 5])
+def test_plateau_rule_is_bitwise_the_oracles(ctx, patience):
+    # optional step-size halving after `patience` evaluations without a new
+    # minimum of the violation count: the same decisions and iterates
+    w = synth.cosmology(16, seed=3, xi=0.05)
+    kw = dict(lr_patience=patience, max_iters=400)
+    ref = oracle.correct(w.orig, w.recon, w.b, w.xi, mode="hf", box=w.box, **kw)
+    _, lab, st = _run(ctx, w, "hf", **kw)
+    assert st["iters"] == ref.iters and st["status"] == ref.status
+    np.testing.assert_array_equal(st["debug_xyz"], ref.p)
+    plain = oracle.correct(w.orig, w.recon, w.b, w.xi, mode="hf", box=w.box, max_iters=400)
+    assert plain.iters != ref.iters or not np.array_equal(plain.p, ref.p)
