@@ -44,7 +44,7 @@ def workload(name):
     raise SystemExit("unknown workload " + name)
 
 
-# algorithmic bytes of all launches of a kernel in one step (see DESIGN.md)
+# algorithmic bytes of all launches of a kernel in one step
 def kernel_bytes(name, st, n):
     if name == "pgd_step":
         # per evaluated row: position read and write (24 + 24 B), original
