@@ -100,3 +100,13 @@ def test_alloc_failure_hook_is_host_only():
     assert pcc.alloc_failure_countdown() < 0
     with pytest.raises(pcc.PccError):
         pcc.inject_alloc_failure(-5)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the benchmark measures one GPU; a request for more exits with a message
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
