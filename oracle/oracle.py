@@ -41,8 +41,7 @@ class _Params(C.Structure):
                 ("margin_policy", C.c_int32), ("lr", C.c_double),
                 ("beta1", C.c_double), ("beta2", C.c_double),
                 ("adam_eps", C.c_double), ("max_iters", C.c_int64),
-                ("loss_tol", C.c_double), ("box", C.c_double * 3),
-                ("lr_patience", C.c_int64)]
+                ("loss_tol", C.c_double), ("box", C.c_double * 3)]
 
 
 class _Consts(C.Structure):
@@ -129,7 +128,7 @@ def _box(box) -> C.Array:
 
 def _params(b, xi, mode=MODE_HF, m_bits=16, optimizer="adam", lr=1e-3, beta1=0.9,
             beta2=0.999, adam_eps=1e-8, max_iters=0, loss_tol=0.0, box=None,
-            margin="safe", lr_patience=0) -> _Params:
+            margin="safe") -> _Params:
     p = _Params()
     _load().orc_params_default(C.byref(p))
     p.b, p.xi = float(b), float(xi)
@@ -140,7 +139,6 @@ def _params(b, xi, mode=MODE_HF, m_bits=16, optimizer="adam", lr=1e-3, beta1=0.9
     p.lr, p.beta1, p.beta2, p.adam_eps = lr, beta1, beta2, adam_eps
     p.max_iters = int(max_iters)
     p.loss_tol = float(loss_tol)
-    p.lr_patience = int(lr_patience)
     for k, v in enumerate(box or (0.0, 0.0, 0.0)):
         p.box[k] = float(v)
     return p

@@ -521,14 +521,6 @@ static int64_t pgd(int64_t na, const uint32_t *a_i, const uint32_t *a_j,
   r->loss_hist = (double *)xmalloc(sizeof(double) * (size_t)cap);
   r->viol_hist = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)cap);
   int64_t t = 0;
-  /* optional plateau rule (not in the paper, whose step size is fixed): the
-     lowest violation count so far, the evaluations since it was reached,
-     and the power-of-two factor applied to alpha.  A factor decided after
-     evaluating iterate t applies from the step that leaves iterate t + 1
-     (a data-parallel step evaluates an iterate and moves it in one pass, so
-     its violation count is known only after that move). */
-  int64_t best = INT64_MAX, stall = 0;
-  double scale = 1.0;
   for (;;) {
     orc_eval ev = evaluate(na, a_i, a_j, a_type, a_thr, eidx, q, g, ne, xyz, box, c);
     if (t + 1 > cap) {
@@ -553,18 +545,7 @@ static int64_t pgd(int64_t na, const uint32_t *a_i, const uint32_t *a_j,
       r->status = ORC_NOT_CONVERGED;
       break;
     }
-    /* the step from this iterate uses the factor decided by the earlier
-       evaluations; this evaluation's verdict applies from the next step */
-    const double lr = p->lr * scale;
-    if (p->lr_patience > 0) {
-      if (ev.viol < best) {
-        best = ev.viol;
-        stall = 0;
-      } else if (++stall >= p->lr_patience) {
-        scale *= 0.5;
-        stall = 0;
-      }
-    }
+    const double lr = p->lr; /* the fixed step of Sec. 4.2 */
     t++;
     double bc1 = 1.0 - pow(p->beta1, (double)t);
     double bc2 = 1.0 - pow(p->beta2, (double)t);

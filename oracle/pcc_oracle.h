@@ -61,9 +61,6 @@ typedef struct {
   int64_t max_iters;   /* <= 0 selects the safety cap of 100000 */
   double loss_tol;     /* 0: stop when no active pair is violated */
   double box[3];       /* periodic side per axis, 0 = open axis */
-  int64_t lr_patience; /* > 0: halve the step size whenever this many
-                          consecutive evaluations bring no new minimum of the
-                          violation count (0: the paper's fixed step) */
 } orc_params;
 
 typedef struct {

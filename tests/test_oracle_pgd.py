@@ -20,10 +20,13 @@ def _two(x0, x1, r0, r1):
 
 
 def _scalar_run(x0, x1, r0, r1, b, xi, kind, steps, opt="adam", lr=1e-3,
-                b1=0.9, b2=0.999, eps=1e-8, patience=0):
+                b1=0.9, b2=0.999, eps=1e-8):
     """1-D, two particles, particle 1 to the right of particle 0.
     kind 'pb': pull together while the gap exceeds b - delta_t;
-    kind 'pc': push apart while the gap is at most b + delta_t."""
+    kind 'pc': push apart while the gap is at most b + delta_t.
+    Returns the iterates, the number of steps and the tightened loss of Eq. 3
+    at every evaluation (the squared overshoot of the one pair, 0 once it is
+    satisfied)."""
     c = oracle.constants(b, xi, maxabs=max(abs(x0), abs(x1), abs(r0), abs(r1)))
     q = [float(np.float32(r0)), float(np.float32(r1))]
     lo = [float(np.float32(x0)) - c["xi_p"], float(np.float32(x1)) - c["xi_p"]]
@@ -32,44 +35,34 @@ def _scalar_run(x0, x1, r0, r1, b, xi, kind, steps, opt="adam", lr=1e-3,
     v = [0.0, 0.0]
     t = 0
     traj = [list(q)]
-    best, stall, scale = None, 0, 1.0
-    while t < steps:
+    losses = []
+    while True:
         gap = q[1] - q[0]
         if kind == "pb":
-            if not gap * gap > c["bm2"]:
-                break
+            viol = gap * gap > c["bm2"]
             h = gap - c["bm"]
             g = [-2.0 * h, 2.0 * h]        # d gap / d q0 = -1
         else:
-            if not gap * gap <= c["bp2"]:
-                break
+            viol = gap * gap <= c["bp2"]
             h = c["bp"] - abs(gap)
             s = 1.0 if gap > 0 else (-1.0 if gap < 0 else 1.0)
             g = [2.0 * h * s, -2.0 * h * s]
-        # plateau rule: one violated pair per evaluation here, so alpha is
-        # halved after every `patience` evaluations that follow the first;
-        # the verdict of this evaluation applies from the next step on
-        step = lr * scale
-        if patience > 0:
-            if best is None:
-                best, stall = 1, 0
-            else:
-                stall += 1
-                if stall >= patience:
-                    scale, stall = scale * 0.5, 0
+        losses.append(h * h if viol else 0.0)
+        if not viol or t >= steps:
+            break
         t += 1
         for k in range(2):
             if opt == "sgd":
-                q[k] = q[k] - step * g[k]
+                q[k] = q[k] - lr * g[k]
             else:
                 m[k] = b1 * m[k] + (1.0 - b1) * g[k]
                 v[k] = b2 * v[k] + (1.0 - b2) * g[k] * g[k]
                 mh = m[k] / (1.0 - math.pow(b1, t))
                 vh = v[k] / (1.0 - math.pow(b2, t))
-                q[k] = q[k] - step * mh / (math.sqrt(vh) + eps)
+                q[k] = q[k] - lr * mh / (math.sqrt(vh) + eps)
             q[k] = min(max(q[k], lo[k]), hi[k])
         traj.append(list(q))
-    return traj, t
+    return traj, t, losses
 
 
 @pytest.mark.parametrize("opt", ["adam", "sgd"])
@@ -77,7 +70,7 @@ def test_two_particle_pull_together(opt):
     x0, x1, r0, r1 = 0.0, 0.2421875, -0.015625, 0.2578125
     b, xi = 0.25, 0.02
     lr = 1e-3 if opt == "adam" else 2e-2
-    traj, steps = _scalar_run(x0, x1, r0, r1, b, xi, "pb", 10000, opt=opt, lr=lr)
+    traj, steps, losses = _scalar_run(x0, x1, r0, r1, b, xi, "pb", 10000, opt=opt, lr=lr)
     assert steps > 3
     orig, rec = _two(x0, x1, r0, r1)
     for k in (1, 2, steps // 2, steps):
@@ -87,32 +80,10 @@ def test_two_particle_pull_together(opt):
     r = oracle.correct(orig, rec, b, xi, mode="vp", optimizer=opt, lr=lr)
     assert r.status == 0 and r.iters == steps
     assert len(r.loss_hist) == steps + 1 and r.viol_hist[-1] == 0
-
-
-@pytest.mark.parametrize("opt", ["adam", "sgd"])
-def test_plateau_rule_halves_the_step(opt):
-    # the optional plateau rule against the scalar recurrence (one violated
-    # pair: alpha halves every `patience` evaluations until it is satisfied);
-    # a patience longer than the run leaves the paper's trajectory unchanged
-    x0, x1, r0, r1 = 0.0, 0.2421875, -0.015625, 0.2578125
-    b, xi = 0.25, 0.02
-    lr = 1e-3 if opt == "adam" else 2e-2
-    plain, psteps = _scalar_run(x0, x1, r0, r1, b, xi, "pb", 20000, opt=opt, lr=lr)
-    patience = 2 * psteps // 3 + 1
-    traj, steps = _scalar_run(x0, x1, r0, r1, b, xi, "pb", 20000, opt=opt, lr=lr,
-                              patience=patience)
-    assert 20000 > steps > psteps > 3
-    orig, rec = _two(x0, x1, r0, r1)
-    for k in sorted({1, patience, patience + 1, steps // 2, steps}):
-        r = oracle.correct(orig, rec, b, xi, mode="vp", max_iters=k, optimizer=opt, lr=lr,
-                           lr_patience=patience)
-        np.testing.assert_allclose(r.p[0], traj[k], rtol=0, atol=1e-15)
-    r = oracle.correct(orig, rec, b, xi, mode="vp", optimizer=opt, lr=lr, lr_patience=patience)
-    assert r.status == 0 and r.iters == steps
-    a = oracle.correct(orig, rec, b, xi, mode="vp", optimizer=opt, lr=lr, lr_patience=10 ** 6)
-    z = oracle.correct(orig, rec, b, xi, mode="vp", optimizer=opt, lr=lr)
-    np.testing.assert_array_equal(a.p, z.p)
-    assert a.iters == z.iters == psteps
+    # Eq. 3 at every evaluation: the squared overshoot of the one pair
+    np.testing.assert_allclose(r.loss_hist, losses, rtol=1e-15, atol=0)
+    assert losses[0] > 0 and losses[-1] == 0.0
+    assert r.stats["loss0"] == r.loss_hist[0] and r.stats["loss_final"] == 0.0
 
 
 def test_first_adam_step_closed_form():
@@ -134,13 +105,17 @@ def test_two_particle_push_apart_from_collapsed_point():
     x0, x1, r0, r1 = 0.0, 0.28125, 0.140625, 0.140625
     b, xi = 0.25, 0.15
     orig, rec = _two(x0, x1, r0, r1)
-    traj, steps = _scalar_run(x0, x1, r0, r1, b, xi, "pc", 10000)
+    traj, steps, losses = _scalar_run(x0, x1, r0, r1, b, xi, "pc", 10000)
     assert steps > 3
     for k in (1, 3, steps):
         r = oracle.correct(orig, rec, b, xi, mode="vp", max_iters=k)
         np.testing.assert_allclose(r.p[0], traj[k], rtol=0, atol=1e-15)
     r = oracle.correct(orig, rec, b, xi, mode="vp")
     assert r.iters == steps and r.status == 0
+    np.testing.assert_allclose(r.loss_hist, losses, rtol=1e-15, atol=0)
+    # at the collapsed start the overshoot is the whole of b + delta_t
+    c = oracle.constants(b, xi, maxabs=0.3)
+    assert r.loss_hist[0] == c["bp"] ** 2
 
 
 def test_no_violation_means_no_iteration_and_no_edit():
@@ -163,6 +138,35 @@ def test_exact_reconstruction_violates_only_pairs_within_margin():
     pc = (d2 > c["b2"])
     expect = int(np.sum(pb & (d2 > c["bm2"])) + np.sum(pc & (d2 <= c["bp2"])))
     assert r.stats["viol0"] == expect
+    # Eq. 3 over the exhaustive pair list: each violated potentially broken
+    # link adds (d - (b - delta_t))^2, each violated potentially created pair
+    # ((b + delta_t) - d)^2
+    d = np.sqrt(d2)
+    h = np.concatenate([(d - c["bm"])[pb & (d2 > c["bm2"])], (c["bp"] - d)[pc & (d2 <= c["bp2"])]])
+    assert h.size == expect and np.all(h >= 0)
+    loss = math.fsum((h * h).tolist())
+    assert loss > 0
+    assert abs(r.stats["loss0"] - loss) <= 1e-12 * loss
+    assert r.loss_hist[0] == r.stats["loss0"]
+
+
+def test_loss_tolerance_stops_at_the_first_evaluation_below_it():
+    # Alg. 1's eps_L: the loop ends at the first iterate whose tightened loss
+    # is <= eps_L; up to there the run is the one without a tolerance
+    w = synth.plain_blobs(4096, seed=5)
+    full = oracle.correct(w.orig, w.recon, w.b, w.xi, mode="hf", box=w.box)
+    assert full.status == 0 and full.iters > 10
+    hist = np.asarray(full.loss_hist)
+    k = full.iters // 2
+    tol = float(np.sqrt(hist[k - 1] * hist[k])) if hist[k] < hist[k - 1] else float(hist[k])
+    stop = int(np.argmax(hist <= tol))
+    assert 0 < stop <= k
+    r = oracle.correct(w.orig, w.recon, w.b, w.xi, mode="hf", box=w.box, loss_tol=tol)
+    assert r.status == 0 and r.iters == stop
+    assert r.stats["loss_final"] == hist[stop] <= tol
+    np.testing.assert_array_equal(np.asarray(r.loss_hist), hist[:stop + 1])
+    capped = oracle.correct(w.orig, w.recon, w.b, w.xi, mode="hf", box=w.box, max_iters=stop)
+    np.testing.assert_array_equal(r.p, capped.p)
 
 
 def test_iteration_cap_reports_not_converged_inside_the_box():
