@@ -220,7 +220,7 @@ def bench_served(args):
     modes = [int(w.mode) for w in ws]
     jobs = []
     for w in ws:
-        kw = {"lr": 0.005 * w.b, "lr_patience": args.lr_patience}
+        kw = {"lr": 0.005 * w.b}
         if args.max_iters:
             kw["max_iters"] = args.max_iters
         jobs.append(dict(orig=torch.from_numpy(w.orig).cuda(), recon=torch.from_numpy(w.recon).cuda(),
@@ -278,7 +278,6 @@ def bench_served(args):
                                "xi = b U(0.1, 0.5); modes VP/SC/HF)" % (len(jobs) - 1),
                    "jobs": len(jobs), "particles": total, "arrival_rate_frac": args.rate,
                    "modes": args.served_modes, "adam_lr": "0.005 b",
-                   "lr_patience": args.lr_patience,
                    "max_iters": args.max_iters or 100000,
                    "parallelism": "single GPU, server with 2 workers"},
         "latency_ms": {"p50": round(_percentile(lat, 50), 2), "p99": round(_percentile(lat, 99), 2),
@@ -333,9 +332,6 @@ def main():
     ap.add_argument("--detail", default="", help="served: write one JSON row per job here")
     ap.add_argument("--served-modes", default="hf", choices=("hf", "spec"),
                     help="served: every job in HF mode, or the stream's own VP/SC/HF draw")
-    ap.add_argument("--lr-patience", type=int, default=0,
-                    help="served: halve a job's step size after this many evaluations without "
-                         "a new minimum of its violation count (0: fixed step)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default scheduling knobs instead of autotuning them first")
     ap.add_argument("--thresholds", default="",

@@ -86,16 +86,15 @@ typedef struct {
   double lr;             /* alpha, default 1e-3 */
   double beta1, beta2;   /* Adam, default 0.9, 0.999 */
   double adam_eps;       /* Adam epsilon, default 1e-8 */
-  int64_t max_iters;     /* T_max; <= 0 selects the safety cap 100000 */
+  int64_t max_iters;     /* T_max; <= 0 selects the safety cap 100000; at most
+                            2^31 (larger: PCC_E_INVALID_ARG) */
   double loss_tol;       /* eps_L; 0 (default) stops when no selected pair is
                             violated, > 0 stops when the tightened loss of
-                            Eq. 3 is <= loss_tol */
+                            Eq. 3 is <= loss_tol.  The loss is summed in
+                            float64 in a fixed order that differs from a
+                            sequential sum over the pairs (relative
+                            difference ~1e-15) */
   double box[3];         /* periodic side per axis; 0 = open axis (default) */
-  int64_t lr_patience;   /* > 0: halve the step size after this many
-                            consecutive evaluations without a new minimum of
-                            the violation count (a damping of the fixed-step
-                            oscillation at loose bounds; not in the paper);
-                            0 (default): the paper's fixed step */
 } pcc_params;
 
 /* Caller-allocated outputs of one correction. */
@@ -275,7 +274,9 @@ pcc_status pcc_correct_multi(pcc_context *ctx, const pcc_particles *orig,
  * converged is masked out.  Each job's results equal those of pcc_correct on
  * that job alone.  results[k].status holds each job's status; the return
  * value is PCC_OK unless a job failed (then the first job error).
+ * 0 <= njobs <= PCC_MAX_BATCH_JOBS (else PCC_E_INVALID_ARG, nothing run).
  */
+#define PCC_MAX_BATCH_JOBS 65536
 pcc_status pcc_correct_batch(pcc_context *ctx, const pcc_job *jobs, int32_t njobs,
                              pcc_job_result *results, void *hip_stream);
 

@@ -43,7 +43,7 @@ class Params(C.Structure):
                 ("m_bits", C.c_int32), ("optimizer", C.c_int32), ("margin_policy", C.c_int32),
                 ("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
                 ("adam_eps", C.c_double), ("max_iters", C.c_int64), ("loss_tol", C.c_double),
-                ("box", C.c_double * 3), ("lr_patience", C.c_int64)]
+                ("box", C.c_double * 3)]
 
 
 class Outputs(C.Structure):
@@ -177,7 +177,7 @@ def stats_dict(s: Stats) -> Dict:
 
 def make_params(b: float, xi: float, mode="hf", box=None, m_bits=16, optimizer="adam",
                 lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8, max_iters=0, loss_tol=0.0,
-                margin="safe", lr_patience=0) -> Params:
+                margin="safe") -> Params:
     p = Params()
     lib().pcc_params_init(C.byref(p))
     p.b, p.xi = float(b), float(xi)
@@ -188,7 +188,6 @@ def make_params(b: float, xi: float, mode="hf", box=None, m_bits=16, optimizer="
     p.lr, p.beta1, p.beta2, p.adam_eps = float(lr), float(beta1), float(beta2), float(adam_eps)
     p.max_iters = int(max_iters)
     p.loss_tol = float(loss_tol)
-    p.lr_patience = int(lr_patience)
     for k, v in enumerate(box or (0.0, 0.0, 0.0)):
         p.box[k] = float(v)
     return p

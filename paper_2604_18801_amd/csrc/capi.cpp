@@ -250,6 +250,8 @@ pcc_status pcc_correct_batch(pcc_context *ctx, const pcc_job *jobs, int32_t njob
                              pcc_job_result *results, void *hip_stream) {
   if (!ctx || njobs < 0 || (njobs > 0 && (!jobs || !results)))
     return fail(PCC_E_INVALID_ARG, "NULL argument");
+  if (njobs > PCC_MAX_BATCH_JOBS)
+    return fail(PCC_E_INVALID_ARG, "at most 65536 jobs per batched call");
   return guarded([&]() -> pcc_status {
     if (njobs == 0) return PCC_OK;
     return pcc::run_batch(ctx->c, jobs, njobs, results, pick(ctx, hip_stream), false);

@@ -80,6 +80,10 @@ struct Context {
   size_t pinned_big_bytes = 0;
 };
 
+// longest bias-correction table a job may read: 2^24 entries (256 MiB)
+constexpr int64_t kMaxBcTable = (int64_t)1 << 24;
+// entries of the table a job with these betas and cap reads
+int64_t bc_length(double beta1, double beta2, int64_t max_iters);
 const double2 *bc_table(Context &C, double beta1, double beta2, int64_t len);
 
 // message returned by pcc_last_error on the calling thread

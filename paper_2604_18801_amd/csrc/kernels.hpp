@@ -123,12 +123,24 @@ struct PgdBufs {
   uint32_t *wl_step;  // [njobs]
   uint64_t *inc_n;    // [njobs] incidences of the rows in wl[0 .. wl_n)
   uint64_t *inc_step; // [njobs] incidences of the rows a step processes
-  // violation count and fixed-point loss of one evaluation: per job,
-  // acc_slots partial sums, each on its own 128-byte line (waves add into
-  // the slot of their index, so no address takes many atomics)
+  // violation count of one evaluation: per job, acc_slots partial sums,
+  // each on its own 128-byte line (waves add into the slot of their index,
+  // so no address takes many atomics)
   unsigned long long *acc;  // [njobs][acc_slots][16]
   int acc_slots;            // power of two
+  // float64 loss of one evaluation: one partial per (job, wave) that holds
+  // the wave's sum over its tiles of that job, stored (not added), so the
+  // sum the finalize kernel forms in slot order is deterministic.  Job j
+  // owns slots lp_off[j] .. lp_off[j+1] - 1, min(its tiles, nwaves) of them;
+  // the wave that walks tile k of the job (k counted from the job's first
+  // tile) uses slot k mod nwaves.
+  double *lossp;
+  const int64_t *lp_off;  // [njobs+1]
+  int nwaves;             // waves of the step grid (blocks * waves per block)
 };
+// waves of the step grid for ne editable rows (the step launches exactly
+// nwaves / 4 blocks of 4 waves)
+int pgd_step_waves(size_t ne);
 // a_k (threshold index per pair) may be NULL; when set it is the last key
 void sort_pairs(uint32_t *a_i, uint32_t *a_j, uint8_t *a_t, uint8_t *a_k, size_t na,
                 const float4 *pos, int id_bits, Arena &ar, hipStream_t s);

@@ -58,10 +58,12 @@ struct JobDev {
   double b, bm, bp, bm2, bp2;  // b -+ delta_t
   double xi_p;                 // box half width
   double lr, beta1, beta2, adam_eps, one_m_beta1, one_m_beta2;
-  double loss_scale;           // fixed-point scale of the loss accumulator
-  const double2 *bc_tab;       // [t] = (1 - beta1^t, 1 - beta2^t), t = 0 .. max_iters + 1
+  // [t] = (1 - beta1^t, 1 - beta2^t) for t = 0 .. bc_len - 1; the last entry
+  // also stands for every later t (both corrections have reached 1 exactly,
+  // or the table covers t = max_iters + 1)
+  const double2 *bc_tab;
+  int64_t bc_len;
   int64_t max_iters;
-  int64_t lr_patience;  // > 0: halve alpha after this many evaluations without a new minimum
   double loss_tol;
   int32_t optimizer;
   int32_t m_bits;
@@ -82,15 +84,11 @@ struct JobLoop {
   int32_t done;
   int32_t status;         // 0 converged, 1 cap reached
   double bc1, bc2;        // 1 - beta^t for the next step
-  unsigned long long viol0, loss0, viol_last, loss_last;
+  unsigned long long viol0, viol_last;
+  double loss0, loss_last;  // tightened loss of Eq. 3, float64
   unsigned long long rows_eval, inc_eval;  // rows and incidences evaluated, all steps
   int32_t have0;
   int32_t pad;
-  // plateau rule: factor on alpha, lowest violation count so far and the
-  // evaluations since it was reached
-  double lr_scale;
-  unsigned long long best_viol;
-  int64_t stall;
 };
 
 // Device helper: the job that owns global index g, by binary search in

@@ -282,8 +282,6 @@ __global__ void k_loop_init(const JobDev *jobs, JobLoop *loop, int njobs, int32_
   JobLoop L = {};
   L.bc1 = jobs[j].bc_tab[1].x;
   L.bc2 = jobs[j].bc_tab[1].y;
-  L.lr_scale = 1.0;
-  L.best_viol = ~0ull;
   loop[j] = L;
 }
 
@@ -309,6 +307,14 @@ __device__ inline unsigned long long wsum(unsigned long long v) {
   return v;
 }
 
+// float64 sum over the wave by a butterfly: every lane ends with the same
+// value (a + b and b + a round alike), formed in a fixed order
+__device__ inline double wsum_d(double v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
 // wave-level barrier: LDS written by lanes of this wave becomes visible to
 // all its lanes
 __device__ inline void wave_sync() {
@@ -323,19 +329,23 @@ constexpr int kPgdWaves = 4;
 #endif
 constexpr int kPgdBlocks = PCC_PGD_BLOCKS;  // 4096 waves: one round of 4 per SIMD
 
-// flush of a wave's violation count (the same in every lane) and
-// fixed-point loss (per lane) for one job into the wave's slot
-__device__ inline void flush_counts(const PgdBufs &B, int job, unsigned long long &viol,
-                                    unsigned long long &lossq) {
-  const unsigned long long sl = wsum(lossq);
-  if ((threadIdx.x & 63) == 0 && job >= 0 && (viol | sl)) {
-    const int slot = (int)((blockIdx.x * kPgdWaves + (threadIdx.x >> 6)) & (B.acc_slots - 1));
-    unsigned long long *a = B.acc + ((size_t)job * B.acc_slots + slot) * 16;
-    if (viol) atomicAdd(a, viol);
-    if (sl) atomicAdd(a + 1, sl);
+int pgd_step_waves(size_t ne) { return blocks_for(ne, 64 * kPgdWaves, kPgdBlocks) * kPgdWaves; }
+
+// flush of a wave's counts for one job: the violation count (the same in
+// every lane) is added into the wave's counter slot; the loss (per lane) is
+// summed over the wave and stored into the job's loss slot of this wave
+__device__ inline void flush_counts(const PgdBufs &B, int job, int lslot,
+                                    unsigned long long &viol, double &loss) {
+  const double sl = wsum_d(loss);
+  if ((threadIdx.x & 63) == 0 && job >= 0) {
+    if (viol) {
+      const int slot = (int)((blockIdx.x * kPgdWaves + (threadIdx.x >> 6)) & (B.acc_slots - 1));
+      atomicAdd(B.acc + ((size_t)job * B.acc_slots + slot) * 16, viol);
+    }
+    B.lossp[B.lp_off[job] + lslot] = sl;
   }
   viol = 0;
-  lossq = 0;
+  loss = 0.0;
 }
 
 __device__ inline uint64_t dbits(double x) { return (uint64_t)__double_as_longlong(x); }
@@ -380,8 +390,10 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
   __shared__ double s_thr[kPgdWaves][4][kMaxThresholds];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t nwaves = (int64_t)gridDim.x * kPgdWaves;
-  unsigned long long viol = 0, lossq = 0;
-  int cjob = -1;  // job whose counts are held in the registers above
+  unsigned long long viol = 0;
+  double loss = 0.0;
+  int cjob = -1;   // job whose counts are held in the registers above
+  int cslot = 0;   // this wave's loss slot of that job
   for (int64_t tile = (int64_t)blockIdx.x * kPgdWaves + w; tile < B.ntiles; tile += nwaves) {
     const int job = __builtin_amdgcn_readfirstlane(job_of(B.tile_off, B.njobs, tile));
     if (B.loop[job].done) continue;
@@ -390,8 +402,9 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
     const int64_t left = (int64_t)B.wl_step[job] - w0;
     if (left <= 0) continue;
     if (job != cjob) {
-      flush_counts(B, cjob, viol, lossq);
+      flush_counts(B, cjob, cslot, viol, loss);
       cjob = job;
+      cslot = (int)((tile - B.tile_off[job]) % nwaves);
     }
     const int64_t t_step = B.loop[job].t;
     const int nrow = (int)(left < 64 ? left : 64);
@@ -402,7 +415,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
     double4 *__restrict__ Pn = cur ? B.P0 : B.P1;
     const double L0 = J.L[0], L1 = J.L[1], L2 = J.L[2];
     const double h0 = J.hL[0], h1 = J.hL[1], h2 = J.hL[2];
-    const double bm = J.bm, bp = J.bp, bm2 = J.bm2, bp2 = J.bp2, scale = J.loss_scale;
+    const double bm = J.bm, bp = J.bp, bm2 = J.bm2, bp2 = J.bp2;
     // the row's position and incidence range; its Adam state is loaded
     // after the gathers (fewer live registers, more waves in flight)
     size_t e = 0;
@@ -526,7 +539,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
           }
           hit = true;
         }
-        if (hit && o > er) lossq += (unsigned long long)(h * h * scale);
+        if (hit && o > er) loss += h * h;
         hit_once = hit && o > er;
       }
       s_term[w][0][lane] = tx;
@@ -565,7 +578,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
       // moment stores below may alias the job table, and would load them
       // again (and wait for the load) for every coordinate
       const int opt = J.optimizer;
-      const double lr = J.lr * B.loop[job].lr_scale, beta1 = J.beta1, beta2 = J.beta2,
+      const double lr = J.lr, beta1 = J.beta1, beta2 = J.beta2,
                    omb1 = J.one_m_beta1,
                    omb2 = J.one_m_beta2, aeps = J.adam_eps, xip = J.xi_p;
       const double g[3] = {gx, gy, gz};
@@ -645,7 +658,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
     }
     wave_sync();  // LDS of this tile is reused by the next one
   }
-  flush_counts(B, cjob, viol, lossq);
+  flush_counts(B, cjob, cslot, viol, loss);
 }
 
 __global__ void k_hot_init(PgdBufs B, size_t n) {
@@ -796,49 +809,46 @@ void renumber_hot(PgdBufs &b, uint32_t *&e_list, Arena &ar, hipStream_t s) {
   e_list = R.ne_list;
 }
 
-// one wave per job: sums (and clears) the job's partial counts, then decides
+// one wave per job: sums (and clears) the job's partial counts, sums its
+// loss slots in slot order, then decides
 __global__ void k_pgd_finalize(PgdBufs B) {
   const int j = blockIdx.x, lane = threadIdx.x;
   JobLoop &L = B.loop[j];
   if (L.done) return;
   const JobDev &J = B.jobs[j];
-  unsigned long long viol = 0, lq = 0;
+  unsigned long long viol = 0;
   unsigned long long *a = B.acc + (size_t)j * B.acc_slots * 16;
   for (int k = lane; k < B.acc_slots; k += kWave) {
     viol += a[16 * k];
-    lq += a[16 * k + 1];
     a[16 * k] = 0;
-    a[16 * k + 1] = 0;
   }
   viol = wsum(viol);
-  lq = wsum(lq);
+  // the slots written by this step: one per wave that walked a tile of the
+  // job, i.e. of the first ceil(wl_step / 64) tiles
+  const uint32_t wl = B.wl_step[j];
+  const int64_t nslot = B.lp_off[j + 1] - B.lp_off[j];
+  const int64_t used = (int64_t)(wl + 63u) / 64 < nslot ? (int64_t)(wl + 63u) / 64 : nslot;
+  double loss = 0.0;
+  for (int64_t k = lane; k < used; k += kWave) loss += B.lossp[B.lp_off[j] + k];
+  loss = wsum_d(loss);
   if (lane != 0) return;
-  L.rows_eval += B.wl_step[j];
+  L.rows_eval += wl;
   L.inc_eval += B.inc_step[j];
   if (!L.have0) {
     L.viol0 = viol;
-    L.loss0 = lq;
+    L.loss0 = loss;
     L.have0 = 1;
   }
   L.viol_last = viol;
-  L.loss_last = lq;
-  const bool conv = J.loss_tol > 0.0 ? ((double)lq / J.loss_scale <= J.loss_tol) : (viol == 0);
+  L.loss_last = loss;
+  // Alg. 1's stopping test: no violated constraint, or the loss of Eq. 3 at
+  // most eps_L when that is set
+  const bool conv = J.loss_tol > 0.0 ? (loss <= J.loss_tol) : (viol == 0);
   if (conv || L.t >= J.max_iters) {
     L.done = 1;
     L.status = conv ? 0 : 1;
     atomicSub(B.n_active, 1);
     return;
-  }
-  // optional plateau rule: halve alpha after lr_patience evaluations
-  // without a new minimum of the violation count
-  if (J.lr_patience > 0) {
-    if (viol < L.best_viol) {
-      L.best_viol = viol;
-      L.stall = 0;
-    } else if (++L.stall >= J.lr_patience) {
-      L.lr_scale *= 0.5;
-      L.stall = 0;
-    }
   }
   // rows that became hot in this step join the next one (the worklist of
   // the first step is replaced by the compaction that follows it)
@@ -847,13 +857,17 @@ __global__ void k_pgd_finalize(PgdBufs B) {
     B.inc_step[j] = B.inc_n[j];
   }
   L.t += 1;
-  L.bc1 = J.bc_tab[L.t + 1].x;
-  L.bc2 = J.bc_tab[L.t + 1].y;
+  const int64_t tb = L.t + 1 < J.bc_len ? L.t + 1 : J.bc_len - 1;
+  L.bc1 = J.bc_tab[tb].x;
+  L.bc2 = J.bc_tab[tb].y;
 }
 
 void launch_pgd_step(const PgdBufs &b, hipStream_t s) {
-  if (b.ne)
-    k_pgd_step<<<blocks_for(b.ne, 64 * kPgdWaves, kPgdBlocks), 64 * kPgdWaves, 0, s>>>(b);
+  if (b.ne) {
+    // the loss slots were sized for this many waves
+    if (b.nwaves != pgd_step_waves(b.ne)) throw Error(-3, "PGD step grid differs from its loss slots");
+    k_pgd_step<<<b.nwaves / kPgdWaves, 64 * kPgdWaves, 0, s>>>(b);
+  }
 }
 void launch_pgd_finalize(const PgdBufs &b, hipStream_t s) {
   if (b.njobs) k_pgd_finalize<<<b.njobs, kWave, 0, s>>>(b);

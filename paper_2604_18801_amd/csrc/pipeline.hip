@@ -52,7 +52,11 @@ int check_params(const pcc_job &j, std::string &err) {
   if (!(p.beta1 >= 0 && p.beta1 < 1 && p.beta2 >= 0 && p.beta2 < 1))
     return err = "Adam betas must lie in [0, 1)", -1;
   if (!(finite(p.loss_tol) && p.loss_tol >= 0)) return err = "loss_tol must be >= 0", -1;
-  if (p.lr_patience < 0) return err = "lr_patience must be >= 0", -1;
+  if (p.max_iters > ((int64_t)1 << 31)) return err = "max_iters must be at most 2^31", -1;
+  if (p.optimizer == PCC_OPT_ADAM &&
+      bc_length(p.beta1, p.beta2, p.max_iters > 0 ? p.max_iters : 100000) > kMaxBcTable)
+    return err = "max_iters too large for these Adam betas (the bias corrections stay below 1 "
+                 "beyond 2^24 steps)", -1;
   for (int a = 0; a < 3; ++a)
     if (!(finite(p.box[a]) && p.box[a] >= 0)) return err = "box sides must be finite and >= 0", -1;
   if (j.orig.n != j.recon.n) return err = "orig and recon differ in size", -1;
@@ -102,14 +106,12 @@ int job_constants(const pcc_params &p, const ScanPart &agg, int64_t n, int cell_
   J.adam_eps = p.adam_eps;
   J.one_m_beta1 = 1.0 - p.beta1;
   J.one_m_beta2 = 1.0 - p.beta2;
-  J.loss_scale = std::ldexp(1.0, 32) / J.b2;
   J.nthr = 1;
   J.thr_bm[0] = J.bm;
   J.thr_bp[0] = J.bp;
   J.thr_bm2[0] = J.bm2;
   J.thr_bp2[0] = J.bp2;
   J.max_iters = p.max_iters > 0 ? p.max_iters : 100000;
-  J.lr_patience = p.lr_patience;
   J.loss_tol = p.loss_tol;
   J.optimizer = p.optimizer;
   J.m_bits = p.m_bits;
@@ -306,9 +308,39 @@ KernelTimer::~KernelTimer() {
   for (auto e : pool) hipEventDestroy(e);
 }
 
+namespace {
+// first t >= 1 at which 1 - beta^t rounds to exactly 1 (binary search: the
+// rounded value does not decrease with t), or 2^25 when that is later
+int64_t bc_saturation(double beta) {
+  auto sat = [&](int64_t t) { return 1.0 - std::pow(beta, (double)t) == 1.0; };
+  int64_t lo = 1, hi = (int64_t)1 << 25;
+  if (sat(lo)) return lo;
+  if (!sat(hi)) return hi;
+  while (hi - lo > 1) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (sat(mid))
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return hi;
+}
+}  // namespace
+
+int64_t bc_length(double beta1, double beta2, int64_t max_iters) {
+  // entries t = 0 .. max_iters + 1, but no further than the first t at which
+  // both corrections are exactly 1 (every later t has the same entry)
+  const int64_t want = max_iters + 2;
+  const int64_t sat = std::max(bc_saturation(beta1), bc_saturation(beta2));
+  return std::min(want, sat + 1);
+}
+
 const double2 *bc_table(Context &C, double beta1, double beta2, int64_t len) {
   for (auto &t : C.bc)
     if (t.beta1 == beta1 && t.beta2 == beta2 && t.len >= len) return t.dev;
+  if (len > kMaxBcTable)
+    throw Error(PCC_E_INVALID_ARG, "max_iters too large for these Adam betas (the bias "
+                                   "corrections stay below 1 beyond 2^24 steps)");
   len = std::max<int64_t>(len, 4096);
   std::vector<double2> h((size_t)len);
   for (int64_t t = 0; t < len; ++t) {
@@ -318,6 +350,10 @@ const double2 *bc_table(Context &C, double beta1, double beta2, int64_t len) {
   double2 *d = nullptr;
   PCC_HIP(hipMalloc((void **)&d, (size_t)len * sizeof(double2)));
   PCC_HIP(hipMemcpy(d, h.data(), (size_t)len * sizeof(double2), hipMemcpyHostToDevice));
+  // a shorter table of the same betas is replaced; no kernel of an earlier
+  // call is still running (calls synchronise before they return) and the
+  // jobs of the current call take their pointers only after every table
+  // they need has been built
   for (auto &t : C.bc)
     if (t.beta1 == beta1 && t.beta2 == beta2) {
       hipFree(t.dev);
@@ -530,8 +566,28 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
         for (auto &ji : C.last.job_index) ji = map[ji];
       return first;
     }
+    // Adam's bias-correction tables: the longest one each pair of betas needs
+    // in this call is built before any job takes a pointer, so no table a
+    // job holds is replaced later in the call
+    std::vector<std::pair<std::pair<double, double>, int64_t>> need;
     for (auto *h : act) {
-      h->dev.bc_tab = bc_table(C, h->dev.beta1, h->dev.beta2, h->dev.max_iters + 2);
+      const auto key = std::make_pair(h->dev.beta1, h->dev.beta2);
+      // the plain step reads no correction
+      const int64_t len = h->dev.optimizer == PCC_OPT_SGD
+                              ? 2
+                              : bc_length(h->dev.beta1, h->dev.beta2, h->dev.max_iters);
+      h->dev.bc_len = len;
+      bool found = false;
+      for (auto &e : need)
+        if (e.first == key) {
+          e.second = std::max(e.second, len);
+          found = true;
+        }
+      if (!found) need.push_back({key, len});
+    }
+    for (auto &e : need) bc_table(C, e.first.first, e.first.second, e.second);
+    for (auto *h : act) {
+      h->dev.bc_tab = bc_table(C, h->dev.beta1, h->dev.beta2, h->dev.bc_len);
       h->dev.cell_base = (uint32_t)cell_total;
       h->dev.p_off = h->p_off;
       cell_total += h->ncell;
@@ -865,6 +921,17 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   gb.acc_slots = 64;
   while (gb.acc_slots > 1 && (int64_t)gb.acc_slots * J > 4096) gb.acc_slots >>= 1;
   gb.acc = dev<unsigned long long>(ar, (size_t)J * gb.acc_slots * 16);
+  gb.nwaves = pgd_step_waves(ne);
+  {
+    // loss slots: min(tiles, waves) per job
+    std::vector<int64_t> lo(J + 1, 0);
+    for (int q = 0; q < J; ++q)
+      lo[q + 1] = lo[q] + std::min<int64_t>((e_off[q + 1] - e_off[q] + 63) / 64, gb.nwaves);
+    int64_t *d_lo = dev<int64_t>(ar, J + 1);
+    PCC_HIP(hipMemcpyAsync(d_lo, lo.data(), (J + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    gb.lp_off = d_lo;
+    gb.lossp = dev<double>(ar, (size_t)lo[J]);
+  }
   launch_pgd_init(e_list, ne, pos, rec, gb.P0, xo, gb.m, gb.v, s);
   launch_hot_init(gb, s);
   launch_loop_init(d_jobs, gb.loop, J, gb.n_active, s);
@@ -933,12 +1000,11 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   st.fetch(lp.data(), gb.loop, J);
   for (int q = 0; q < J; ++q) {
     pcc_stats &S = act[q]->st;
-    const double sc = act[q]->dev.loss_scale;
     S.iters = lp[q].t;
     S.viol0 = (int64_t)lp[q].viol0;
     S.viol_final = (int64_t)lp[q].viol_last;
-    S.loss0 = (double)lp[q].loss0 / sc;
-    S.loss_final = (double)lp[q].loss_last / sc;
+    S.loss0 = lp[q].loss0;
+    S.loss_final = lp[q].loss_last;
     S.pgd_rows_evaluated = (int64_t)lp[q].rows_eval;
     S.pgd_incidences_evaluated = (int64_t)lp[q].inc_eval;
     act[q]->status = lp[q].status ? PCC_NOT_CONVERGED : PCC_OK;

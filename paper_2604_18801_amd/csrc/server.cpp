@@ -184,7 +184,8 @@ pcc_status pcc_server_create(pcc_context *ctx, const pcc_server_config *cfg, pcc
   *out = nullptr;
   pcc_server_config c{};
   if (cfg) c = *cfg;
-  if (c.max_inflight < 0 || c.n_streams < 0 || c.n_streams > 16)
+  if (c.max_inflight < 0 || c.max_inflight > PCC_MAX_BATCH_JOBS || c.n_streams < 0 ||
+      c.n_streams > 16)
     return fail(PCC_E_INVALID_ARG, "max_inflight >= 0 and n_streams in 0..16");
   try {
     auto *S = new pcc_server;

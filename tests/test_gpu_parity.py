@@ -62,7 +62,21 @@ def _compare(ctx, w, mode, **kw):
     assert st["iters"] == ref.iters and st["status"] == ref.status
     dp = np.abs(st["debug_xyz"] - ref.p).max() if w.n else 0.0
     assert dp <= TOL * w.xi, dp
+    _check_loss(st, ref)
     return ref, stream, st
+
+
+# The loss of Eq. 3 is a float64 sum over the violated pairs; the GPU adds
+# per-wave partials in a fixed order, the oracle adds pair by pair, so the two
+# sums differ by rounding only: a relative 1e-12 bounds it for the pair
+# counts here (each of n additions errs by at most 2^-53 relative).
+LOSS_RTOL = 1e-12
+
+
+def _check_loss(st, ref):
+    for k in ("loss0", "loss_final"):
+        a, b = st[k], ref.stats[k]
+        assert abs(a - b) <= LOSS_RTOL * abs(b), (k, a, b)
 
 
 @pytest.mark.parametrize("case", golden_cases.load(), ids=lambda c: c["name"])
@@ -265,15 +279,80 @@ def test_slotted_and_exact_pair_paths_agree(ctx, mode):
     assert st1["iters"] == st2["iters"] and st1["n_active"] == st2["n_active"]
 
 
-@pytest.mark.parametrize("patience", [4, 5])
-def test_plateau_rule_is_bitwise_the_oracles(ctx, patience):
-    # optional step-size halving after `patience` evaluations without a new
-    # minimum of the violation count: the same decisions and iterates
-    w = synth.cosmology(16, seed=3, xi=0.05)
-    kw = dict(lr_patience=patience, max_iters=400)
-    ref = oracle.correct(w.orig, w.recon, w.b, w.xi, mode="hf", box=w.box, **kw)
-    _, lab, st = _run(ctx, w, "hf", **kw)
-    assert st["iters"] == ref.iters and st["status"] == ref.status
+@pytest.mark.parametrize("mode", ["hf", "vp"])
+def test_loss_tolerance_stop_matches_oracle(ctx, mode):
+    # Alg. 1's eps_L: both sides stop at the first iterate whose tightened
+    # loss is <= eps_L.  eps_L is placed between two consecutive losses of the
+    # run without a tolerance, far (relative 1e-6) from every evaluated loss,
+    # so the rounding difference of the two sums cannot change the decision.
+    w = synth.plain_blobs(8192, seed=21)
+    full = oracle.correct(w.orig, w.recon, w.b, w.xi, mode=mode, box=w.box)
+    hist = np.asarray(full.loss_hist)
+    assert full.status == 0 and full.iters > 8
+    k = full.iters // 2
+    while hist[k] >= hist[k - 1]:
+        k += 1
+    tol = float(np.sqrt(hist[k - 1] * hist[k]))
+    stop = int(np.argmax(hist <= tol))
+    assert np.all(np.abs(hist[:stop + 1] - tol) > 1e-6 * tol)
+    ref = oracle.correct(w.orig, w.recon, w.b, w.xi, mode=mode, box=w.box, loss_tol=tol)
+    assert ref.iters == stop and ref.status == 0 and ref.stats["viol_final"] > 0
+    _, lab, st = _run(ctx, w, mode, loss_tol=tol)
+    np.testing.assert_array_equal(lab, ref.labels)
+    assert st["iters"] == ref.iters and st["status"] == 0
+    assert st["viol_final"] == ref.stats["viol_final"] and st["viol0"] == ref.stats["viol0"]
+    _check_loss(st, ref)
+    assert st["loss_final"] <= tol
     np.testing.assert_array_equal(st["debug_xyz"], ref.p)
-    plain = oracle.correct(w.orig, w.recon, w.b, w.xi, mode="hf", box=w.box, max_iters=400)
-    assert plain.iters != ref.iters or not np.array_equal(plain.p, ref.p)
+
+
+@pytest.mark.parametrize("k", [1, 3, 20])
+def test_loss_per_iteration_matches_oracle(ctx, k):
+    # the loss of the last evaluated iterate at several caps, in a run whose
+    # rows span many PGD tiles and waves
+    w = synth.cosmology(24, seed=13, xi=0.05)
+    ref = oracle.correct(w.orig, w.recon, w.b, w.xi, mode="hf", box=w.box, max_iters=k)
+    _, _, st = _run(ctx, w, "hf", max_iters=k)
+    assert st["iters"] == ref.iters == k
+    assert ref.stats["loss_final"] > 0
+    _check_loss(st, ref)
+    assert st["loss_final"] == pytest.approx(ref.loss_hist[-1], rel=LOSS_RTOL)
+
+
+def test_batch_with_mixed_caps_equals_single_calls(ctx):
+    # jobs of one call with different iteration caps (and so different
+    # lengths of Adam's bias-correction table), the short cap first
+    ws = [synth.plain_blobs(4000, seed=50), synth.plain_blobs(5000, seed=51),
+          synth.plain_blobs(3000, seed=52)]
+    caps = [50, 0, 7]
+    jobs = [dict(orig=_dev(w.orig), recon=_dev(w.recon), b=w.b, xi=w.xi, mode="hf", box=w.box,
+                 debug_xyz=True, opts={"max_iters": c} if c else {}) for w, c in zip(ws, caps)]
+    out = ctx.correct_batch(jobs)
+    for (status, stream, lab, st), w, c in zip(out, ws, caps):
+        kw = {"max_iters": c} if c else {}
+        s1, l1, st1 = _run(ctx, w, "hf", **kw)
+        ref = oracle.correct(w.orig, w.recon, w.b, w.xi, mode="hf", box=w.box, **kw)
+        assert status == st1["status"] == ref.status
+        assert st["iters"] == st1["iters"] == ref.iters
+        assert stream == s1
+        np.testing.assert_array_equal(st["debug_xyz"], st1["debug_xyz"])
+        np.testing.assert_array_equal(st["debug_xyz"], ref.p)
+
+
+def test_iteration_cap_above_the_limit_is_rejected(ctx):
+    import paper_2604_18801_amd as pcc
+    w = synth.plain_blobs(2000, seed=3)
+    with pytest.raises(pcc.PccError) as e:
+        ctx.correct(_dev(w.orig), _dev(w.recon), w.b, w.xi, max_iters=(1 << 31) + 1)
+    assert e.value.status == -1
+    # betas whose bias corrections stay below 1 for longer than the table
+    # the library keeps, with a cap beyond it
+    with pytest.raises(pcc.PccError) as e:
+        ctx.correct(_dev(w.orig), _dev(w.recon), w.b, w.xi, beta2=1.0 - 1e-12,
+                    max_iters=1 << 30)
+    assert e.value.status == -1
+    # at the limit with the default betas the table ends where both
+    # corrections reach 1: the call runs as with the default cap
+    a = ctx.correct(_dev(w.orig), _dev(w.recon), w.b, w.xi, max_iters=1 << 31, debug_xyz=True)
+    b = ctx.correct(_dev(w.orig), _dev(w.recon), w.b, w.xi, debug_xyz=True)
+    assert a[0] == b[0] and a[2]["iters"] == b[2]["iters"]
