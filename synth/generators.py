@@ -27,11 +27,27 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from typing import Dict, List, Optional, Tuple
 
 import numpy as np
 
 MODE_VP, MODE_SC, MODE_HF = 0, 1, 2
+
+
+def _pieces(n: int, fn, piece: int = 1 << 18) -> None:
+    """fn(a, b) over [0, n) in pieces, on threads (numpy releases the GIL).
+    Only used for elementwise work, so the result does not depend on the
+    split."""
+    ranges = [(a, min(n, a + piece)) for a in range(0, n, piece)]
+    if len(ranges) <= 1:
+        for a, b in ranges:
+            fn(a, b)
+        return
+    with ThreadPoolExecutor(max(1, min(16, os.cpu_count() or 1))) as ex:
+        for _ in ex.map(lambda r: fn(*r), ranges):
+            pass
 
 
 @dataclasses.dataclass
@@ -59,29 +75,42 @@ def grid_reconstruction(orig: np.ndarray, xi: float) -> np.ndarray:
 
     Returns float32 positions with |x_hat - x| <= xi checked in float64.
     """
-    x64 = orig.astype(np.float64)
-    q = np.rint(x64 / (2.0 * xi))
-    rec = (q * (2.0 * xi)).astype(np.float32)
-    bad = np.abs(rec.astype(np.float64) - x64) > xi
-    while bad.any():
-        rec[bad] = np.nextafter(rec[bad], orig[bad])
-        bad = np.abs(rec.astype(np.float64) - x64) > xi
-    return np.ascontiguousarray(rec)
+    orig = np.ascontiguousarray(orig)
+    rec = np.empty_like(orig, dtype=np.float32)
+
+    def work(a, b):
+        o = orig[:, a:b]
+        x64 = o.astype(np.float64)
+        q = np.rint(x64 / (2.0 * xi))
+        r = (q * (2.0 * xi)).astype(np.float32)
+        bad = np.abs(r.astype(np.float64) - x64) > xi
+        while bad.any():
+            r[bad] = np.nextafter(r[bad], o[bad])
+            bad = np.abs(r.astype(np.float64) - x64) > xi
+        rec[:, a:b] = r
+
+    _pieces(orig.shape[1], work)
+    return rec
 
 
 def _finish(name, pos64, rng, b, xi, box, mode, seed, meta, wrap=False):
     """Permute, store float32 SoA, build the reconstruction."""
     n = pos64.shape[0]
     perm = rng.permutation(n)
-    pos64 = pos64[perm]
-    orig = np.ascontiguousarray(pos64.T.astype(np.float32))
-    if wrap:
-        for a in range(3):
-            L = np.float32(box[a])
-            if L > 0:
-                # float32 rounding can land a wrapped value on L itself
-                orig[a][orig[a] >= L] -= L
-                orig[a][orig[a] < 0] += L
+    orig = np.empty((3, n), dtype=np.float32)
+
+    def work(a, b):
+        o = pos64[perm[a:b]].T.astype(np.float32)
+        if wrap:
+            for k in range(3):
+                L = np.float32(box[k])
+                if L > 0:
+                    # float32 rounding can land a wrapped value on L itself
+                    o[k][o[k] >= L] -= L
+                    o[k][o[k] < 0] += L
+        orig[:, a:b] = o
+
+    _pieces(n, work)
     recon = grid_reconstruction(orig, xi)
     return Workload(name=name, orig=orig, recon=recon, b=float(b), xi=float(xi),
                     box=tuple(float(v) for v in box), mode=mode, seed=seed,
@@ -165,19 +194,26 @@ def cosmology(n_side: int = 256, seed: int = 1, xi: float = 0.05, b: float = 0.2
     chunk = 1 << 22
     for s in range(0, n_halo, chunk):
         e = min(n_halo, s + chunk)
-        h = owner[s:e]
+        # draws in a fixed order per chunk; the per-particle work below uses
+        # no random numbers and runs on threads
         target = rng.random(e - s) * mu_c
-        lo = np.zeros(e - s)
-        hi = np.full(e - s, conc)
-        for _ in range(bisect_steps):
-            mid = 0.5 * (lo + hi)
-            below = _nfw_mu(mid) < target
-            lo = np.where(below, mid, lo)
-            hi = np.where(below, hi, mid)
-        r = 0.5 * (lo + hi) * rs[h]
         d = rng.normal(size=(e - s, 3))
-        d /= np.linalg.norm(d, axis=1, keepdims=True)
-        pos[s:e] = np.mod(centres[h] + r[:, None] * d, L)
+
+        def work(a, b, s=s, target=target, d=d):
+            h = owner[s + a:s + b]
+            lo = np.zeros(b - a)
+            hi = np.full(b - a, conc)
+            tg = target[a:b]
+            for _ in range(bisect_steps):
+                mid = 0.5 * (lo + hi)
+                below = _nfw_mu(mid) < tg
+                lo = np.where(below, mid, lo)
+                hi = np.where(below, hi, mid)
+            r = 0.5 * (lo + hi) * rs[h]
+            dd = d[a:b] / np.linalg.norm(d[a:b], axis=1, keepdims=True)
+            pos[s + a:s + b] = np.mod(centres[h] + r[:, None] * dd, L)
+
+        _pieces(e - s, work)
     pos[n_halo:] = rng.random((n - n_halo, 3)) * L
     return _finish("cosmology_%d" % n, pos, rng, b, xi, (L, L, L), mode, seed,
                    {"n_halos": int(nh), "L": L}, wrap=True)
