@@ -308,6 +308,28 @@ pcc_status pcc_fof_labels(pcc_context *ctx, const pcc_particles *pts, double b,
                           const double box[3], int32_t *labels, void *hip_stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * labels as pcc_fof_labels, bit for bit, computed by the same kernels, with
+ * every device buffer taken from a static device array of 128 MiB that the
+ * library holds on each GPU it runs on until the process ends.  The call
+ * makes no hipMalloc / hipFree / hipHostMalloc and creates no HIP object;
+ * the caller passes the points and the labels buffer (memspace of pts; host
+ * inputs are staged through the static array).  n above
+ * pcc_fof_labels_noalloc_max_n() (520192) returns PCC_E_INVALID_ARG before
+ * any device work.  The array keeps the last call's contents; the call
+ * initialises everything it reads.  Calls on one GPU share the one array:
+ * within a process they are serialised by a lock (each returns only when
+ * its work on hip_stream has finished); calls that overlap on one GPU
+ * without it (e.g. work still queued by a caller that ignored an error)
+ * would race.  The context supplies the device, its scheduling knobs and
+ * its stage events; its workspace and retained debug data are not touched.
+ */
+pcc_status pcc_fof_labels_noalloc(pcc_context *ctx, const pcc_particles *pts, double b,
+                                  const double box[3], int32_t *labels, void *hip_stream);
+int64_t pcc_fof_labels_noalloc_max_n(void);
+
+/*
  * Test hook: copy an intermediate result of job `job` of the last
  * pcc_correct / pcc_correct_batch call on this context into host memory.
  * Pair lists use particle indices of the job with i < j, unsorted.
@@ -343,8 +365,10 @@ pcc_status pcc_debug_fetch(pcc_context *ctx, int32_t job, int32_t what, void *ho
  *                               value -1 switches it off.
  * pcc_debug_get reads the current value (the allocations left before the
  * failure, or a negative number when off).
+ *   PCC_DEBUG_NOALLOC_HIGH_WATER  (get only) bytes of the static array the
+ *                               last pcc_fof_labels_noalloc call used.
  */
-enum { PCC_DEBUG_ALLOC_FAIL_AFTER = 1 };
+enum { PCC_DEBUG_ALLOC_FAIL_AFTER = 1, PCC_DEBUG_NOALLOC_HIGH_WATER = 2 };
 pcc_status pcc_debug_set(int32_t key, int64_t value);
 pcc_status pcc_debug_get(int32_t key, int64_t *value);
 

@@ -130,6 +130,10 @@ def lib() -> C.CDLL:
                                  C.c_void_p, C.c_void_p]
         L.pcc_fof_labels.argtypes = [C.c_void_p, C.POINTER(Particles), C.c_double,
                                      C.POINTER(C.c_double), C.c_void_p, C.c_void_p]
+        L.pcc_fof_labels_noalloc.argtypes = [C.c_void_p, C.POINTER(Particles), C.c_double,
+                                             C.POINTER(C.c_double), C.c_void_p, C.c_void_p]
+        L.pcc_fof_labels_noalloc_max_n.argtypes = []
+        L.pcc_fof_labels_noalloc_max_n.restype = C.c_int64
         L.pcc_context_set.argtypes = [C.c_void_p, C.c_int32, C.c_int64]
         L.pcc_context_get.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]
         L.pcc_debug_set.argtypes = [C.c_int32, C.c_int64]
@@ -149,7 +153,8 @@ def lib() -> C.CDLL:
         L.pcc_server_drain.argtypes = [C.c_void_p]
         L.pcc_server_destroy.argtypes = [C.c_void_p]
         for name in ("pcc_context_create", "pcc_context_destroy", "pcc_correct",
-                     "pcc_correct_multi", "pcc_correct_batch", "pcc_decode", "pcc_fof_labels", "pcc_debug_fetch",
+                     "pcc_correct_multi", "pcc_correct_batch", "pcc_decode", "pcc_fof_labels",
+                     "pcc_fof_labels_noalloc", "pcc_debug_fetch",
                      "pcc_context_set", "pcc_context_get", "pcc_autotune", "pcc_decode_device",
                      "pcc_debug_set", "pcc_debug_get", "pcc_server_create", "pcc_server_submit",
                      "pcc_server_poll", "pcc_server_wait", "pcc_server_cancel",
@@ -419,10 +424,22 @@ class Context:
                                        _stream_handle(True)))
         return out[:, : pr.n]
 
-    def fof_labels(self, pts, b: float, box=None):
+    def fof_labels(self, pts, b: float, box=None, labels=None):
+        return self._fof(lib().pcc_fof_labels, pts, b, box, labels)
+
+    def fof_labels_noalloc(self, pts, b: float, box=None, labels=None):
+        """pcc_fof_labels_noalloc: the same labels with no device allocation
+        in the library (pass `labels`, an int32 buffer of N entries in the
+        memspace of pts, to allocate nothing here either)."""
+        return self._fof(lib().pcc_fof_labels_noalloc, pts, b, box, labels)
+
+    def _fof(self, fn, pts, b, box, labels):
         p, keep = _view(pts)
         n = p.n
-        if p.memspace == MEM_DEVICE:
+        if labels is not None:
+            lab = labels
+            ptr = lab.data_ptr() if p.memspace == MEM_DEVICE else lab.ctypes.data
+        elif p.memspace == MEM_DEVICE:
             import torch
             lab = torch.empty(max(n, 1), dtype=torch.int32, device=keep.device)
             ptr = lab.data_ptr()
@@ -430,8 +447,8 @@ class Context:
             lab = np.zeros(max(n, 1), dtype=np.int32)
             ptr = lab.ctypes.data
         bx = (C.c_double * 3)(*[float(v) for v in (box or (0.0, 0.0, 0.0))])
-        _check(lib().pcc_fof_labels(self._h, C.byref(p), float(b), bx, C.c_void_p(ptr),
-                                    _stream_handle(p.memspace == MEM_DEVICE)))
+        _check(fn(self._h, C.byref(p), float(b), bx, C.c_void_p(ptr),
+                  _stream_handle(p.memspace == MEM_DEVICE)))
         return lab[:n]
 
     def debug_fetch(self, job: int, what: str):
@@ -451,6 +468,18 @@ def inject_alloc_failure(after: int):
     """Test hook: the workspace allocation after `after` more successful ones
     fails as if the device were out of memory (-1 switches it off)."""
     _check(lib().pcc_debug_set(1, int(after)))
+
+
+def fof_labels_noalloc_max_n() -> int:
+    """Largest point count pcc_fof_labels_noalloc accepts."""
+    return int(lib().pcc_fof_labels_noalloc_max_n())
+
+
+def noalloc_high_water() -> int:
+    """Bytes of the static scratch the last pcc_fof_labels_noalloc used."""
+    v = C.c_int64(0)
+    _check(lib().pcc_debug_get(2, C.byref(v)))
+    return v.value
 
 
 def alloc_failure_countdown() -> int:

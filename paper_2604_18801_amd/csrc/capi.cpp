@@ -114,9 +114,16 @@ pcc_status pcc_debug_set(int32_t key, int64_t value) {
 }
 
 pcc_status pcc_debug_get(int32_t key, int64_t *value) {
-  if (key != PCC_DEBUG_ALLOC_FAIL_AFTER || !value) return fail(PCC_E_INVALID_ARG, "bad argument");
-  *value = pcc::g_alloc_fail_after.load();
-  return PCC_OK;
+  if (!value) return fail(PCC_E_INVALID_ARG, "bad argument");
+  if (key == PCC_DEBUG_ALLOC_FAIL_AFTER) {
+    *value = pcc::g_alloc_fail_after.load();
+    return PCC_OK;
+  }
+  if (key == PCC_DEBUG_NOALLOC_HIGH_WATER) {
+    *value = pcc::noalloc_high_water();
+    return PCC_OK;
+  }
+  return fail(PCC_E_INVALID_ARG, "unknown debug key");
 }
 
 pcc_status pcc_autotune(pcc_context *ctx, const pcc_job *jobs, int32_t njobs, int32_t flags,
@@ -162,11 +169,22 @@ pcc_status pcc_context_create(int device, pcc_context **out) {
     PCC_HIP(hipGetDeviceProperties(&prop, device));
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
       return fail(PCC_E_UNSUPPORTED, std::string("built for gfx950, device is ") + prop.gcnArchName);
+    // the device's static scratch of the allocation-free calls
+    pcc::scratch_init(device);
     auto *c = new pcc_context;
     c->c.device = device;
     if (hipStreamCreate(&c->c.own) != hipSuccess) {
       delete c;
       return fail(PCC_E_DEVICE, "hipStreamCreate failed");
+    }
+    try {
+      pcc::create_events(c->c);
+    } catch (...) {
+      for (auto &e : c->c.ev)
+        if (e) hipEventDestroy(e);
+      hipStreamDestroy(c->c.own);
+      delete c;
+      throw;
     }
     *out = c;
     return PCC_OK;

@@ -177,8 +177,8 @@ __global__ void k_cell_starts(const uint32_t *keys, const uint8_t *flag, const u
 void build_cells(const uint32_t *keys, size_t n, uint32_t *cell_of, uint32_t *cell_start,
                  uint32_t *cell_key, uint32_t *n_cells, Arena &ar, hipStream_t s) {
   if (n == 0) {
-    PCC_HIP(hipMemsetAsync(n_cells, 0, sizeof(uint32_t), s));
-    PCC_HIP(hipMemsetAsync(cell_start, 0, sizeof(uint32_t), s));
+    fill_u32(n_cells, 0, 1, s);
+    fill_u32(cell_start, 0, 1, s);
     return;
   }
   uint8_t *flag = ar.get<uint8_t>(n);

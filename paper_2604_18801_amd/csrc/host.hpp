@@ -96,8 +96,19 @@ void autotune(Context &C, const pcc_job *jobs, int njobs, hipStream_t s, int32_t
 
 // multi: the jobs are one snapshot at several linking lengths, corrected
 // together into job 0's particles (job 0's stream; every job's labels)
+// scratch: labels only, every device buffer of the call from this fixed
+// arena (no device or pinned allocation, no kernel timing, the context's
+// arena and retained debug data untouched)
 pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs, pcc_job_result *res,
-                     hipStream_t s, bool labels_only, bool multi = false);
+                     hipStream_t s, bool labels_only, bool multi = false,
+                     Arena *scratch = nullptr);
+// stage events of a context (created once, with the context)
+void create_events(Context &C);
+// scratch.hip: finds the device address of the static scratch of the
+// allocation-free calls on `device` (the current device), once per device
+void scratch_init(int device);
+// static-scratch bytes the last allocation-free call used
+int64_t noalloc_high_water();
 
 // codec.cpp
 struct HuffTable {

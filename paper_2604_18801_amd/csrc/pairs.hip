@@ -589,7 +589,7 @@ void plan_pairs(PairPlan &pl, const uint32_t *cell_of, const uint32_t *cell_star
     scan_u32_u32(units, uoff, n, cnt + 1, ar, s);
     k_unit_list<<<nb, 256, 0, s>>>(units, uoff, n, pl.ucell, pl.uchunk);
   } else {
-    PCC_HIP(hipMemsetAsync(cnt, 0, 2 * sizeof(uint32_t), s));
+    fill_u32(cnt, 0, 2, s);
   }
   uint32_t h[2] = {0, 0};
   PCC_HIP(hipMemcpyAsync(h, cnt, sizeof h, hipMemcpyDeviceToHost, s));

@@ -124,6 +124,10 @@ class Arena {
   }
   void reset();          // start a new call (previous data becomes invalid)
   void release();        // free everything
+  // Serve every request from the caller's buffer [base, base + bytes) and
+  // never allocate: a request that does not fit throws PCC_E_OUT_OF_MEMORY.
+  // release() then forgets the buffer without freeing it.
+  void attach(void *base, size_t bytes);
   size_t used() const { return used_; }
   size_t high_water() const { return high_; }
 
@@ -134,6 +138,7 @@ class Arena {
   };
   std::vector<Chunk> chunks_;
   size_t used_ = 0, high_ = 0, last_total_ = 0;
+  bool fixed_ = false;  // chunks_ holds one borrowed buffer
 };
 
 // ---------------------------------------------------------------------------

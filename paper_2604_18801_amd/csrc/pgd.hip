@@ -243,7 +243,7 @@ void build_csr(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t, con
                Arena &ar, hipStream_t s) {
   if (ne > kColRow) throw Error(-6, "more than 2^28 editable particles in one call");
   if (!na) {
-    PCC_HIP(hipMemsetAsync(row_ptr, 0, sizeof(uint32_t) * ((size_t)ne + 1), s));
+    fill_u32(row_ptr, 0, (size_t)ne + 1, s);
     return;
   }
   const size_t m = 2 * na;

@@ -217,6 +217,7 @@ __global__ void k_e_off(const uint32_t *eid, const int64_t *p_off, int njobs, si
 struct Staging {
   Context &C;
   hipStream_t s;
+  bool pageable;  // copy straight into the caller's host memory (no pinned buffer)
   void *get(size_t bytes) {
     if (C.pinned_bytes < bytes) {
       if (C.pinned) hipHostFree(C.pinned);
@@ -230,6 +231,11 @@ struct Staging {
   template <typename T>
   void fetch(T *host, const T *devp, size_t count) {
     if (!count) return;
+    if (pageable) {
+      PCC_HIP(hipMemcpyAsync(host, devp, count * sizeof(T), hipMemcpyDeviceToHost, s));
+      PCC_HIP(hipStreamSynchronize(s));
+      return;
+    }
     void *p = get(count * sizeof(T));
     PCC_HIP(hipMemcpyAsync(p, devp, count * sizeof(T), hipMemcpyDeviceToHost, s));
     PCC_HIP(hipStreamSynchronize(s));
@@ -367,37 +373,49 @@ const double2 *bc_table(Context &C, double beta1, double beta2, int64_t len) {
 
 namespace {
 pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_result *res,
-                          hipStream_t s, bool labels_only, bool multi);
+                          hipStream_t s, bool labels_only, bool multi, Arena *scratch);
 }  // namespace
 
+void create_events(Context &C) {
+  for (int k = 0; k < 12; ++k)
+    if (!C.ev[k]) PCC_HIP(hipEventCreate(&C.ev[k]));
+}
+
 pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_result *res,
-                     hipStream_t s, bool labels_only, bool multi) {
+                     hipStream_t s, bool labels_only, bool multi, Arena *scratch) {
+  if (scratch && (!labels_only || multi)) throw Error(-3, "a fixed scratch serves labels only");
   try {
-    return run_batch_impl(C, jobs, njobs_in, res, s, labels_only, multi);
+    return run_batch_impl(C, jobs, njobs_in, res, s, labels_only, multi, scratch);
   } catch (...) {
     // nothing the failed call queued may still be running when its error is
     // reported: the caller may free its buffers and the arena may be released
     (void)hipStreamSynchronize(s);
     (void)hipGetLastError();
-    C.last.valid = false;
+    if (!scratch) C.last.valid = false;
     throw;
   }
 }
 
 namespace {
 pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_result *res,
-                          hipStream_t s, bool labels_only, bool multi) {
+                          hipStream_t s, bool labels_only, bool multi, Arena *scratch) {
   const auto t_wall0 = std::chrono::steady_clock::now();
   PCC_HIP(hipSetDevice(C.device));
   PCC_HIP(hipStreamSynchronize(s));
-  C.last.valid = false;
-  C.arena.reset();
-  KernelTimer &kt = C.kt;
+  KernelTimer no_timing;  // off: reserving timing events would create them
+  KernelTimer &kt = scratch ? no_timing : C.kt;
+  if (!scratch) {
+    C.last.valid = false;
+    C.arena.reset();
+    create_events(C);
+  } else {
+    scratch->reset();
+    for (int k = 0; k < 12; ++k)
+      if (!C.ev[k]) throw Error(-3, "context without stage events");
+  }
   kt.begin_call();
-  Arena &ar = C.arena;
-  Staging st{C, s};
-  for (int k = 0; k < 12; ++k)
-    if (!C.ev[k]) PCC_HIP(hipEventCreate(&C.ev[k]));
+  Arena &ar = scratch ? *scratch : C.arena;
+  Staging st{C, s, scratch != nullptr};
   // stage boundary k; with PCC_VERBOSE set, waits for the stage and prints
   // the wall time since the call started (diagnostics only)
   const bool verbose = getenv("PCC_VERBOSE") != nullptr;
@@ -556,7 +574,9 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
           map.push_back(h.index);
         }
       std::vector<pcc_job_result> sub(rest.size());
-      pcc_status r = rest.empty() ? PCC_OK : run_batch(C, rest.data(), (int)rest.size(), sub.data(), s, labels_only);
+      pcc_status r = rest.empty() ? PCC_OK
+                                  : run_batch(C, rest.data(), (int)rest.size(), sub.data(), s,
+                                              labels_only, false, scratch);
       for (size_t q = 0; q < map.size(); ++q) res[map[q]] = sub[q];
       (void)r;
       pcc_status first = PCC_OK;
@@ -685,7 +705,7 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   pb.job_counts = dev<unsigned long long>(ar, n_jc);
   iota_u32(pb.safe_par, n, s);
   iota_u32(pb.fof_par, n, s);
-  PCC_HIP(hipMemsetAsync(pb.job_counts, 0, n_jc * sizeof(unsigned long long), s));
+  fill_u64((uint64_t *)pb.job_counts, 0, n_jc, s);
   {
     const int at = kt.start(0, s);
     launch_pair_pass1(pb, plan, s);

@@ -22,12 +22,26 @@ std::atomic<int64_t> g_alloc_fail_after{-1};
 Arena::~Arena() { release(); }
 
 void Arena::release() {
-  for (auto &c : chunks_) hipFree(c.base);
+  if (!fixed_)
+    for (auto &c : chunks_) hipFree(c.base);
   chunks_.clear();
   used_ = 0;
+  fixed_ = false;
+}
+
+void Arena::attach(void *base, size_t bytes) {
+  release();
+  chunks_.push_back({(char *)base, bytes, 0});
+  fixed_ = true;
+  high_ = 0;
 }
 
 void Arena::reset() {
+  if (fixed_) {
+    chunks_[0].off = 0;
+    used_ = 0;
+    return;
+  }
   size_t total = 0;
   for (auto &c : chunks_) total += c.size;
   // Consolidate into one chunk big enough for the previous call, unless that
@@ -57,6 +71,9 @@ void *Arena::alloc(size_t bytes) {
       return p;
     }
   }
+  if (fixed_)
+    throw Error(-2, "the static scratch buffer is exhausted (" + std::to_string(bytes) +
+                        " more bytes needed)");
   size_t last = chunks_.empty() ? 0 : chunks_.back().size;
   size_t sz = std::max(bytes, std::max(last, (size_t)64 << 20));
   void *p = nullptr;
@@ -180,7 +197,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(const Tin *in, Tout 
 template <typename Tin, typename Tout>
 static void scan_impl(const Tin *in, Tout *out, size_t n, Tout *total, Arena &ar, hipStream_t s) {
   if (n == 0) {
-    if (total) PCC_HIP(hipMemsetAsync(total, 0, sizeof(Tout), s));
+    if (total) k_fill<Tout><<<1, 64, 0, s>>>(total, (Tout)0, 1);
     return;
   }
   size_t nb = (n + kScanTile - 1) / kScanTile;

@@ -35,6 +35,9 @@ def test_host_only_entry_points():
     p = pcc.make_params(0.2, 0.05)
     assert p.m_bits == 16 and p.mode == 2 and abs(p.lr - 1e-3) < 1e-18
     assert L.pcc_stream_bound(1000, ctypes.byref(p)) > 1000 * 6
+    # the allocation-free FoF call's size limit (256 B per particle of a
+    # 128 MiB static scratch, 1 MiB kept back)
+    assert pcc.fof_labels_noalloc_max_n() == ((128 << 20) - (1 << 20)) // 256
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libpcc.so not built")
