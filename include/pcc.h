@@ -108,6 +108,14 @@ typedef struct {
   double *debug_xyz;     /* host [3][n] planar float64 coordinates before
                             quantisation (the reconstruction for particles
                             that were not edited); may be NULL */
+  /* Per-evaluation trace of the loop of Alg. 1 (the loss-against-iteration
+     curve of Sec. 4): entry t holds the tightened loss of Eq. 3 (float64)
+     and the number of violated selected constraints at iterate t, for
+     t = 0 .. min(iters, trace_cap - 1).  Host buffers of trace_cap entries;
+     either may be NULL (then trace_cap is ignored for it). */
+  double *loss_trace;
+  int64_t *viol_trace;
+  int64_t trace_cap;
 } pcc_outputs;
 
 #define PCC_NSTAGES 10
@@ -373,13 +381,18 @@ pcc_status pcc_debug_set(int32_t key, int64_t value);
 pcc_status pcc_debug_get(int32_t key, int64_t *value);
 
 /*
- * Served form: a job queue in front of the batched pass.  Worker threads
- * (n_streams of them, each with its own HIP stream and workspace on the
- * context's device) take the queued jobs in arrival order and run as many
- * of them together as max_inflight and their share of hbm_budget allow
- * (continuous batching: a batch starts as soon as a worker is free and takes
- * whatever has arrived).  Each job's results equal those of pcc_correct on
- * that job alone.  When a batch runs out of device memory its jobs are run
+ * Served form: a job queue in front of the batched pass, with
+ * iteration-level continuous batching.  Slot threads (n_streams of them,
+ * each with its own HIP stream and workspace on the context's device) take
+ * the queued jobs in arrival order, as many together as max_inflight and
+ * their share of hbm_budget allow, and run every stage up to the first PGD
+ * step on their own streams.  The PGD iterations of every prepared call then
+ * run in one shared loop (one stream, a captured graph of K steps over all
+ * resident calls): a call joins it between two replays and leaves it, to be
+ * encoded on its slot's stream, at the end of the replay in which its last
+ * job converged, so jobs that arrive while others iterate overlap with them
+ * and no job waits for a slower one.  Each job's results equal those of
+ * pcc_correct on that job alone.  When a batch runs out of device memory its jobs are run
  * again one at a time, and a job that runs out of memory alone gets one
  * more try after its worker's workspace is released.  Job buffers are borrowed until the job has finished;
  * device inputs must be ready (their producing stream synchronised) when
@@ -391,7 +404,7 @@ typedef struct {
   size_t hbm_budget;     /* device bytes the workers may use together; 0 = 80%
                             of the free memory at creation */
   int32_t max_inflight;  /* jobs per batch at most; 0 = 256 */
-  int32_t n_streams;     /* batches in flight at once (workers); 0 = 2 */
+  int32_t n_streams;     /* calls in flight at once (slots); 0 = 4 */
 } pcc_server_config;
 
 pcc_status pcc_server_create(pcc_context *ctx, const pcc_server_config *cfg,

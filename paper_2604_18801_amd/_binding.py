@@ -48,7 +48,8 @@ class Params(C.Structure):
 
 class Outputs(C.Structure):
     _fields_ = [("labels", C.c_void_p), ("stream", C.c_void_p), ("stream_cap", C.c_size_t),
-                ("stream_len", C.POINTER(C.c_size_t)), ("debug_xyz", C.c_void_p)]
+                ("stream_len", C.POINTER(C.c_size_t)), ("debug_xyz", C.c_void_p),
+                ("loss_trace", C.c_void_p), ("viol_trace", C.c_void_p), ("trace_cap", C.c_int64)]
 
 
 class Stats(C.Structure):
@@ -218,6 +219,24 @@ def _view(a) -> Tuple[Particles, object]:
     return Particles(base, base + st, base + 2 * st, a.shape[1], MEM_HOST, 0), a
 
 
+def _trace_buffers(out: "Outputs", k: int):
+    """Host buffers of a k-entry loss / violation trace, set into out."""
+    if k <= 0:
+        return None, None
+    tl = np.zeros(k, dtype=np.float64)
+    tv = np.zeros(k, dtype=np.int64)
+    out.loss_trace, out.viol_trace, out.trace_cap = tl.ctypes.data, tv.ctypes.data, k
+    return tl, tv
+
+
+def _trace_results(stats: Dict, tl, tv):
+    if tl is None:
+        return
+    m = min(len(tl), int(stats["iters"]) + 1)
+    stats["loss_trace"] = tl[:m].copy()
+    stats["viol_trace"] = tv[:m].copy()
+
+
 def _stream_handle(on_device: bool):
     if not on_device:
         return None
@@ -319,9 +338,11 @@ class Context:
 
     # ------------------------------------------------------------------
     def correct(self, orig, recon, b: float, xi: float, mode="hf", box=None, labels=True,
-                debug_xyz=False, stream_cap: Optional[int] = None, **opts):
+                debug_xyz=False, stream_cap: Optional[int] = None, trace: int = 0, **opts):
         """Alg. 1 on one snapshot.  Returns (stream bytes, labels, stats);
-        labels live where `orig` lives; stats['status'] is 0 or 1."""
+        labels live where `orig` lives; stats['status'] is 0 or 1.  With
+        trace = K > 0, stats['loss_trace'] / ['viol_trace'] hold the loss of
+        Eq. 3 and the violated-constraint count of the first K evaluations."""
         po, ko = _view(orig)
         pr, kr = _view(recon)
         n = po.n
@@ -342,6 +363,7 @@ class Context:
         dbg = np.zeros((3, max(n, 1)), dtype=np.float64) if debug_xyz else None
         out = Outputs(lab_ptr, sbuf.ctypes.data, cap, C.pointer(slen),
                       dbg.ctypes.data if dbg is not None else None)
+        tl, tv = _trace_buffers(out, trace)
         st = Stats()
         status = lib().pcc_correct(self._h, C.byref(po), C.byref(pr), C.byref(params),
                                    C.byref(out), C.byref(st),
@@ -352,6 +374,7 @@ class Context:
         res_lab = lab[:n] if lab is not None else None
         if dbg is not None:
             stats["debug_xyz"] = dbg[:, :n]
+        _trace_results(stats, tl, tv)
         return bytes(sbuf[: slen.value]), res_lab, stats
 
     def correct_multi(self, orig, recon, b_list: Sequence[float], xi: float, mode="hf",

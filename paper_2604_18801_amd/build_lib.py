@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build", "pcc")
 LIB = os.path.join(HERE, "libpcc.so")
 SOURCES = ["prims.hip", "cells.hip", "pairs.hip", "pgd.hip", "encode.hip", "decode.hip", "pipeline.hip",
-           "codec.cpp", "capi.cpp", "server.cpp", "tune.cpp", "scratch.hip"]
+           "codec.cpp", "capi.cpp", "server.cpp", "tune.cpp", "scratch.hip", "engine.cpp"]
 ARCH = os.environ.get("PCC_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -252,6 +252,9 @@ pcc_status pcc_correct_multi(pcc_context *ctx, const pcc_particles *orig,
     jobs[0].out.stream_cap = out->stream_cap;
     jobs[0].out.stream_len = out->stream_len;
     jobs[0].out.debug_xyz = out->debug_xyz;
+    jobs[0].out.loss_trace = out->loss_trace;
+    jobs[0].out.viol_trace = out->viol_trace;
+    jobs[0].out.trace_cap = out->trace_cap;
     std::vector<pcc_job_result> r(nb);
     for (auto &x : r) std::memset(&x, 0, sizeof x);
     pcc::run_batch(ctx->c, jobs.data(), nb, r.data(), pick(ctx, hip_stream), false, true);

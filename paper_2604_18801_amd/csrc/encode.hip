@@ -8,8 +8,11 @@
 
 namespace pcc {
 
-__device__ inline const double4 *final_buf(const EncBufs &b, int job) {
-  return (b.loop[job].t & 1) ? b.P1 : b.P0;
+// final position of row e of job `job`
+__device__ inline double3 final_pos(const EncBufs &b, int job, size_t e) {
+  double3 p;
+  load_p((b.loop[job].t & 1) ? b.P1 : b.P0, e, p.x, p.y, p.z);
+  return p;
 }
 
 __global__ void k_edit_flags(EncBufs B) {
@@ -17,7 +20,7 @@ __global__ void k_edit_flags(EncBufs B) {
        e += (size_t)gridDim.x * blockDim.x) {
     const int j = job_of(B.e_off, B.njobs, (int64_t)e);
     const uint32_t k = B.e_list[e];
-    const double4 p = final_buf(B, j)[e];
+    const double3 p = final_pos(B, j, e);
     const float4 r = B.rec[k];
     const bool moved = (p.x - (double)r.x) != 0.0 || (p.y - (double)r.y) != 0.0 ||
                        (p.z - (double)r.z) != 0.0;
@@ -40,7 +43,7 @@ __global__ void k_edit_codes(EncBufs B, const uint32_t *fstart) {
     const int64_t g = B.p_off[j] + __float_as_uint(B.pos[k].w);
     if (!B.flag8[g]) continue;
     const JobDev &J = B.jobs[j];
-    const double4 p = final_buf(B, j)[e];
+    const double3 p = final_pos(B, j, e);
     const float4 r = B.rec[k];
     const double d[3] = {p.x - (double)r.x, p.y - (double)r.y, p.z - (double)r.z};
     const int per = J.m_bits == 32 ? 2 : 1;
@@ -221,7 +224,7 @@ __global__ void k_debug_e(EncBufs B) {
     const int j = job_of(B.e_off, B.njobs, (int64_t)e);
     const uint32_t k = B.e_list[e];
     const int64_t g = B.p_off[j] + __float_as_uint(B.pos[k].w);
-    const double4 p = final_buf(B, j)[e];
+    const double3 p = final_pos(B, j, e);
     B.debug[g] = p.x;
     B.debug[B.n + g] = p.y;
     B.debug[2 * B.n + g] = p.z;

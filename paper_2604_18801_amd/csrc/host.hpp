@@ -61,8 +61,13 @@ struct KernelTimer {
   ~KernelTimer();
 };
 
+class PgdEngine;
+
 struct Context {
   int device = 0;
+  // served form: the shared PGD loop this context's calls join (none for a
+  // plain context)
+  PgdEngine *engine = nullptr;
   KernelTimer kt;
   int graph_iters = 8;
   bool force_exact_pairs = false;  // always count the kept pairs before writing them
@@ -104,6 +109,13 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs, pcc_job_result 
                      Arena *scratch = nullptr);
 // stage events of a context (created once, with the context)
 void create_events(Context &C);
+
+// engine.cpp: the shared PGD loop of the served form.  engine_run adds the
+// group gb (past its first step and renumbering, `active` jobs not done) to
+// the loop and returns when every job of it is done.
+PgdEngine *engine_create(int device, int graph_iters);
+void engine_destroy(PgdEngine *e);
+void engine_run(PgdEngine *e, const PgdBufs &gb, int32_t active);
 // scratch.hip: finds the device address of the static scratch of the
 // allocation-free calls on `device` (the current device), once per device
 void scratch_init(int device);

@@ -99,6 +99,33 @@ int64_t boruvka(uint64_t *key, uint32_t *u, uint32_t *v, size_t ncand, uint32_t 
                 uint32_t *out_i, uint32_t *out_j, uint8_t *out_t, Arena &ar, hipStream_t s);
 
 // pgd.hip
+// Iterates of the PGD loop: one record of kPStride float64 per editable row
+// (x, y, z, then padding).
+constexpr int kPStride = 3;
+__device__ inline void load_p(const double *P, size_t i, double &x, double &y, double &z) {
+  if (kPStride == 4) {
+    const double2 a = reinterpret_cast<const double2 *>(P)[2 * i];
+    x = a.x;
+    y = a.y;
+    z = P[4 * i + 2];
+  } else {
+    const double *p = P + (size_t)kPStride * i;
+    x = p[0];
+    y = p[1];
+    z = p[2];
+  }
+}
+__device__ inline void store_p(double *P, size_t i, double x, double y, double z) {
+  if (kPStride == 4) {
+    reinterpret_cast<double2 *>(P)[2 * i] = make_double2(x, y);
+    P[4 * i + 2] = z;
+  } else {
+    double *p = P + (size_t)kPStride * i;
+    p[0] = x;
+    p[1] = y;
+    p[2] = z;
+  }
+}
 struct PgdBufs {
   const JobDev *jobs;
   JobLoop *loop;
@@ -109,7 +136,7 @@ struct PgdBufs {
   size_t ne;
   const uint32_t *row_ptr, *col;
   size_t ninc;            // incidences: twice the active pairs
-  double4 *P0, *P1;
+  double *P0, *P1;        // [ne][kPStride]: x, y, z of each row
   double *m, *v;          // [3][ne]
   const float4 *xo;       // original position of each row
   int32_t *n_active;      // device: jobs not done
@@ -139,8 +166,25 @@ struct PgdBufs {
   int nwaves;             // waves of the step grid (blocks * waves per block)
 };
 // waves of the step grid for ne editable rows (the step launches exactly
-// nwaves / 4 blocks of 4 waves)
+// nwaves / 4 blocks of 4 waves), and of the largest grid; a job's loss slots
+// are min(its tiles, pgd_max_waves())
 int pgd_step_waves(size_t ne);
+int pgd_max_waves();
+
+// The groups one step launch walks: each group is the PGD state of one call
+// (PgdBufs), its tiles follow the previous group's in the launch's tile
+// space, and its jobs' finalize blocks follow the previous group's.  A plain
+// call is one group; the served form's shared loop holds several.
+constexpr int kMaxGroups = 64;
+constexpr int kMaxGroupJobs = 4096;  // jobs of all groups of the shared loop
+struct PgdGroups {
+  int32_t ngroups;
+  int32_t pad;
+  int64_t tile_base[kMaxGroups + 1];
+  int32_t job_base[kMaxGroups + 1];
+  int32_t active[kMaxGroups];  // shared loop: the groups' not-done job counts
+  PgdBufs g[kMaxGroups];
+};
 // a_k (threshold index per pair) may be NULL; when set it is the last key
 void sort_pairs(uint32_t *a_i, uint32_t *a_j, uint8_t *a_t, uint8_t *a_k, size_t na,
                 const float4 *pos, int id_bits, Arena &ar, hipStream_t s);
@@ -162,7 +206,7 @@ void build_csr(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t, con
                size_t na, const uint32_t *eid, uint32_t ne, uint32_t *row_ptr, uint32_t *col,
                Arena &ar, hipStream_t s);
 void launch_pgd_init(const uint32_t *e_list, size_t ne, const float4 *pos, const float4 *rec,
-                     double4 *P0, float4 *xo, double *m, double *v, hipStream_t s);
+                     double *P0, float4 *xo, double *m, double *v, hipStream_t s);
 // worklist of the first step: every row; no row hot yet
 void launch_hot_init(const PgdBufs &b, hipStream_t s);
 // After the first step: renumbers each job's rows so that its hot rows come
@@ -172,8 +216,13 @@ void launch_hot_init(const PgdBufs &b, hipStream_t s);
 void renumber_hot(PgdBufs &b, uint32_t *&e_list, Arena &ar, hipStream_t s);
 void launch_loop_init(const JobDev *jobs, JobLoop *loop, int njobs, int32_t *n_active,
                       hipStream_t s);
-void launch_pgd_step(const PgdBufs &b, hipStream_t s);
-void launch_pgd_finalize(const PgdBufs &b, hipStream_t s);
+// one step (and its finalize) over the groups of the device table g; the
+// host copy h gives the launch sizes of a plain call (one group)
+void launch_pgd_step(const PgdGroups *g, const PgdBufs &h, hipStream_t s);
+void launch_pgd_finalize(const PgdGroups *g, const PgdBufs &h, hipStream_t s);
+// the shared loop's launches: the largest grid, kMaxGroupJobs finalize blocks
+void launch_pgd_step_shared(const PgdGroups *g, hipStream_t s);
+void launch_pgd_finalize_shared(const PgdGroups *g, hipStream_t s);
 
 // encode.hip
 struct EncBufs {
@@ -185,7 +234,7 @@ struct EncBufs {
   size_t ne, n;
   const uint32_t *e_list;
   const float4 *pos, *rec;
-  const double4 *P0, *P1;
+  const double *P0, *P1;   // [ne][kPStride]
   uint8_t *flag8;          // [n] global original order
   uint32_t *fpos;          // exclusive scan of flag8
   uint16_t *sym;           // symbols

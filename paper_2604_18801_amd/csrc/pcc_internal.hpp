@@ -76,6 +76,11 @@ struct JobDev {
   int32_t nthr;
   double thr_bm[kMaxThresholds], thr_bp[kMaxThresholds];
   double thr_bm2[kMaxThresholds], thr_bp2[kMaxThresholds];
+  // per-evaluation trace of the loop (loss of Eq. 3, violated constraints),
+  // entries 0 .. trace_cap - 1 (device; none when trace_cap = 0)
+  double *trace_loss;
+  unsigned long long *trace_viol;
+  int64_t trace_cap;
 };
 
 // Mutable per-job state of the correction loop (device memory).

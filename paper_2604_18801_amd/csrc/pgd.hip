@@ -255,12 +255,12 @@ void build_csr(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t, con
 }
 
 __global__ void k_pgd_init(const uint32_t *e_list, size_t ne, const float4 *pos, const float4 *rec,
-                           double4 *P0, float4 *xo, double *m, double *v) {
+                           double *P0, float4 *xo, double *m, double *v) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne;
        e += (size_t)gridDim.x * blockDim.x) {
     const uint32_t k = e_list[e];
     const float4 r = rec[k];
-    P0[e] = make_double4((double)r.x, (double)r.y, (double)r.z, 0.0);
+    store_p(P0, e, (double)r.x, (double)r.y, (double)r.z);
     xo[e] = pos[k];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -271,7 +271,7 @@ __global__ void k_pgd_init(const uint32_t *e_list, size_t ne, const float4 *pos,
 }
 
 void launch_pgd_init(const uint32_t *e_list, size_t ne, const float4 *pos, const float4 *rec,
-                     double4 *P0, float4 *xo, double *m, double *v, hipStream_t s) {
+                     double *P0, float4 *xo, double *m, double *v, hipStream_t s) {
   if (ne) k_pgd_init<<<blocks_for(ne, 256, 65536), 256, 0, s>>>(e_list, ne, pos, rec, P0, xo, m, v);
 }
 
@@ -324,23 +324,54 @@ __device__ inline void wave_sync() {
 }
 
 constexpr int kPgdWaves = 4;
-#ifndef PCC_PGD_BLOCKS
-#define PCC_PGD_BLOCKS 1024
+#ifndef PCC_PGD_MIN_WAVES
+#define PCC_PGD_MIN_WAVES 4
 #endif
-constexpr int kPgdBlocks = PCC_PGD_BLOCKS;  // 4096 waves: one round of 4 per SIMD
+// a persistent grid of PCC_PGD_MIN_WAVES waves per SIMD on the 256 CUs
+constexpr int kPgdBlocks = 256 * 4 * PCC_PGD_MIN_WAVES / kPgdWaves;
 
 int pgd_step_waves(size_t ne) { return blocks_for(ne, 64 * kPgdWaves, kPgdBlocks) * kPgdWaves; }
+int pgd_max_waves() { return kPgdBlocks * kPgdWaves; }
 
-// flush of a wave's counts for one job: the violation count (the same in
-// every lane) is added into the wave's counter slot; the loss (per lane) is
+// tiles with at most this many incidences per lane take the chunked
+// evaluation, the others the per-lane walk of whole rows
+constexpr uint32_t kChunkPerLane = 24;
+
+// group of a tile (or of a finalize block): the last with base <= x
+template <typename T>
+__device__ inline int group_of(const T *base, int ngroups, int64_t x) {
+  int lo = 0, hi = ngroups - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((int64_t)base[mid] <= x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// The dispatcher hands consecutive blocks to the 8 XCDs in turn, and each
+// XCD has its own L2.  Renumbering the blocks so that every XCD holds a
+// contiguous range of them makes the tiles it walks at the same time
+// neighbours in row (Morton) order, whose partner gathers then share its L2.
+__device__ inline int xcd_block() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  if (nb & 7) return b;
+  return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+// flush of a wave's counts for one job: the violation count is summed over
+// the wave and added into the wave's counter slot; the loss (per lane) is
 // summed over the wave and stored into the job's loss slot of this wave
-__device__ inline void flush_counts(const PgdBufs &B, int job, int lslot,
+__device__ inline void flush_counts(const PgdBufs &B, int job, int lslot, int wave_id,
                                     unsigned long long &viol, double &loss) {
   const double sl = wsum_d(loss);
+  const unsigned long long sv = wsum(viol);
   if ((threadIdx.x & 63) == 0 && job >= 0) {
-    if (viol) {
-      const int slot = (int)((blockIdx.x * kPgdWaves + (threadIdx.x >> 6)) & (B.acc_slots - 1));
-      atomicAdd(B.acc + ((size_t)job * B.acc_slots + slot) * 16, viol);
+    if (sv) {
+      const int slot = wave_id & (B.acc_slots - 1);
+      atomicAdd(B.acc + ((size_t)job * B.acc_slots + slot) * 16, sv);
     }
     B.lossp[B.lp_off[job] + lslot] = sl;
   }
@@ -366,205 +397,330 @@ __device__ inline uint64_t dbits(double x) { return (uint64_t)__double_as_longlo
 // iterates, the violation counts and the loss are exactly those of
 // evaluating every row in every step.
 //
-// The incidences of the tile's rows are concatenated and spread over the 64
-// lanes, 64 at a time: each lane gathers one partner, evaluates one
-// constraint and leaves its gradient term in LDS; then each row's owner
-// lane adds the terms of its row in column order (increasing partner index).
-// Finally every row takes the Adam step and the projection.  Counts stay in
+// Evaluation.  The tile's incidences, row after row, are cut into 64 runs
+// of about equal length at row boundaries: lane L takes the rows whose
+// first incidence falls in [L T / 64, (L + 1) T / 64) (T incidences in the
+// tile), so every row is walked by one lane, in partner order, and its
+// gradient is summed in exactly that order.  Each lane keeps the column
+// entry two incidences ahead and the partner position one ahead in flight.
+// The gradients go through LDS to the Adam step and the projection, where
+// lane r takes row r (coalesced row reads and writes).  Counts stay in
 // registers until the wave moves to another job or finishes.
-#ifndef PCC_PGD_MIN_WAVES
-#define PCC_PGD_MIN_WAVES 4
-#endif
-__global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(PgdBufs B) {
-  // positions of the tile's rows, one array per axis: lanes read rows at
-  // random, and 8-byte entries spread them over the LDS banks
-  __shared__ double s_px[kPgdWaves][64], s_py[kPgdWaves][64], s_pz[kPgdWaves][64];
-  __shared__ double s_term[kPgdWaves][3][64];
-  __shared__ uint32_t s_rp[kPgdWaves][64];  // first incidence of each row in the CSR
-  __shared__ uint32_t s_vb[kPgdWaves][64];  // first slot of each row in the tile's work list
-  __shared__ uint32_t s_e[kPgdWaves][64];   // row index
-  __shared__ uint8_t s_mk[kPgdWaves][64];   // the row marks its partners hot
-  // loss thresholds b -+ delta_t and their squares per linking length of a
-  // multi-threshold job (read from LDS: a memory load in the evaluation
-  // would make the gathers already in flight complete first)
-  __shared__ double s_thr[kPgdWaves][4][kMaxThresholds];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+__global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES)
+    k_pgd_step(const PgdGroups *__restrict__ G) {
+  // LDS of one wave: one struct, so that every access is the wave's base
+  // (uniform) plus the lane's or row's offset plus a constant
+  struct WaveLds {
+    double px[64], py[64], pz[64];  // row positions
+    double gx[64], gy[64], gz[64];  // row gradients
+    double tx[64], ty[64], tz[64];  // chunked evaluation: one term per lane
+    // loss thresholds b -+ delta_t and their squares per linking length of
+    // a multi-threshold job
+    double thr[4][kMaxThresholds];
+    uint32_t vb[65];    // tile offset of each row's first incidence
+    uint32_t base[64];  // CSR position of a row's incidence f: base + f
+    uint32_t e[64];     // row index
+    uint8_t hit[64];    // some constraint of the row is violated
+    uint8_t mk[64];     // the row marks its partners hot
+  };
+  __shared__ WaveLds s_lds[kPgdWaves];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  WaveLds &S = s_lds[w];
   const int64_t nwaves = (int64_t)gridDim.x * kPgdWaves;
+  const int wave_id = xcd_block() * kPgdWaves + w;
   unsigned long long viol = 0;
   double loss = 0.0;
-  int cjob = -1;   // job whose counts are held in the registers above
+  int cgrp = 0;    // group and job whose counts are held in the registers above
+  int cjob = -1;
   int cslot = 0;   // this wave's loss slot of that job
-  for (int64_t tile = (int64_t)blockIdx.x * kPgdWaves + w; tile < B.ntiles; tile += nwaves) {
-    const int job = __builtin_amdgcn_readfirstlane(job_of(B.tile_off, B.njobs, tile));
+  const int ngroups = G->ngroups;
+  const int64_t ntiles = G->tile_base[ngroups];
+  for (int64_t tile = wave_id; tile < ntiles; tile += nwaves) {
+    const int grp =
+        ngroups > 1 ? __builtin_amdgcn_readfirstlane(group_of(G->tile_base, ngroups, tile)) : 0;
+    const PgdBufs &B = G->g[grp];
+    const int64_t tl = tile - G->tile_base[grp];  // tile within its group
+    const int job = __builtin_amdgcn_readfirstlane(job_of(B.tile_off, B.njobs, tl));
     if (B.loop[job].done) continue;
     const int64_t eoff = B.e_off[job];
-    const int64_t w0 = (tile - B.tile_off[job]) * 64;  // first worklist entry of the tile
+    const int64_t w0 = (tl - B.tile_off[job]) * 64;  // first worklist entry of the tile
     const int64_t left = (int64_t)B.wl_step[job] - w0;
     if (left <= 0) continue;
-    if (job != cjob) {
-      flush_counts(B, cjob, cslot, viol, loss);
+    if (job != cjob || grp != cgrp) {
+      flush_counts(G->g[cgrp], cjob, cslot, wave_id, viol, loss);
+      cgrp = grp;
       cjob = job;
-      cslot = (int)((tile - B.tile_off[job]) % nwaves);
+      cslot = (int)((tl - B.tile_off[job]) % nwaves);
     }
     const int64_t t_step = B.loop[job].t;
     const int nrow = (int)(left < 64 ? left : 64);
     const bool valid = lane < nrow;
     const JobDev &J = B.jobs[job];
     const int cur = (int)(t_step & 1);
-    const double4 *__restrict__ Pc = cur ? B.P1 : B.P0;
-    double4 *__restrict__ Pn = cur ? B.P0 : B.P1;
+    const double *__restrict__ Pc = cur ? B.P1 : B.P0;
+    double *__restrict__ Pn = cur ? B.P0 : B.P1;
     const double L0 = J.L[0], L1 = J.L[1], L2 = J.L[2];
     const double h0 = J.hL[0], h1 = J.hL[1], h2 = J.hL[2];
     const double bm = J.bm, bp = J.bp, bm2 = J.bm2, bp2 = J.bp2;
-    // the row's position and incidence range; its Adam state is loaded
-    // after the gathers (fewer live registers, more waves in flight)
-    size_t e = 0;
-    uint32_t q0 = 0, len = 0;
-    double4 pe = make_double4(0.0, 0.0, 0.0, 0.0);
-    if (valid) {
-      e = B.wl[eoff + w0 + lane];
-      q0 = B.row_ptr[e];
-      len = B.row_ptr[e + 1] - q0;
-      pe = Pc[e];
-    }
-    uint32_t incl = len;  // inclusive prefix sum of len over the wave
+    const bool multi = J.nthr > 1;
+    // the row's position and incidence range go to LDS; its Adam state is
+    // loaded after the walk (fewer live registers, more waves in flight)
+    uint32_t total;
+    {
+      size_t e = 0;
+      uint32_t q0 = 0, len = 0;
+      double pex = 0.0, pey = 0.0, pez = 0.0;
+      if (valid) {
+        e = B.wl[eoff + w0 + lane];
+        q0 = B.row_ptr[e];
+        len = B.row_ptr[e + 1] - q0;
+        load_p(Pc, e, pex, pey, pez);
+      }
+      uint32_t incl = len;  // inclusive prefix sum of len over the wave
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t y = __shfl_up(incl, d, kWave);
-      if (lane >= d) incl += y;
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += y;
+      }
+      const uint32_t vb = incl - len;
+      total = __shfl(incl, 63, kWave);
+      S.px[lane] = pex;
+      S.py[lane] = pey;
+      S.pz[lane] = pez;
+      S.gx[lane] = 0.0;
+      S.gy[lane] = 0.0;
+      S.gz[lane] = 0.0;
+      S.hit[lane] = 0;
+      S.vb[lane] = vb;
+      if (lane == 63) S.vb[64] = total;
+      S.base[lane] = q0 - vb;
+      S.e[lane] = (uint32_t)e;
     }
-    const uint32_t vb = incl - len, total = __shfl(incl, 63, kWave);
-    s_px[w][lane] = pe.x;
-    s_py[w][lane] = pe.y;
-    s_pz[w][lane] = pe.z;
-    s_rp[w][lane] = q0;
-    s_vb[w][lane] = vb;
-    s_e[w][lane] = (uint32_t)e;
-    if (J.nthr > 1 && lane < 4 * kMaxThresholds) {
+    if (multi && lane < 4 * kMaxThresholds) {
       const int a = lane / kMaxThresholds, k = lane % kMaxThresholds;
       const double *src = a == 0 ? J.thr_bm : a == 1 ? J.thr_bp : a == 2 ? J.thr_bm2 : J.thr_bp2;
-      s_thr[w][a][k] = src[k];
+      S.thr[a][k] = src[k];
     }
     wave_sync();
-    double gx = 0.0, gy = 0.0, gz = 0.0;
-    bool hrow = false;  // some constraint of the row is violated
-    // owner row of slot q (last r with s_vb[r] <= q) and its column entry;
-    // each chunk loads the next chunk's entries before it waits for its own
-    // gathers
-    auto locate = [&](uint32_t q, int &r, uint32_t &col) {
-      int lo = 0, hi = nrow - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_vb[w][mid] <= q)
-          lo = mid;
-        else
-          hi = mid - 1;
-      }
-      r = lo;
-      col = B.col[s_rp[w][lo] + (q - s_vb[w][lo])];
-    };
-    // two-deep pipeline: while chunk c is evaluated, the partner gather of
-    // chunk c + 1 and the column entries of chunk c + 2 are in flight
-    auto gather = [&](uint32_t col) {
-      const double *pp = reinterpret_cast<const double *>(Pc + (col & kColRow));
-      return make_double3(pp[0], pp[1], pp[2]);
-    };
-    int r_nx = 0, r_nx2 = 0;
-    uint32_t col_nx = 0, col_nx2 = 0;
-    double3 po_nx = make_double3(0.0, 0.0, 0.0);
-    if ((uint32_t)lane < total) {
-      locate(lane, r_nx, col_nx);
-      po_nx = gather(col_nx);
-    }
-    if ((uint32_t)lane + 64 < total) locate(lane + 64, r_nx2, col_nx2);
-    for (uint32_t c0 = 0; c0 < total; c0 += 64) {
-      const uint32_t q = c0 + lane;
-      double tx = 0.0, ty = 0.0, tz = 0.0;
-      bool hit = false, hit_once = false;
-      const int r = r_nx;
-      const uint32_t col = col_nx;
-      const double3 po = po_nx;
-      r_nx = r_nx2;
-      col_nx = col_nx2;
-      if (q + 64 < total) po_nx = gather(col_nx);
-      if (q + 128 < total) locate(q + 128, r_nx2, col_nx2);
-      if (q < total) {
-        const uint32_t o = col & kColRow;
-        const uint32_t er = s_e[w][r];
-        const double dx = wrapd(s_px[w][r] - po.x, L0, h0);
-        const double dy = wrapd(s_py[w][r] - po.y, L1, h1);
-        const double dz = wrapd(s_pz[w][r] - po.z, L2, h2);
-        const double d2 = (dx * dx + dy * dy) + dz * dz;
-        // squared threshold of the constraint (b - delta_t for a potentially
-        // broken link, b + delta_t for a potentially created pair): of the
-        // job's linking length, or of the constraint's own when several are
-        // corrected at once
-        const bool created = (col & kColPc) != 0;
-        const uint32_t kk = (col >> kColThrShift) & 7u;
-        double t2 = created ? bp2 : bm2;
-        if (kk) t2 = s_thr[w][created ? 3 : 2][kk];
-        double h = 0.0;
-        if (created ? d2 <= t2 : d2 > t2) {
-          double t1 = created ? bp : bm;
-          if (kk) t1 = s_thr[w][created ? 1 : 0][kk];
-          const double d = sqrt(d2);
-          if (!created) {
-            // potentially broken: an original link pulled back inside b - delta_t
-            h = d - t1;
-            tx = 2.0 * h * (dx / d);
-            ty = 2.0 * h * (dy / d);
-            tz = 2.0 * h * (dz / d);
-          } else {
-            // potentially created: an original non-link pushed beyond b + delta_t
-            h = t1 - d;
-            double ux, uy, uz;
-            if (d > 0.0) {
-              ux = dx / d;
-              uy = dy / d;
-              uz = dz / d;
-            } else {
-              // coincident points: take the direction of the original pair
-              const float4 a = B.xo[er], b = B.xo[o];
-              const double ox = wrapd((double)a.x - (double)b.x, L0, h0);
-              const double oy = wrapd((double)a.y - (double)b.y, L1, h1);
-              const double oz = wrapd((double)a.z - (double)b.z, L2, h2);
-              const double od = sqrt((ox * ox + oy * oy) + oz * oz);
-              ux = ox / od;
-              uy = oy / od;
-              uz = oz / od;
-            }
-            tx = -(2.0 * h * ux);
-            ty = -(2.0 * h * uy);
-            tz = -(2.0 * h * uz);
-          }
-          hit = true;
+    // the term of one incidence (column word col, partner position o) in
+    // the row at r (index er); a violated pair adds its squared hinge and a
+    // count once, in the row of its smaller index
+    auto eval = [&](uint32_t col, double ox, double oy, double oz, double rx, double ry,
+                    double rz, uint32_t er, double &tx, double &ty, double &tz) -> bool {
+      const uint32_t o = col & kColRow;
+      const double dx = wrapd(rx - ox, L0, h0);
+      const double dy = wrapd(ry - oy, L1, h1);
+      const double dz = wrapd(rz - oz, L2, h2);
+      const double d2 = (dx * dx + dy * dy) + dz * dz;
+      // squared threshold of the constraint (b - delta_t for a potentially
+      // broken link, b + delta_t for a potentially created pair): of the
+      // job's linking length, or of the constraint's own when several are
+      // corrected at once
+      const bool created = (col & kColPc) != 0;
+      const uint32_t kk = (col >> kColThrShift) & 7u;
+      double t2 = created ? bp2 : bm2;
+      if (kk) t2 = S.thr[created ? 3 : 2][kk];
+      if (!(created ? d2 <= t2 : d2 > t2)) return false;
+      double t1 = created ? bp : bm;
+      if (kk) t1 = S.thr[created ? 1 : 0][kk];
+      const double d = sqrt(d2);
+      double h;
+      if (!created) {
+        // potentially broken: an original link pulled back inside b - delta_t
+        h = d - t1;
+        // one divide at a time (interleaved divide sequences cost
+        // registers, hence occupancy)
+        tx = 2.0 * h * (dx / d);
+        __builtin_amdgcn_sched_barrier(0);
+        ty = 2.0 * h * (dy / d);
+        __builtin_amdgcn_sched_barrier(0);
+        tz = 2.0 * h * (dz / d);
+      } else {
+        // potentially created: an original non-link pushed beyond b + delta_t
+        h = t1 - d;
+        double ux, uy, uz;
+        if (d > 0.0) {
+          ux = dx / d;
+          __builtin_amdgcn_sched_barrier(0);
+          uy = dy / d;
+          __builtin_amdgcn_sched_barrier(0);
+          uz = dz / d;
+        } else {
+          // coincident points: take the direction of the original pair
+          const float4 a = B.xo[er], b = B.xo[o];
+          const double ox2 = wrapd((double)a.x - (double)b.x, L0, h0);
+          const double oy2 = wrapd((double)a.y - (double)b.y, L1, h1);
+          const double oz2 = wrapd((double)a.z - (double)b.z, L2, h2);
+          const double od = sqrt((ox2 * ox2 + oy2 * oy2) + oz2 * oz2);
+          ux = ox2 / od;
+          uy = oy2 / od;
+          uz = oz2 / od;
         }
-        if (hit && o > er) loss += h * h;
-        hit_once = hit && o > er;
+        tx = -(2.0 * h * ux);
+        ty = -(2.0 * h * uy);
+        tz = -(2.0 * h * uz);
       }
-      s_term[w][0][lane] = tx;
-      s_term[w][1][lane] = ty;
-      s_term[w][2][lane] = tz;
-      const uint64_t hb = __ballot(hit);
-      viol += (unsigned)__popcll(__ballot(hit_once));
-      wave_sync();
-      // the owner adds the terms of its row that fall in this chunk, in order
-      const uint32_t a = vb > c0 ? vb : c0;
-      const uint32_t b = vb + len < c0 + 64 ? vb + len : c0 + 64;
-      for (uint32_t t = a; t < b; ++t) {
-        gx += s_term[w][0][t - c0];
-        gy += s_term[w][1][t - c0];
-        gz += s_term[w][2][t - c0];
+      if (o > er) {
+        loss += h * h;
+        viol += 1;
       }
-      if (b > a) {
-        const uint32_t wd = b - a;
-        const uint64_t mask = (wd >= 64 ? ~0ull : ((1ull << wd) - 1ull)) << (a - c0);
-        hrow |= (hb & mask) != 0;
+      return true;
+    };
+    auto gather = [&](uint32_t col, double &x, double &y, double &z) {
+      load_p(Pc, col & kColRow, x, y, z);
+    };
+    // this lane's rows [r0, r1) in the balanced walk: those whose first
+    // incidence lies in [ta, tb)
+    const uint32_t ta = (uint32_t)(((uint64_t)lane * total + 63u) / 64u);
+    const uint32_t tb = (uint32_t)(((uint64_t)(lane + 1) * total + 63u) / 64u);
+    auto first_at = [&](uint32_t t) {
+      int lo = 0, hi = nrow;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (S.vb[mid] < t)
+          lo = mid + 1;
+        else
+          hi = mid;
       }
-      wave_sync();
+      return lo;
+    };
+    const int r0 = first_at(ta), r1 = first_at(tb);
+    const uint32_t fA = S.vb[r0], fB = S.vb[r1];
+    if (total <= 64u * kChunkPerLane) {
+      // Few incidences per lane: they are spread over the lanes 64 at a
+      // time (one partner gather per lane, two chunks in flight), each
+      // lane leaves its term in LDS and the row's own lane adds the terms
+      // of its row in column order.  A long row then costs one lane a few
+      // LDS adds instead of a lane walking it while the others wait.
+      double gx = 0.0, gy = 0.0, gz = 0.0;
+      bool hrow = false;
+      const uint32_t vb = S.vb[lane], vend = S.vb[lane < 63 ? lane + 1 : 64];
+      // row of tile slot q: the last row starting at or before it
+      auto locate = [&](uint32_t q, int &r, uint32_t &col) {
+        int lo = 0, hi = nrow - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (S.vb[mid] <= q)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        r = lo;
+        col = B.col[S.base[lo] + q];
+      };
+      int r_nx = 0, r_nx2 = 0;
+      uint32_t col_nx = 0, col_nx2 = 0;
+      double ax = 0.0, ay = 0.0, az = 0.0;
+      if ((uint32_t)lane < total) {
+        locate(lane, r_nx, col_nx);
+        gather(col_nx, ax, ay, az);
+      }
+      if ((uint32_t)lane + 64 < total) locate(lane + 64, r_nx2, col_nx2);
+      for (uint32_t c0 = 0; c0 < total; c0 += 64) {
+        const uint32_t q = c0 + lane;
+        double tx = 0.0, ty = 0.0, tz = 0.0;
+        bool hit = false;
+        const int r = r_nx;
+        const uint32_t col = col_nx;
+        const double ox = ax, oy = ay, oz = az;
+        r_nx = r_nx2;
+        col_nx = col_nx2;
+        if (q + 64 < total) gather(col_nx, ax, ay, az);
+        if (q + 128 < total) locate(q + 128, r_nx2, col_nx2);
+        if (q < total) hit = eval(col, ox, oy, oz, S.px[r], S.py[r], S.pz[r], S.e[r], tx, ty, tz);
+        S.tx[lane] = tx;
+        S.ty[lane] = ty;
+        S.tz[lane] = tz;
+        const uint64_t hb = __ballot(hit);
+        wave_sync();
+        // the row's lane adds its terms that fall in this chunk, in order
+        const uint32_t a = vb > c0 ? vb : c0;
+        const uint32_t b = vend < c0 + 64 ? vend : c0 + 64;
+        for (uint32_t t = a; t < b; ++t) {
+          gx += S.tx[t - c0];
+          gy += S.ty[t - c0];
+          gz += S.tz[t - c0];
+        }
+        if (b > a) {
+          const uint32_t wd = b - a;
+          const uint64_t mask = (wd >= 64 ? ~0ull : ((1ull << wd) - 1ull)) << (a - c0);
+          hrow |= (hb & mask) != 0;
+        }
+        wave_sync();
+      }
+      if (valid) {
+        S.gx[lane] = gx;
+        S.gy[lane] = gy;
+        S.gz[lane] = gz;
+        S.hit[lane] = hrow ? 1 : 0;
+      }
+    } else if (fA < fB) {
+      // Many incidences per lane: each lane walks its run of whole rows,
+      // in partner order, the column entry two incidences ahead and the
+      // partner position one ahead in flight.
+      // row of incidence f (rows only move forward; empty rows are skipped)
+      auto row_of = [&](int r, uint32_t f) {
+        while (S.vb[r + 1] <= f) ++r;
+        return r;
+      };
+      // the row being summed and its own data
+      int rr = row_of(r0, fA);
+      uint32_t rend = S.vb[rr + 1];
+      uint32_t er = S.e[rr];
+      double rx = S.px[rr], ry = S.py[rr], rz = S.pz[rr];
+      double gx = 0.0, gy = 0.0, gz = 0.0;
+      bool hrow = false;
+      uint32_t col_a = B.col[S.base[rr] + fA];
+      double ax, ay, az;
+      gather(col_a, ax, ay, az);
+      int rb = rr;
+      uint32_t col_b = 0;
+      if (fA + 1 < fB) {
+        rb = row_of(rr, fA + 1);
+        col_b = B.col[S.base[rb] + fA + 1];
+      }
+      for (uint32_t f = fA; f < fB; ++f) {
+        const uint32_t col = col_a;
+        const double ox = ax, oy = ay, oz = az;
+        if (f + 1 < fB) {
+          col_a = col_b;
+          gather(col_a, ax, ay, az);
+        }
+        if (f + 2 < fB) {
+          rb = row_of(rb, f + 2);
+          col_b = B.col[S.base[rb] + f + 2];
+        }
+        double tx, ty, tz;
+        if (eval(col, ox, oy, oz, rx, ry, rz, er, tx, ty, tz)) {
+          gx += tx;
+          gy += ty;
+          gz += tz;
+          hrow = true;
+        }
+        if (f + 1 == rend) {
+          S.gx[rr] = gx;
+          S.gy[rr] = gy;
+          S.gz[rr] = gz;
+          S.hit[rr] = hrow ? 1 : 0;
+          if (f + 1 < fB) {
+            rr = row_of(rr + 1, f + 1);
+            rend = S.vb[rr + 1];
+            er = S.e[rr];
+            rx = S.px[rr];
+            ry = S.py[rr];
+            rz = S.pz[rr];
+            gx = 0.0;
+            gy = 0.0;
+            gz = 0.0;
+            hrow = false;
+          }
+        }
+      }
     }
+    wave_sync();
     bool mark = false;
     if (valid) {
+      const size_t e = S.e[lane];
       const uint32_t hotv = B.hot[e];
       const float4 x = B.xo[e];
       double mo[3], vo[3];
@@ -581,8 +737,8 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
       const double lr = J.lr, beta1 = J.beta1, beta2 = J.beta2,
                    omb1 = J.one_m_beta1,
                    omb2 = J.one_m_beta2, aeps = J.adam_eps, xip = J.xi_p;
-      const double g[3] = {gx, gy, gz};
-      const double p[3] = {s_px[w][lane], s_py[w][lane], s_pz[w][lane]};
+      const double g[3] = {S.gx[lane], S.gy[lane], S.gz[lane]};
+      const double p[3] = {S.px[lane], S.py[lane], S.pz[lane]};
       const double xs[3] = {(double)x.x, (double)x.y, (double)x.z};
       double np[3];
       uint64_t state = 0;
@@ -609,29 +765,31 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
         // square-root sequences costs registers, hence occupancy
         __builtin_amdgcn_sched_barrier(0);
       }
-      Pn[e] = make_double4(np[0], np[1], np[2], 0.0);
+      store_p(Pn, e, np[0], np[1], np[2]);
       // a live row that has not yet done so marks itself and its partners hot
-      mark = (moved || hrow || state != 0) && hotv != 2;
+      mark = (moved || S.hit[lane] || state != 0) && hotv != 2;
       if (mark) B.hot[e] = 2;
     }
     if (__ballot(mark)) {
-      s_mk[w][lane] = mark ? 1 : 0;
+      S.mk[lane] = mark ? 1 : 0;
       wave_sync();
-      for (uint32_t c0 = 0; c0 < total; c0 += 64) {
-        const uint32_t q = c0 + lane;
+      // the same runs as the evaluation, walked in step by every lane (the
+      // appends below take a wave-wide ballot)
+      unsigned long long run = fB - fA;
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) {
+        const unsigned long long y = __shfl_xor(run, d, kWave);
+        run = y > run ? y : run;
+      }
+      int rm = fA < fB ? r0 : 0;
+      for (uint32_t k = 0; k < (uint32_t)run; ++k) {
+        const uint32_t f = fA + k;
         bool app = false;
         uint32_t o = 0;
-        if (q < total) {
-          int lo = 0, hi = nrow - 1;
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_vb[w][mid] <= q)
-              lo = mid;
-            else
-              hi = mid - 1;
-          }
-          if (s_mk[w][lo]) {
-            o = B.col[s_rp[w][lo] + (q - s_vb[w][lo])] & kColRow;
+        if (f < fB) {
+          while (S.vb[rm + 1] <= f) ++rm;
+          if (S.mk[rm]) {
+            o = B.col[S.base[rm] + f] & kColRow;
             uint32_t cold = 0u;
             // the first marking of a cold row appends it to the worklist
             // (after the first step, which lists every row and is followed
@@ -658,7 +816,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_step(
     }
     wave_sync();  // LDS of this tile is reused by the next one
   }
-  flush_counts(B, cjob, cslot, viol, loss);
+  flush_counts(G->g[cgrp], cjob, cslot, wave_id, viol, loss);
 }
 
 __global__ void k_hot_init(PgdBufs B, size_t n) {
@@ -706,11 +864,11 @@ __global__ void k_new_ids(const uint8_t *f, const uint32_t *pos, const uint32_t 
 
 struct RowPerm {
   const uint32_t *new_id;
-  const double4 *P0, *P1;
+  const double *P0, *P1;
   const double *m, *v;
   const float4 *xo;
   const uint32_t *hot, *e_list, *row_ptr;
-  double4 *nP0, *nP1;
+  double *nP0, *nP1;
   double *nm, *nv;
   float4 *nxo;
   uint32_t *nhot, *ne_list, *nlen, *wl;
@@ -720,8 +878,11 @@ __global__ void k_permute_rows(RowPerm R, size_t ne) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne;
        e += (size_t)gridDim.x * blockDim.x) {
     const uint32_t r = R.new_id[e];
-    R.nP0[r] = R.P0[e];
-    R.nP1[r] = R.P1[e];
+#pragma unroll
+    for (int k = 0; k < kPStride; ++k) {
+      R.nP0[(size_t)kPStride * r + k] = R.P0[(size_t)kPStride * e + k];
+      R.nP1[(size_t)kPStride * r + k] = R.P1[(size_t)kPStride * e + k];
+    }
     R.nxo[r] = R.xo[e];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -782,8 +943,8 @@ void renumber_hot(PgdBufs &b, uint32_t *&e_list, Arena &ar, hipStream_t s) {
   R.hot = b.hot;
   R.e_list = e_list;
   R.row_ptr = b.row_ptr;
-  R.nP0 = ar.get<double4>(ne);
-  R.nP1 = ar.get<double4>(ne);
+  R.nP0 = ar.get<double>(kPStride * ne);
+  R.nP1 = ar.get<double>(kPStride * ne);
   R.nm = ar.get<double>(3 * ne);
   R.nv = ar.get<double>(3 * ne);
   R.nxo = ar.get<float4>(ne);
@@ -811,8 +972,12 @@ void renumber_hot(PgdBufs &b, uint32_t *&e_list, Arena &ar, hipStream_t s) {
 
 // one wave per job: sums (and clears) the job's partial counts, sums its
 // loss slots in slot order, then decides
-__global__ void k_pgd_finalize(PgdBufs B) {
-  const int j = blockIdx.x, lane = threadIdx.x;
+__global__ void k_pgd_finalize(const PgdGroups *__restrict__ G) {
+  const int ngroups = G->ngroups, lane = threadIdx.x;
+  if ((int)blockIdx.x >= G->job_base[ngroups]) return;
+  const int grp = ngroups > 1 ? group_of(G->job_base, ngroups, (int64_t)blockIdx.x) : 0;
+  const PgdBufs &B = G->g[grp];
+  const int j = (int)blockIdx.x - G->job_base[grp];
   JobLoop &L = B.loop[j];
   if (L.done) return;
   const JobDev &J = B.jobs[j];
@@ -841,6 +1006,10 @@ __global__ void k_pgd_finalize(PgdBufs B) {
   }
   L.viol_last = viol;
   L.loss_last = loss;
+  if (L.t < J.trace_cap) {
+    J.trace_loss[L.t] = loss;
+    J.trace_viol[L.t] = viol;
+  }
   // Alg. 1's stopping test: no violated constraint, or the loss of Eq. 3 at
   // most eps_L when that is set
   const bool conv = J.loss_tol > 0.0 ? (loss <= J.loss_tol) : (viol == 0);
@@ -862,15 +1031,21 @@ __global__ void k_pgd_finalize(PgdBufs B) {
   L.bc2 = J.bc_tab[tb].y;
 }
 
-void launch_pgd_step(const PgdBufs &b, hipStream_t s) {
+void launch_pgd_step(const PgdGroups *g, const PgdBufs &b, hipStream_t s) {
   if (b.ne) {
     // the loss slots were sized for this many waves
     if (b.nwaves != pgd_step_waves(b.ne)) throw Error(-3, "PGD step grid differs from its loss slots");
-    k_pgd_step<<<b.nwaves / kPgdWaves, 64 * kPgdWaves, 0, s>>>(b);
+    k_pgd_step<<<b.nwaves / kPgdWaves, 64 * kPgdWaves, 0, s>>>(g);
   }
 }
-void launch_pgd_finalize(const PgdBufs &b, hipStream_t s) {
-  if (b.njobs) k_pgd_finalize<<<b.njobs, kWave, 0, s>>>(b);
+void launch_pgd_finalize(const PgdGroups *g, const PgdBufs &b, hipStream_t s) {
+  if (b.njobs) k_pgd_finalize<<<b.njobs, kWave, 0, s>>>(g);
+}
+void launch_pgd_step_shared(const PgdGroups *g, hipStream_t s) {
+  k_pgd_step<<<kPgdBlocks, 64 * kPgdWaves, 0, s>>>(g);
+}
+void launch_pgd_finalize_shared(const PgdGroups *g, hipStream_t s) {
+  k_pgd_finalize<<<kMaxGroupJobs, kWave, 0, s>>>(g);
 }
 
 }  // namespace pcc

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <memory>
 
 #include "host.hpp"
 
@@ -646,6 +647,16 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
     p_off[q] = act[q]->p_off;
     cbase[q] = act[q]->dev.cell_base;
     jd[q] = act[q]->dev;
+    // per-evaluation trace (at most one entry per evaluation the cap allows)
+    const pcc_outputs &o = act[q]->in->out;
+    jd[q].trace_cap = 0;
+    jd[q].trace_loss = nullptr;
+    jd[q].trace_viol = nullptr;
+    if (!labels_only && (o.loss_trace || o.viol_trace) && o.trace_cap > 0) {
+      jd[q].trace_cap = std::min<int64_t>(o.trace_cap, jd[q].max_iters + 1);
+      jd[q].trace_loss = dev<double>(ar, (size_t)jd[q].trace_cap);
+      jd[q].trace_viol = dev<unsigned long long>(ar, (size_t)jd[q].trace_cap);
+    }
   }
   p_off[J] = N;
   cbase[J] = (uint32_t)std::min<uint64_t>(cell_total, 0xffffffffull);
@@ -925,8 +936,8 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   gb.row_ptr = row_ptr;
   gb.col = col;
   gb.ninc = 2 * na;
-  gb.P0 = dev<double4>(ar, ne);
-  gb.P1 = dev<double4>(ar, ne);
+  gb.P0 = dev<double>(ar, kPStride * (size_t)ne);
+  gb.P1 = dev<double>(ar, kPStride * (size_t)ne);
   gb.m = dev<double>(ar, 3 * (size_t)ne);
   gb.v = dev<double>(ar, 3 * (size_t)ne);
   float4 *xo = dev<float4>(ar, ne);
@@ -946,7 +957,7 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
     // loss slots: min(tiles, waves) per job
     std::vector<int64_t> lo(J + 1, 0);
     for (int q = 0; q < J; ++q)
-      lo[q + 1] = lo[q] + std::min<int64_t>((e_off[q + 1] - e_off[q] + 63) / 64, gb.nwaves);
+      lo[q + 1] = lo[q] + std::min<int64_t>((e_off[q + 1] - e_off[q] + 63) / 64, pgd_max_waves());
     int64_t *d_lo = dev<int64_t>(ar, J + 1);
     PCC_HIP(hipMemcpyAsync(d_lo, lo.data(), (J + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
     gb.lp_off = d_lo;
@@ -955,18 +966,41 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   launch_pgd_init(e_list, ne, pos, rec, gb.P0, xo, gb.m, gb.v, s);
   launch_hot_init(gb, s);
   launch_loop_init(d_jobs, gb.loop, J, gb.n_active, s);
+  // the call's PGD state as the one group of the step's group table
+  PgdGroups *d_grp = dev<PgdGroups>(ar, 1);
+  std::unique_ptr<PgdGroups> h_grp(new PgdGroups());
+  auto put_group = [&]() {
+    h_grp->ngroups = 1;
+    h_grp->tile_base[0] = 0;
+    h_grp->tile_base[1] = gb.ntiles;
+    h_grp->job_base[0] = 0;
+    h_grp->job_base[1] = J;
+    h_grp->g[0] = gb;
+    st.put(d_grp, h_grp.get(), 1);
+  };
+  put_group();
   {
     // the first step evaluates every row; later ones only the hot rows
     int at = kt.start(3, s);
-    launch_pgd_step(gb, s);
+    launch_pgd_step(d_grp, gb, s);
     kt.stop(at, s);
     at = kt.start(4, s);
-    launch_pgd_finalize(gb, s);
+    launch_pgd_finalize(d_grp, gb, s);
     kt.stop(at, s);
     renumber_hot(gb, e_list, ar, s);
+    put_group();
   }
   const int K = std::max(1, std::min(64, C.graph_iters));
-  {
+  bool shared = false;
+  if (C.engine && J <= kMaxGroupJobs) {
+    // the served form's shared loop: this call's jobs step together with
+    // every other call's resident jobs until all of them are done
+    int32_t h_act = 0;
+    st.fetch(&h_act, gb.n_active, 1);
+    if (h_act > 0) engine_run(C.engine, gb, h_act);
+    shared = true;
+  }
+  if (!shared) {
     // K steps per captured graph.  With kernel timing on, each replay is
     // bracketed by two events outside the graph and its time is split evenly
     // over its K steps (a step launch and its finalize launch together):
@@ -976,8 +1010,8 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
     PCC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     try {
       for (int k = 0; k < K; ++k) {
-        launch_pgd_step(gb, s);
-        launch_pgd_finalize(gb, s);
+        launch_pgd_step(d_grp, gb, s);
+        launch_pgd_finalize(d_grp, gb, s);
       }
     } catch (...) {
       // leave the stream out of capture mode before reporting the error
@@ -1018,6 +1052,16 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   }
   std::vector<JobLoop> lp(J);
   st.fetch(lp.data(), gb.loop, J);
+  for (int q = 0; q < J; ++q) {
+    if (jd[q].trace_cap <= 0) continue;
+    const pcc_outputs &o = act[q]->in->out;
+    const size_t cnt = (size_t)std::min<int64_t>(jd[q].trace_cap, lp[q].t + 1);
+    if (o.loss_trace) st.fetch(o.loss_trace, jd[q].trace_loss, cnt);
+    if (o.viol_trace) {
+      static_assert(sizeof(int64_t) == sizeof(unsigned long long), "trace entry size");
+      st.fetch(reinterpret_cast<unsigned long long *>(o.viol_trace), jd[q].trace_viol, cnt);
+    }
+  }
   for (int q = 0; q < J; ++q) {
     pcc_stats &S = act[q]->st;
     S.iters = lp[q].t;

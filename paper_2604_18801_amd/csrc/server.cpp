@@ -1,9 +1,15 @@
 // Served form of the correction pass: a job queue in front of the batched
-// pipeline, drained by worker threads that each own a context (workspace and
-// HIP stream) on the same device.  A worker takes the queued jobs in arrival
-// order and runs as many as fit together (continuous batching); several
-// workers keep the device busy while one of them waits on the host part of
-// a batch (readbacks, Huffman tables, ZSTD).
+// pipeline, drained by slot threads that each own a context (workspace and
+// HIP stream) on the same device, and one shared PGD loop (engine.cpp).  A
+// slot takes the queued jobs in arrival order, as many as fit its share of
+// the device memory, and prepares them on its own stream (every stage up to
+// the first PGD step); their PGD state then joins the shared loop, which
+// steps every resident call's jobs in the same launches and lets each call
+// leave as soon as its jobs have converged, when its slot encodes them and
+// takes the next jobs.  Jobs are thus admitted and retired at the
+// granularity of a few PGD steps (iteration-level continuous batching),
+// and the setup and encoding of some calls overlap the iterations of
+// others on the device.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -42,6 +48,7 @@ constexpr int64_t kLearnMin = 100000;
 
 struct pcc_server {
   int device = 0;
+  pcc::PgdEngine *engine = nullptr;  // the shared PGD loop
   double budget = 0.0;
   int max_inflight = 256;
   std::vector<pcc_context *> ctx;
@@ -191,7 +198,7 @@ pcc_status pcc_server_create(pcc_context *ctx, const pcc_server_config *cfg, pcc
     auto *S = new pcc_server;
     S->device = ctx->c.device;
     S->max_inflight = c.max_inflight ? c.max_inflight : 256;
-    const int nw = c.n_streams ? c.n_streams : 2;
+    const int nw = c.n_streams ? c.n_streams : 4;
     if (hipSetDevice(S->device) != hipSuccess) {
       delete S;
       return fail(PCC_E_DEVICE, "hipSetDevice failed");
@@ -202,14 +209,22 @@ pcc_status pcc_server_create(pcc_context *ctx, const pcc_server_config *cfg, pcc
       return fail(PCC_E_DEVICE, "hipMemGetInfo failed");
     }
     S->budget = c.hbm_budget ? (double)c.hbm_budget : 0.8 * (double)free_b;
+    try {
+      S->engine = pcc::engine_create(S->device, ctx->c.graph_iters);
+    } catch (const pcc::Error &e) {
+      delete S;
+      return fail(e.status, e.what());
+    }
     for (int w = 0; w < nw; ++w) {
       pcc_context *h = nullptr;
       const pcc_status st = pcc_context_create(S->device, &h);
       if (st != PCC_OK) {
         for (auto *x : S->ctx) pcc_context_destroy(x);
+        pcc::engine_destroy(S->engine);
         delete S;
         return st;
       }
+      h->c.engine = S->engine;
       h->c.graph_iters = ctx->c.graph_iters;
       h->c.cell_pct = ctx->c.cell_pct;
       h->c.dense_cell = ctx->c.dense_cell;
@@ -304,6 +319,7 @@ pcc_status pcc_server_destroy(pcc_server *srv) {
   }
   srv->cv_work.notify_all();
   for (auto &t : srv->workers) t.join();
+  pcc::engine_destroy(srv->engine);
   for (auto *c : srv->ctx) pcc_context_destroy(c);
   delete srv;
   return PCC_OK;

@@ -13,7 +13,13 @@ size:
   that joins two halos, and its potentially broken pairs join two safe
   components;
 * every active pair of the call lies in the distance window of its class;
-* the decoded stream keeps every label and the error box.
+* the decoded stream keeps every label and the error box;
+* complete FoF of the originals and of the decoded positions computed
+  without the library (a scipy k-d tree proposes pairs within b(1 + 1e-9),
+  the exact float64 link predicate keeps the links, scipy's connected
+  components join them): both equal the returned labels;
+* the safe components joined by the halo-forest constraints are exactly the
+  FoF components (the forest spans every halo).
 """
 import numpy as np
 import pytest
@@ -135,6 +141,60 @@ def test_sampled_vulnerable_sets(run):
         # every created pair across two halos is kept
         across = vul[(cls == 3) & (lab[vul] != lab[k])]
         assert set(across.tolist()) <= set(partner[ptype == 3].tolist())
+
+
+def _independent_fof(pos, b, box):
+    """Canonical FoF labels (smallest member index) with no library code."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    from scipy.spatial import cKDTree
+    n = pos.shape[1]
+    L = box[0]
+    pts = np.mod(pos.T.astype(np.float64), L)
+    pts[pts >= L] = 0.0  # a tiny negative coordinate can round up to L
+    tree = cKDTree(pts, boxsize=L, balanced_tree=False, compact_nodes=False)
+    p = tree.query_pairs(b * (1 + 1e-9), output_type="ndarray")
+    del tree, pts
+    x = pos.astype(np.float64)
+    d2 = None
+    for a in range(3):
+        d = _axis(x[a][p[:, 0]] - x[a][p[:, 1]], box[a])
+        d2 = d * d if d2 is None else d2 + d * d
+    p = p[d2 <= b * b]
+    del d2
+    g = coo_matrix((np.ones(len(p), np.int8), (p[:, 0], p[:, 1])), shape=(n, n)).tocsr()
+    del p
+    _, comp = connected_components(g, directed=False)
+    minid = np.full(comp.max() + 1, n, dtype=np.int64)
+    np.minimum.at(minid, comp, np.arange(n))
+    return minid[comp].astype(np.int32)
+
+
+def test_complete_fof_without_the_library(run):
+    import paper_2604_18801_amd as pcc
+    w, ctx, stream, lab, st, pairs, safe = run
+    print("case independent FoF of the originals", flush=True)
+    np.testing.assert_array_equal(_independent_fof(w.orig, w.b, w.box), lab)
+    print("case independent FoF of the decoded positions", flush=True)
+    x = pcc.decode(stream, w.recon)
+    np.testing.assert_array_equal(_independent_fof(x, w.b, w.box), lab)
+
+
+def test_forest_spans_every_halo(run):
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    w, ctx, stream, lab, st, (ai, aj, at), safe = run
+    n = w.n
+    pb = at == 2
+    # nodes: particles; edges: every particle to its safe component's label
+    # and every forest constraint
+    u = np.concatenate([np.arange(n), ai[pb].astype(np.int64)])
+    v = np.concatenate([safe.astype(np.int64), aj[pb].astype(np.int64)])
+    g = coo_matrix((np.ones(len(u), np.int8), (u, v)), shape=(n, n)).tocsr()
+    _, comp = connected_components(g, directed=False)
+    minid = np.full(comp.max() + 1, n, dtype=np.int64)
+    np.minimum.at(minid, comp, np.arange(n))
+    np.testing.assert_array_equal(minid[comp].astype(np.int32), lab)
 
 
 def test_decoded_stream_keeps_labels_and_box(run):

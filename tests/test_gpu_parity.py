@@ -356,3 +356,25 @@ def test_iteration_cap_above_the_limit_is_rejected(ctx):
     a = ctx.correct(_dev(w.orig), _dev(w.recon), w.b, w.xi, max_iters=1 << 31, debug_xyz=True)
     b = ctx.correct(_dev(w.orig), _dev(w.recon), w.b, w.xi, debug_xyz=True)
     assert a[0] == b[0] and a[2]["iters"] == b[2]["iters"]
+
+
+@pytest.mark.parametrize("mode,cap", [("vp", 0), ("sc", 0), ("hf", 0), ("hf", 9)])
+def test_loss_trace_matches_oracle(ctx, mode, cap):
+    # the per-evaluation trace of Alg. 1's loop (loss of Eq. 3 and violated
+    # constraints at every iterate): the loss-against-iteration curve; the
+    # plain workload converges in about 100 steps in every mode
+    w = synth.plain_blobs() if cap == 0 else synth.cosmology(24, seed=12, xi=0.05)
+    kw = {"max_iters": cap} if cap else {}
+    ref = oracle.correct(w.orig, w.recon, w.b, w.xi, mode=mode, box=w.box, **kw)
+    print("case trace", mode, cap, flush=True)
+    _, _, st = ctx.correct(_dev(w.orig), _dev(w.recon), w.b, w.xi, mode=mode, box=w.box,
+                           trace=100000, **kw)
+    assert len(st["loss_trace"]) == ref.iters + 1 == len(ref.loss_hist)
+    np.testing.assert_array_equal(st["viol_trace"], ref.viol_hist)
+    scale = np.maximum(np.abs(ref.loss_hist), 1e-300)
+    assert np.all(np.abs(st["loss_trace"] - ref.loss_hist) <= LOSS_RTOL * scale)
+    assert st["loss_trace"][0] == st["loss0"] and st["loss_trace"][-1] == st["loss_final"]
+    # a trace shorter than the run keeps its first entries
+    _, _, st5 = ctx.correct(_dev(w.orig), _dev(w.recon), w.b, w.xi, mode=mode, box=w.box,
+                            trace=5, **kw)
+    np.testing.assert_array_equal(st5["viol_trace"], ref.viol_hist[:5])

@@ -90,3 +90,38 @@ def test_cancel_poll_and_failures(ctx):
     else:
         s2, _, _ = ctx.correct(_dev(small.orig), _dev(small.recon), small.b, small.xi, mode="vp")
         assert r_cancel[1] == s2
+
+
+def test_arrivals_join_while_another_job_iterates(ctx):
+    # iteration-level continuous batching: small jobs submitted while a long
+    # job is iterating start, iterate beside it in the shared loop and
+    # finish before it; every result equals the job run alone (plain call)
+    # and the oracle's
+    import oracle
+    import paper_2604_18801_amd as pcc
+    big = synth.cosmology(40, seed=90, xi=0.05)
+    smalls = [synth.plain_blobs(2500 + 700 * k, seed=91 + k) for k in range(4)]
+    modes = ["hf", "sc", "vp", "hf"]
+    big_opts = {"max_iters": 3000}
+    srv = pcc.Server(ctx, n_streams=2, max_inflight=1)
+    try:
+        print("case served: long VP job, then four small jobs", flush=True)
+        t_big = srv.submit(**_job(big, "vp", opts=big_opts))
+        ts = [srv.submit(**_job(w, m)) for w, m in zip(smalls, modes)]
+        rs = [srv.wait(t) for t in ts]
+        r_big = srv.wait(t_big)
+    finally:
+        srv.close()
+    fin_big = r_big[3]["t_finish_ms"]
+    for r in rs:
+        assert r[3]["t_start_ms"] < fin_big and r[3]["t_finish_ms"] < fin_big, (r[3], r_big[3])
+    s1, l1, st1 = ctx.correct(_dev(big.orig), _dev(big.recon), big.b, big.xi, mode="vp",
+                              box=big.box, **big_opts)
+    assert r_big[0] == st1["status"] and r_big[1] == s1 and r_big[3]["iters"] == st1["iters"]
+    np.testing.assert_array_equal(r_big[2].cpu().numpy(), l1.cpu().numpy())
+    for (status, stream, lab, st), w, m in zip(rs, smalls, modes):
+        ref = oracle.correct(w.orig, w.recon, w.b, w.xi, mode=m, box=w.box)
+        assert status == ref.status and st["iters"] == ref.iters, (w.name, m)
+        np.testing.assert_array_equal(lab.cpu().numpy(), ref.labels)
+        s2, _, _ = ctx.correct(_dev(w.orig), _dev(w.recon), w.b, w.xi, mode=m, box=w.box)
+        assert stream == s2
