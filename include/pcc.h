@@ -193,7 +193,8 @@ enum {
   PCC_CTX_GRAPH_ITERS = 2,
   PCC_CTX_EXACT_PAIRS = 3,
   PCC_CTX_CELL_PCT = 4,
-  PCC_CTX_DENSE_CELL = 5
+  PCC_CTX_DENSE_CELL = 5,
+  PCC_CTX_WORKSPACE_HIGH_WATER = 6
 };
 /*
  * Scheduling knobs (no result depends on them; pcc_autotune sets them):
@@ -206,6 +207,8 @@ enum {
  *                          searched by whole waves (64 home particles per
  *                          wave, partners staged through LDS), the others by
  *                          one thread per particle; 1 .. 4096 (default 32).
+ *   PCC_CTX_WORKSPACE_HIGH_WATER  (get only) device workspace bytes the last
+ *                          call on the context used at most.
  */
 pcc_status pcc_context_set(pcc_context *ctx, int32_t key, int64_t value);
 /* Reads a context option (any key above) into *value. */
@@ -308,6 +311,21 @@ pcc_status pcc_decode_device(pcc_context *ctx, const uint8_t *stream, size_t len
                              float *out_z, void *hip_stream);
 
 /*
+ * Device workspace a pcc_correct of these inputs would take at most, for
+ * admission by footprint (the served form uses it): the call's stages run
+ * up to the first pair pass (cells, pair classes and their per-particle
+ * counts, Sec. 3.1-3.3) and the rest is bounded from those counts (the
+ * slots for every vulnerable pair the mode may keep, the spanning-forest
+ * candidates, the CSR, the PGD state and the encoder); the bound is at
+ * least the workspace high water of the full call.  Inputs as for
+ * pcc_correct (device or host); the work is queued on hip_stream and the
+ * call returns when it is done.  Status as for pcc_correct's input checks.
+ */
+pcc_status pcc_workspace_query(pcc_context *ctx, const pcc_particles *orig,
+                               const pcc_particles *recon, const pcc_params *params,
+                               size_t *bytes, void *hip_stream);
+
+/*
  * Friends-of-friends labels (Sec. 2.4) of a point set at linking length b:
  * labels[k] is the smallest index in k's cluster.  box as in pcc_params.
  * labels has the memspace of pts.
@@ -349,6 +367,11 @@ int64_t pcc_fof_labels_noalloc_max_n(void);
  *   PCC_DBG_ACTIVE_THR      uint8  [n_active]  linking-length index of each
  *                                              active pair (0 outside
  *                                              pcc_correct_multi)
+ *   PCC_DBG_CELL_START      uint32 [cells + 1] first sorted particle of each
+ *                                              non-empty cell of the call (all
+ *                                              jobs), then the particle count
+ *   PCC_DBG_NEIGHBORS       int32  [13 cells]  the 13 forward neighbour cells
+ *                                              of each cell, -1 where none
  * *count receives the element count; nothing is copied if cap < count.
  */
 enum {
@@ -357,7 +380,9 @@ enum {
   PCC_DBG_ACTIVE_TYPE = 3,
   PCC_DBG_SAFE_LABELS = 4,
   PCC_DBG_EDITABLE = 5,
-  PCC_DBG_ACTIVE_THR = 6
+  PCC_DBG_ACTIVE_THR = 6,
+  PCC_DBG_CELL_START = 7,
+  PCC_DBG_NEIGHBORS = 8
 };
 pcc_status pcc_debug_fetch(pcc_context *ctx, int32_t job, int32_t what, void *host_dst,
                            int64_t cap, int64_t *count);

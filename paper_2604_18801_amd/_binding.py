@@ -133,6 +133,8 @@ def lib() -> C.CDLL:
                                      C.POINTER(C.c_double), C.c_void_p, C.c_void_p]
         L.pcc_fof_labels_noalloc.argtypes = [C.c_void_p, C.POINTER(Particles), C.c_double,
                                              C.POINTER(C.c_double), C.c_void_p, C.c_void_p]
+        L.pcc_workspace_query.argtypes = [C.c_void_p, C.POINTER(Particles), C.POINTER(Particles),
+                                          C.POINTER(Params), C.POINTER(C.c_size_t), C.c_void_p]
         L.pcc_fof_labels_noalloc_max_n.argtypes = []
         L.pcc_fof_labels_noalloc_max_n.restype = C.c_int64
         L.pcc_context_set.argtypes = [C.c_void_p, C.c_int32, C.c_int64]
@@ -155,7 +157,7 @@ def lib() -> C.CDLL:
         L.pcc_server_destroy.argtypes = [C.c_void_p]
         for name in ("pcc_context_create", "pcc_context_destroy", "pcc_correct",
                      "pcc_correct_multi", "pcc_correct_batch", "pcc_decode", "pcc_fof_labels",
-                     "pcc_fof_labels_noalloc", "pcc_debug_fetch",
+                     "pcc_fof_labels_noalloc", "pcc_workspace_query", "pcc_debug_fetch",
                      "pcc_context_set", "pcc_context_get", "pcc_autotune", "pcc_decode_device",
                      "pcc_debug_set", "pcc_debug_get", "pcc_server_create", "pcc_server_submit",
                      "pcc_server_poll", "pcc_server_wait", "pcc_server_cancel",
@@ -304,7 +306,7 @@ class Context:
             pass
 
     _OPTIONS = {"kernel_timing": 1, "graph_iters": 2, "exact_pairs": 3, "cell_pct": 4,
-                "dense_cell": 5}
+                "dense_cell": 5, "workspace_high_water": 6}
 
     def set_option(self, key: str, value: int):
         _check(lib().pcc_context_set(self._h, self._OPTIONS[key], int(value)))
@@ -376,6 +378,21 @@ class Context:
             stats["debug_xyz"] = dbg[:, :n]
         _trace_results(stats, tl, tv)
         return bytes(sbuf[: slen.value]), res_lab, stats
+
+    def workspace_query(self, orig, recon, b: float, xi: float, mode="hf", box=None,
+                        **opts) -> int:
+        """Bound of the device workspace bytes correct() would take."""
+        po, ko = _view(orig)
+        pr, kr = _view(recon)
+        params = make_params(b, xi, mode=mode, box=box, **opts)
+        out = C.c_size_t(0)
+        _check(lib().pcc_workspace_query(self._h, C.byref(po), C.byref(pr), C.byref(params),
+                                         C.byref(out), _stream_handle(po.memspace == MEM_DEVICE)))
+        return int(out.value)
+
+    def workspace_high_water(self) -> int:
+        """Device workspace bytes the last call on this context used at most."""
+        return self.get_option("workspace_high_water")
 
     def correct_multi(self, orig, recon, b_list: Sequence[float], xi: float, mode="hf",
                       box=None, labels=True, debug_xyz=False, **opts):
@@ -476,9 +493,9 @@ class Context:
 
     def debug_fetch(self, job: int, what: str):
         code = {"active_i": 1, "active_j": 2, "active_type": 3, "safe_labels": 4,
-                "editable": 5, "active_thr": 6}[what]
+                "editable": 5, "active_thr": 6, "cell_start": 7, "neighbors": 8}[what]
         dtype = {1: np.uint32, 2: np.uint32, 3: np.uint8, 4: np.int32, 5: np.uint32,
-                 6: np.uint8}[code]
+                 6: np.uint8, 7: np.uint32, 8: np.int32}[code]
         cnt = C.c_int64(0)
         _check(lib().pcc_debug_fetch(self._h, int(job), code, None, 0, C.byref(cnt)))
         buf = np.zeros(max(cnt.value, 1), dtype=dtype)

@@ -102,6 +102,7 @@ pcc_status pcc_context_get(pcc_context *ctx, int32_t key, int64_t *value) {
     case PCC_CTX_EXACT_PAIRS: *value = ctx->c.force_exact_pairs ? 1 : 0; return PCC_OK;
     case PCC_CTX_CELL_PCT: *value = ctx->c.cell_pct; return PCC_OK;
     case PCC_CTX_DENSE_CELL: *value = ctx->c.dense_cell; return PCC_OK;
+    case PCC_CTX_WORKSPACE_HIGH_WATER: *value = (int64_t)ctx->c.arena.high_water(); return PCC_OK;
     default: return fail(PCC_E_INVALID_ARG, "unknown context option");
   }
 }
@@ -222,6 +223,31 @@ pcc_status pcc_correct(pcc_context *ctx, const pcc_particles *orig, const pcc_pa
     if (stats) *stats = r.stats;
     if (r.status < 0 && g_err.empty()) g_err = pcc_status_string(r.status);
     return r.status;
+  });
+}
+
+pcc_status pcc_workspace_query(pcc_context *ctx, const pcc_particles *orig,
+                               const pcc_particles *recon, const pcc_params *params,
+                               size_t *bytes, void *hip_stream) {
+  if (!ctx || !orig || !recon || !params || !bytes)
+    return fail(PCC_E_INVALID_ARG, "NULL argument");
+  *bytes = 0;
+  return guarded([&]() -> pcc_status {
+    pcc_job job;
+    std::memset(&job, 0, sizeof job);
+    job.orig = *orig;
+    job.recon = *recon;
+    job.params = *params;
+    pcc_job_result r;
+    std::memset(&r, 0, sizeof r);
+    size_t fp = 0;
+    pcc::run_batch(ctx->c, &job, 1, &r, pick(ctx, hip_stream), false, false, nullptr, &fp);
+    if (r.status < 0) {
+      if (g_err.empty()) g_err = pcc_status_string(r.status);
+      return r.status;
+    }
+    *bytes = fp;
+    return PCC_OK;
   });
 }
 
@@ -403,6 +429,20 @@ extern "C" pcc_status pcc_debug_fetch(pcc_context *ctx, int32_t job, int32_t wha
     PCC_HIP(hipMemcpyAsync(d_poff, L.p_off.data(), L.p_off.size() * sizeof(int64_t),
                            hipMemcpyHostToDevice, s));
     const int64_t n_job = L.p_off[q + 1] - L.p_off[q];
+    if (what == PCC_DBG_CELL_START || what == PCC_DBG_NEIGHBORS) {
+      uint32_t u = 0;
+      if (L.n) {
+        PCC_HIP(hipMemcpyAsync(&u, L.n_cells, sizeof u, hipMemcpyDeviceToHost, s));
+        PCC_HIP(hipStreamSynchronize(s));
+      }
+      const int64_t m = what == PCC_DBG_CELL_START ? (int64_t)u + 1 : 13 * (int64_t)u;
+      *count = L.n ? m : 0;
+      if (!host_dst || cap < *count || !*count) return PCC_OK;
+      const void *src = what == PCC_DBG_CELL_START ? (const void *)L.cell_start : (const void *)L.nbr;
+      PCC_HIP(hipMemcpyAsync(host_dst, src, (size_t)m * 4, hipMemcpyDeviceToHost, s));
+      PCC_HIP(hipStreamSynchronize(s));
+      return PCC_OK;
+    }
     if (what == PCC_DBG_SAFE_LABELS) {
       *count = n_job;
       if (cap < n_job || !host_dst) return PCC_OK;

@@ -24,6 +24,11 @@ struct LastCall {
   const uint32_t *safe_root = nullptr;
   const float4 *pos = nullptr;
   const uint32_t *e_list = nullptr;
+  // cell list of the call (all jobs): cell starts [n_cells + 1] and the 13
+  // forward neighbour cells of each cell (-1: none)
+  const uint32_t *cell_start = nullptr;
+  const int32_t *nbr = nullptr;
+  const uint32_t *n_cells = nullptr;
 };
 
 // Adam bias corrections (1 - beta1^t, 1 - beta2^t) for t = 0 .. len - 1,
@@ -104,9 +109,11 @@ void autotune(Context &C, const pcc_job *jobs, int njobs, hipStream_t s, int32_t
 // scratch: labels only, every device buffer of the call from this fixed
 // arena (no device or pinned allocation, no kernel timing, the context's
 // arena and retained debug data untouched)
+// footprint: run only through pair pass 1 and the slot counts, and store a
+// bound of the workspace bytes the whole call takes
 pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs, pcc_job_result *res,
                      hipStream_t s, bool labels_only, bool multi = false,
-                     Arena *scratch = nullptr);
+                     Arena *scratch = nullptr, size_t *footprint = nullptr);
 // stage events of a context (created once, with the context)
 void create_events(Context &C);
 

@@ -134,7 +134,7 @@ class Arena {
   // release() then forgets the buffer without freeing it.
   void attach(void *base, size_t bytes);
   size_t used() const { return used_; }
-  size_t high_water() const { return high_; }
+  size_t high_water() const { return high_; }  // most bytes in use since reset()
 
  private:
   struct Chunk {

@@ -435,20 +435,30 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES)
   int cslot = 0;   // this wave's loss slot of that job
   const int ngroups = G->ngroups;
   const int64_t ntiles = G->tile_base[ngroups];
+  // the buffers of the group being walked, copied once into (scalar)
+  // registers: read through the table for every tile they would cost a
+  // chain of scalar loads per tile
+  PgdBufs B = G->g[0];
+  int64_t gbase = 0;
   for (int64_t tile = wave_id; tile < ntiles; tile += nwaves) {
     const int grp =
         ngroups > 1 ? __builtin_amdgcn_readfirstlane(group_of(G->tile_base, ngroups, tile)) : 0;
-    const PgdBufs &B = G->g[grp];
-    const int64_t tl = tile - G->tile_base[grp];  // tile within its group
+    if (grp != cgrp) {
+      flush_counts(B, cjob, cslot, wave_id, viol, loss);
+      B = G->g[grp];
+      gbase = G->tile_base[grp];
+      cgrp = grp;
+      cjob = -1;
+    }
+    const int64_t tl = tile - gbase;  // tile within its group
     const int job = __builtin_amdgcn_readfirstlane(job_of(B.tile_off, B.njobs, tl));
     if (B.loop[job].done) continue;
     const int64_t eoff = B.e_off[job];
     const int64_t w0 = (tl - B.tile_off[job]) * 64;  // first worklist entry of the tile
     const int64_t left = (int64_t)B.wl_step[job] - w0;
     if (left <= 0) continue;
-    if (job != cjob || grp != cgrp) {
-      flush_counts(G->g[cgrp], cjob, cslot, wave_id, viol, loss);
-      cgrp = grp;
+    if (job != cjob) {
+      flush_counts(B, cjob, cslot, wave_id, viol, loss);
       cjob = job;
       cslot = (int)((tl - B.tile_off[job]) % nwaves);
     }
@@ -816,7 +826,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES)
     }
     wave_sync();  // LDS of this tile is reused by the next one
   }
-  flush_counts(G->g[cgrp], cjob, cslot, wave_id, viol, loss);
+  flush_counts(B, cjob, cslot, wave_id, viol, loss);
 }
 
 __global__ void k_hot_init(PgdBufs B, size_t n) {

@@ -374,7 +374,8 @@ const double2 *bc_table(Context &C, double beta1, double beta2, int64_t len) {
 
 namespace {
 pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_result *res,
-                          hipStream_t s, bool labels_only, bool multi, Arena *scratch);
+                          hipStream_t s, bool labels_only, bool multi, Arena *scratch,
+                          size_t *footprint);
 }  // namespace
 
 void create_events(Context &C) {
@@ -383,10 +384,11 @@ void create_events(Context &C) {
 }
 
 pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_result *res,
-                     hipStream_t s, bool labels_only, bool multi, Arena *scratch) {
+                     hipStream_t s, bool labels_only, bool multi, Arena *scratch,
+                     size_t *footprint) {
   if (scratch && (!labels_only || multi)) throw Error(-3, "a fixed scratch serves labels only");
   try {
-    return run_batch_impl(C, jobs, njobs_in, res, s, labels_only, multi, scratch);
+    return run_batch_impl(C, jobs, njobs_in, res, s, labels_only, multi, scratch, footprint);
   } catch (...) {
     // nothing the failed call queued may still be running when its error is
     // reported: the caller may free its buffers and the arena may be released
@@ -399,7 +401,9 @@ pcc_status run_batch(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_resu
 
 namespace {
 pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job_result *res,
-                          hipStream_t s, bool labels_only, bool multi, Arena *scratch) {
+                          hipStream_t s, bool labels_only, bool multi, Arena *scratch,
+                          size_t *footprint) {
+  if (footprint) *footprint = 0;
   const auto t_wall0 = std::chrono::steady_clock::now();
   PCC_HIP(hipSetDevice(C.device));
   PCC_HIP(hipStreamSynchronize(s));
@@ -577,7 +581,7 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
       std::vector<pcc_job_result> sub(rest.size());
       pcc_status r = rest.empty() ? PCC_OK
                                   : run_batch(C, rest.data(), (int)rest.size(), sub.data(), s,
-                                              labels_only, false, scratch);
+                                              labels_only, false, scratch, footprint);
       for (size_t q = 0; q < map.size(); ++q) res[map[q]] = sub[q];
       (void)r;
       pcc_status first = PCC_OK;
@@ -783,6 +787,27 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   scan_u32_u64(cap_f, off_f, n, tot + 1, ar, s);
   uint64_t htot[3];
   st.fetch(htot, tot, 2);
+  if (footprint) {
+    // Bound of the bytes the rest of the call takes from the workspace, from
+    // the slot capacities A (active pairs; the kept pairs are fewer) and F
+    // (forest candidates) and n: pair lists and their compaction 18 A + 16 F
+    // + 17 n; the spanning forest 12 n + 30 F (+ scan parts); the sort of
+    // the active list and the CSR, with its radix-sort buffers, 91.25 per
+    // active pair (at most A + n) and 33.25 n; the PGD state and its
+    // renumbered copy 258 n + 8 per active pair; encoding 131.125 n and two
+    // 256 KiB tables per job; 1 MiB for small tables and 256-byte rounding.
+    const double A = (double)htot[0], F = (double)htot[1], nn = (double)n;
+    const double rest = 18.0 * A + 16.0 * F + 17.0 * nn + 12.0 * nn + 30.004 * F +
+                        99.25 * (A + nn) + 33.25 * nn + 258.0 * nn + 131.125 * nn +
+                        526336.0 * J + (double)(1 << 20);
+    *footprint = ar.used() + (size_t)rest;
+    PCC_HIP(hipStreamSynchronize(s));
+    for (auto *h : act) res[h->index].stats = h->st;
+    pcc_status first = PCC_OK;
+    for (int k = 0; k < njobs_in; ++k)
+      if (res[k].status < 0 && first == PCC_OK) first = res[k].status;
+    return first;
+  }
   size_t free_b = 0, total_b = 0;
   PCC_HIP(hipMemGetInfo(&free_b, &total_b));
   const double slot_bytes = 9.0 * (double)htot[0] * (all_vp ? 1.0 : 2.0) + 16.0 * (double)htot[1];
@@ -1244,6 +1269,9 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   C.last.safe_root = pb.safe_par;
   C.last.pos = pos;
   C.last.e_list = e_list;
+  C.last.cell_start = cell_start;
+  C.last.nbr = nbr;
+  C.last.n_cells = n_cells;
 
   pcc_status first = PCC_OK;
   for (auto *h : act) {

@@ -37,6 +37,7 @@ void Arena::attach(void *base, size_t bytes) {
 }
 
 void Arena::reset() {
+  high_ = 0;
   if (fixed_) {
     chunks_[0].off = 0;
     used_ = 0;

@@ -36,6 +36,7 @@ struct Rec {
   int state = kQueued;
   bool solo = false;  // run alone (after its batch ran out of memory)
   bool retried = false;  // ran out of memory alone once already
+  size_t footprint = 0;  // workspace bound from pcc_workspace_query (0: not known)
   std::string err;
 };
 
@@ -43,6 +44,9 @@ struct Rec {
 // kLearnMin particles has been measured
 constexpr double kBytesPerParticle0 = 2048.0;
 constexpr int64_t kLearnMin = 100000;
+// jobs at least this large are admitted by their counted footprint
+// (pcc_workspace_query on the slot's stream), the others by the estimate
+constexpr int64_t kQueryMin = 1000000;
 
 }  // namespace
 
@@ -61,6 +65,7 @@ struct pcc_server {
   size_t outstanding = 0;
   bool stop = false;
   double bpp = kBytesPerParticle0;
+  double reserved = 0.0;  // workspace bytes the running calls hold
   Clock::time_point t0 = Clock::now();
 
   double now_ms() const {
@@ -75,22 +80,32 @@ pcc_status fail(pcc_status s, const std::string &m) {
   return s;
 }
 
-// Admission: jobs in arrival order while the batch stays within the worker's
-// share of the budget (the first job is always taken).
-void take_batch(pcc_server *S, std::vector<uint64_t> &batch) {
-  const double share = S->budget / (double)S->ctx.size();
-  double est = 0.0;
+bool needs_query(const Rec &r) { return r.footprint == 0 && r.job.orig.n >= kQueryMin; }
+
+double footprint_of(const pcc_server *S, const Rec &r) {
+  return r.footprint ? (double)r.footprint : (double)std::max<int64_t>(r.job.orig.n, 1) * S->bpp;
+}
+
+// Admission: jobs in arrival order while the device memory not held by the
+// running calls covers their footprints (counted for large jobs, estimated
+// for the others).  A job that does not fit waits for memory to free up,
+// unless nothing is running (then it is taken and may run out of memory).
+// A job whose footprint is still to be counted is taken alone.
+void take_batch(pcc_server *S, std::vector<uint64_t> &batch, double &est) {
+  est = 0.0;
   while (!S->queue.empty() && (int)batch.size() < S->max_inflight) {
     const uint64_t tk = S->queue.front();
     Rec &r = S->recs[tk];
-    const double e = (double)std::max<int64_t>(r.job.orig.n, 1) * S->bpp;
-    if (!batch.empty() && (r.solo || est + e > share)) break;
+    const bool count = needs_query(r);
+    const double e = footprint_of(S, r);
+    if (!batch.empty() && (r.solo || count || S->reserved + est + e > S->budget)) break;
+    if (batch.empty() && !count && S->reserved > 0.0 && S->reserved + e > S->budget) break;
     S->queue.pop_front();
     r.state = kRunning;
     r.res.t_start_ms = S->now_ms();
     batch.push_back(tk);
     est += e;
-    if (r.solo) break;
+    if (r.solo || count) break;
   }
 }
 
@@ -102,17 +117,48 @@ void worker_main(pcc_server *S, int w) {
   std::vector<pcc_job_result> res;
   for (;;) {
     batch.clear();
+    double hold = 0.0;  // workspace bytes this call reserves
+    bool count = false;
     {
       std::unique_lock<std::mutex> lk(S->mu);
       S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty(); });
       if (S->queue.empty()) return;  // stopping, nothing left
-      take_batch(S, batch);
+      take_batch(S, batch, hold);
+      if (batch.empty()) {
+        // the next job waits for memory held by running calls
+        S->cv_work.wait(lk);
+        continue;
+      }
+      count = batch.size() == 1 && needs_query(S->recs[batch[0]]);
+      if (!count) S->reserved += hold;
       jobs.clear();
       for (uint64_t tk : batch) jobs.push_back(S->recs[tk].job);
     }
     res.assign(batch.size(), pcc_job_result{});
     pcc_status err = PCC_OK;
     std::string msg;
+    if (count) {
+      // count the large job's footprint on this slot's stream, then admit
+      // it by that (or put it back until memory frees up)
+      size_t fp = 0;
+      try {
+        pcc_job_result q{};
+        pcc::run_batch(C, jobs.data(), 1, &q, C.own, false, false, nullptr, &fp);
+      } catch (const std::exception &) {
+        fp = 0;  // the correction itself reports the failure
+      }
+      std::unique_lock<std::mutex> lk(S->mu);
+      Rec &r = S->recs[batch[0]];
+      r.footprint = fp ? fp : (size_t)footprint_of(S, r) + 1;
+      hold = (double)r.footprint;
+      if (S->reserved > 0.0 && S->reserved + hold > S->budget) {
+        r.state = kQueued;
+        S->queue.push_front(batch[0]);
+        S->cv_work.notify_all();
+        continue;
+      }
+      S->reserved += hold;
+    }
     try {
       pcc::run_batch(C, jobs.data(), (int)jobs.size(), res.data(), C.own, false);
     } catch (const pcc::Error &e) {
@@ -127,6 +173,8 @@ void worker_main(pcc_server *S, int w) {
     }
     if (err == PCC_E_OUT_OF_MEMORY) C.arena.release();  // start the next batch afresh
     std::lock_guard<std::mutex> lk(S->mu);
+    S->reserved -= hold;
+    S->cv_work.notify_all();  // memory freed: a waiting job may fit now
     if (err == PCC_E_OUT_OF_MEMORY && (batch.size() > 1 || !S->recs[batch[0]].retried)) {
       // run each job of the batch on its own, at the head of the queue; a
       // job that ran out of memory alone gets one more try with the

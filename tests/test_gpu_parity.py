@@ -378,3 +378,44 @@ def test_loss_trace_matches_oracle(ctx, mode, cap):
     _, _, st5 = ctx.correct(_dev(w.orig), _dev(w.recon), w.b, w.xi, mode=mode, box=w.box,
                             trace=5, **kw)
     np.testing.assert_array_equal(st5["viol_trace"], ref.viol_hist[:5])
+
+
+@pytest.mark.parametrize("kind,mode", [("plain", "vp"), ("plain", "hf"), ("cosmo", "hf"),
+                                       ("cosmo", "sc"), ("md", "hf"), ("sph", "sc")])
+def test_workspace_query_bounds_the_call(ctx, kind, mode):
+    # the footprint the served form admits by is at least the workspace the
+    # full call then takes, and within a small factor of it
+    w = {"plain": lambda: synth.plain_blobs(),
+         "cosmo": lambda: synth.cosmology(32, seed=13, xi=0.05),
+         "md": lambda: synth.md_block(40000, 14),
+         "sph": lambda: synth.sph_voids(30000, 15)}[kind]()
+    kw = {"max_iters": 50} if mode != "hf" else {}
+    print("case workspace query", kind, mode, flush=True)
+    q = ctx.workspace_query(_dev(w.orig), _dev(w.recon), w.b, w.xi, mode=mode, box=w.box, **kw)
+    ctx.correct(_dev(w.orig), _dev(w.recon), w.b, w.xi, mode=mode, box=w.box, **kw)
+    hw = ctx.workspace_high_water()
+    assert 0 < hw <= q <= 8 * hw + (4 << 20), (hw, q)
+
+
+def test_cell_list_tables_stay_in_bounds(ctx):
+    # the cell starts and forward-neighbour table every pair pass indexes:
+    # starts nondecreasing from 0 to n, every neighbour entry -1 or a cell
+    cases = [(synth.cosmology(24, seed=16, xi=0.05), "hf"), (synth.md_block(30000, 17), "sc"),
+             (synth.plain_blobs(), "vp"), (synth.plain_blobs(2, seed=18), "hf")]
+    for w, m in cases:
+        print("case cell tables", w.name, flush=True)
+        ctx.correct(_dev(w.orig), _dev(w.recon), w.b, w.xi, mode=m, box=w.box, max_iters=5)
+        cs = ctx.debug_fetch(0, "cell_start").astype(np.int64)
+        nb = ctx.debug_fetch(0, "neighbors").astype(np.int64)
+        u = len(cs) - 1
+        assert cs[0] == 0 and cs[-1] == w.n and np.all(np.diff(cs) >= 1)
+        assert len(nb) == 13 * u and np.all((nb == -1) | ((nb >= 0) & (nb < u)))
+    # several jobs in one index space
+    ws = [synth.plain_blobs(3000, seed=19), synth.cosmology(16, seed=20, xi=0.05)]
+    ctx.correct_batch([dict(orig=_dev(w.orig), recon=_dev(w.recon), b=w.b, xi=w.xi, mode="hf",
+                            box=w.box) for w in ws])
+    cs = ctx.debug_fetch(0, "cell_start").astype(np.int64)
+    nb = ctx.debug_fetch(1, "neighbors").astype(np.int64)
+    u = len(cs) - 1
+    assert cs[-1] == sum(w.n for w in ws) and np.all(np.diff(cs) >= 1)
+    assert np.all((nb == -1) | ((nb >= 0) & (nb < u)))
