@@ -101,7 +101,7 @@ int64_t boruvka(uint64_t *key, uint32_t *u, uint32_t *v, size_t ncand, uint32_t 
 // pgd.hip
 // Iterates of the PGD loop: one record of kPStride float64 per editable row
 // (x, y, z, then padding).
-constexpr int kPStride = 3;
+constexpr int kPStride = 4;
 __device__ inline void load_p(const double *P, size_t i, double &x, double &y, double &z) {
   if (kPStride == 4) {
     const double2 a = reinterpret_cast<const double2 *>(P)[2 * i];

@@ -336,6 +336,10 @@ int pgd_max_waves() { return kPgdBlocks * kPgdWaves; }
 // tiles with at most this many incidences per lane take the chunked
 // evaluation, the others the per-lane walk of whole rows
 constexpr uint32_t kChunkPerLane = 24;
+// calls with at most this many incidences per row on average take the
+// chunked-only kernel (k_pgd_rows)
+constexpr double kRowsKernelDegree = 12.0;
+static_assert(kPStride == 4, "k_pgd_rows reads the iterates as double4 records");
 
 // group of a tile (or of a finalize block): the last with base <= x
 template <typename T>
@@ -829,6 +833,336 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES)
   flush_counts(B, cjob, cslot, wave_id, viol, loss);
 }
 
+// flush of a wave's counts for one job: the violation count (the same in
+// every lane) is added into the wave's counter slot; the loss (per lane) is
+// summed over the wave and stored into the job's loss slot of this wave
+__device__ inline void flush_rows(const PgdBufs &B, int job, int lslot,
+                                    unsigned long long &viol, double &loss) {
+  const double sl = wsum_d(loss);
+  if ((threadIdx.x & 63) == 0 && job >= 0) {
+    if (viol) {
+      const int slot = (int)((blockIdx.x * kPgdWaves + (threadIdx.x >> 6)) & (B.acc_slots - 1));
+      atomicAdd(B.acc + ((size_t)job * B.acc_slots + slot) * 16, viol);
+    }
+    B.lossp[B.lp_off[job] + lslot] = sl;
+  }
+  viol = 0;
+  loss = 0.0;
+}
+
+// The step of a call whose rows have few incidences (one group, passed by
+// value): the chunked evaluation alone.  Each wave walks tiles of up to 64
+// rows of one job's worklist (tiles never straddle two jobs, so the job and
+// its constants are wave-uniform).
+//
+// Hot rows.  A row whose constraints are all satisfied, whose Adam moments
+// are zero and whose position lies in the box is a fixed point of the step
+// bit for bit (zero gradient, zero moments, zero displacement, clamp of a
+// point already inside), and stays one while none of its partners moves.
+// The first step evaluates every row.  A row that is live in some step
+// (moved, had a violated constraint or nonzero moments) becomes hot, and so
+// do its partners, once; from then on hot rows are evaluated in every step.
+// A cold row has never been live and no partner of it has, so none of its
+// distances has changed since the first step: it is still a fixed point
+// with no violated pair.  Its position is the same in both buffers.  So the
+// iterates, the violation counts and the loss are exactly those of
+// evaluating every row in every step.
+//
+// The incidences of the tile's rows are concatenated and spread over the 64
+// lanes, 64 at a time: each lane gathers one partner, evaluates one
+// constraint and leaves its gradient term in LDS; then each row's owner
+// lane adds the terms of its row in column order (increasing partner index).
+// Finally every row takes the Adam step and the projection.  Counts stay in
+// registers until the wave moves to another job or finishes.
+#ifndef PCC_PGD_MIN_WAVES
+#define PCC_PGD_MIN_WAVES 4
+#endif
+__global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_rows(PgdBufs B) {
+  // positions of the tile's rows, one array per axis: lanes read rows at
+  // random, and 8-byte entries spread them over the LDS banks
+  __shared__ double s_px[kPgdWaves][64], s_py[kPgdWaves][64], s_pz[kPgdWaves][64];
+  __shared__ double s_term[kPgdWaves][3][64];
+  __shared__ uint32_t s_rp[kPgdWaves][64];  // first incidence of each row in the CSR
+  __shared__ uint32_t s_vb[kPgdWaves][64];  // first slot of each row in the tile's work list
+  __shared__ uint32_t s_e[kPgdWaves][64];   // row index
+  __shared__ uint8_t s_mk[kPgdWaves][64];   // the row marks its partners hot
+  // loss thresholds b -+ delta_t and their squares per linking length of a
+  // multi-threshold job (read from LDS: a memory load in the evaluation
+  // would make the gathers already in flight complete first)
+  __shared__ double s_thr[kPgdWaves][4][kMaxThresholds];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t nwaves = (int64_t)gridDim.x * kPgdWaves;
+  unsigned long long viol = 0;
+  double loss = 0.0;
+  int cjob = -1;   // job whose counts are held in the registers above
+  int cslot = 0;   // this wave's loss slot of that job
+  for (int64_t tile = (int64_t)blockIdx.x * kPgdWaves + w; tile < B.ntiles; tile += nwaves) {
+    const int job = __builtin_amdgcn_readfirstlane(job_of(B.tile_off, B.njobs, tile));
+    if (B.loop[job].done) continue;
+    const int64_t eoff = B.e_off[job];
+    const int64_t w0 = (tile - B.tile_off[job]) * 64;  // first worklist entry of the tile
+    const int64_t left = (int64_t)B.wl_step[job] - w0;
+    if (left <= 0) continue;
+    if (job != cjob) {
+      flush_rows(B, cjob, cslot, viol, loss);
+      cjob = job;
+      cslot = (int)((tile - B.tile_off[job]) % nwaves);
+    }
+    const int64_t t_step = B.loop[job].t;
+    const int nrow = (int)(left < 64 ? left : 64);
+    const bool valid = lane < nrow;
+    const JobDev &J = B.jobs[job];
+    const int cur = (int)(t_step & 1);
+    const double4 *__restrict__ Pc = reinterpret_cast<const double4 *>(cur ? B.P1 : B.P0);
+    double4 *__restrict__ Pn = reinterpret_cast<double4 *>(cur ? B.P0 : B.P1);
+    const double L0 = J.L[0], L1 = J.L[1], L2 = J.L[2];
+    const double h0 = J.hL[0], h1 = J.hL[1], h2 = J.hL[2];
+    const double bm = J.bm, bp = J.bp, bm2 = J.bm2, bp2 = J.bp2;
+    // the row's position and incidence range; its Adam state is loaded
+    // after the gathers (fewer live registers, more waves in flight)
+    size_t e = 0;
+    uint32_t q0 = 0, len = 0;
+    double4 pe = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (valid) {
+      e = B.wl[eoff + w0 + lane];
+      q0 = B.row_ptr[e];
+      len = B.row_ptr[e + 1] - q0;
+      pe = Pc[e];
+    }
+    uint32_t incl = len;  // inclusive prefix sum of len over the wave
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(incl, d, kWave);
+      if (lane >= d) incl += y;
+    }
+    const uint32_t vb = incl - len, total = __shfl(incl, 63, kWave);
+    s_px[w][lane] = pe.x;
+    s_py[w][lane] = pe.y;
+    s_pz[w][lane] = pe.z;
+    s_rp[w][lane] = q0;
+    s_vb[w][lane] = vb;
+    s_e[w][lane] = (uint32_t)e;
+    if (J.nthr > 1 && lane < 4 * kMaxThresholds) {
+      const int a = lane / kMaxThresholds, k = lane % kMaxThresholds;
+      const double *src = a == 0 ? J.thr_bm : a == 1 ? J.thr_bp : a == 2 ? J.thr_bm2 : J.thr_bp2;
+      s_thr[w][a][k] = src[k];
+    }
+    wave_sync();
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    bool hrow = false;  // some constraint of the row is violated
+    // owner row of slot q (last r with s_vb[r] <= q) and its column entry;
+    // each chunk loads the next chunk's entries before it waits for its own
+    // gathers
+    auto locate = [&](uint32_t q, int &r, uint32_t &col) {
+      int lo = 0, hi = nrow - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_vb[w][mid] <= q)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      r = lo;
+      col = B.col[s_rp[w][lo] + (q - s_vb[w][lo])];
+    };
+    // two-deep pipeline: while chunk c is evaluated, the partner gather of
+    // chunk c + 1 and the column entries of chunk c + 2 are in flight
+    auto gather = [&](uint32_t col) {
+      const double *pp = reinterpret_cast<const double *>(Pc + (col & kColRow));
+      return make_double3(pp[0], pp[1], pp[2]);
+    };
+    int r_nx = 0, r_nx2 = 0;
+    uint32_t col_nx = 0, col_nx2 = 0;
+    double3 po_nx = make_double3(0.0, 0.0, 0.0);
+    if ((uint32_t)lane < total) {
+      locate(lane, r_nx, col_nx);
+      po_nx = gather(col_nx);
+    }
+    if ((uint32_t)lane + 64 < total) locate(lane + 64, r_nx2, col_nx2);
+    for (uint32_t c0 = 0; c0 < total; c0 += 64) {
+      const uint32_t q = c0 + lane;
+      double tx = 0.0, ty = 0.0, tz = 0.0;
+      bool hit = false, hit_once = false;
+      const int r = r_nx;
+      const uint32_t col = col_nx;
+      const double3 po = po_nx;
+      r_nx = r_nx2;
+      col_nx = col_nx2;
+      if (q + 64 < total) po_nx = gather(col_nx);
+      if (q + 128 < total) locate(q + 128, r_nx2, col_nx2);
+      if (q < total) {
+        const uint32_t o = col & kColRow;
+        const uint32_t er = s_e[w][r];
+        const double dx = wrapd(s_px[w][r] - po.x, L0, h0);
+        const double dy = wrapd(s_py[w][r] - po.y, L1, h1);
+        const double dz = wrapd(s_pz[w][r] - po.z, L2, h2);
+        const double d2 = (dx * dx + dy * dy) + dz * dz;
+        // squared threshold of the constraint (b - delta_t for a potentially
+        // broken link, b + delta_t for a potentially created pair): of the
+        // job's linking length, or of the constraint's own when several are
+        // corrected at once
+        const bool created = (col & kColPc) != 0;
+        const uint32_t kk = (col >> kColThrShift) & 7u;
+        double t2 = created ? bp2 : bm2;
+        if (kk) t2 = s_thr[w][created ? 3 : 2][kk];
+        double h = 0.0;
+        if (created ? d2 <= t2 : d2 > t2) {
+          double t1 = created ? bp : bm;
+          if (kk) t1 = s_thr[w][created ? 1 : 0][kk];
+          const double d = sqrt(d2);
+          if (!created) {
+            // potentially broken: an original link pulled back inside b - delta_t
+            h = d - t1;
+            tx = 2.0 * h * (dx / d);
+            ty = 2.0 * h * (dy / d);
+            tz = 2.0 * h * (dz / d);
+          } else {
+            // potentially created: an original non-link pushed beyond b + delta_t
+            h = t1 - d;
+            double ux, uy, uz;
+            if (d > 0.0) {
+              ux = dx / d;
+              uy = dy / d;
+              uz = dz / d;
+            } else {
+              // coincident points: take the direction of the original pair
+              const float4 a = B.xo[er], b = B.xo[o];
+              const double ox = wrapd((double)a.x - (double)b.x, L0, h0);
+              const double oy = wrapd((double)a.y - (double)b.y, L1, h1);
+              const double oz = wrapd((double)a.z - (double)b.z, L2, h2);
+              const double od = sqrt((ox * ox + oy * oy) + oz * oz);
+              ux = ox / od;
+              uy = oy / od;
+              uz = oz / od;
+            }
+            tx = -(2.0 * h * ux);
+            ty = -(2.0 * h * uy);
+            tz = -(2.0 * h * uz);
+          }
+          hit = true;
+        }
+        if (hit && o > er) loss += h * h;
+        hit_once = hit && o > er;
+      }
+      s_term[w][0][lane] = tx;
+      s_term[w][1][lane] = ty;
+      s_term[w][2][lane] = tz;
+      const uint64_t hb = __ballot(hit);
+      viol += (unsigned)__popcll(__ballot(hit_once));
+      wave_sync();
+      // the owner adds the terms of its row that fall in this chunk, in order
+      const uint32_t a = vb > c0 ? vb : c0;
+      const uint32_t b = vb + len < c0 + 64 ? vb + len : c0 + 64;
+      for (uint32_t t = a; t < b; ++t) {
+        gx += s_term[w][0][t - c0];
+        gy += s_term[w][1][t - c0];
+        gz += s_term[w][2][t - c0];
+      }
+      if (b > a) {
+        const uint32_t wd = b - a;
+        const uint64_t mask = (wd >= 64 ? ~0ull : ((1ull << wd) - 1ull)) << (a - c0);
+        hrow |= (hb & mask) != 0;
+      }
+      wave_sync();
+    }
+    bool mark = false;
+    if (valid) {
+      const uint32_t hotv = B.hot[e];
+      const float4 x = B.xo[e];
+      double mo[3], vo[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        mo[k] = B.m[(size_t)k * B.ne + e];
+        vo[k] = B.v[(size_t)k * B.ne + e];
+      }
+      const double bc1 = B.loop[job].bc1, bc2 = B.loop[job].bc2;
+      // the step's constants, read once: the compiler must assume that the
+      // moment stores below may alias the job table, and would load them
+      // again (and wait for the load) for every coordinate
+      const int opt = J.optimizer;
+      const double lr = J.lr, beta1 = J.beta1, beta2 = J.beta2,
+                   omb1 = J.one_m_beta1,
+                   omb2 = J.one_m_beta2, aeps = J.adam_eps, xip = J.xi_p;
+      const double g[3] = {gx, gy, gz};
+      const double p[3] = {s_px[w][lane], s_py[w][lane], s_pz[w][lane]};
+      const double xs[3] = {(double)x.x, (double)x.y, (double)x.z};
+      double np[3];
+      uint64_t state = 0;
+      bool moved = false;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        double r;
+        if (opt == 1) {
+          r = p[k] - lr * g[k];
+        } else {
+          const size_t ia = (size_t)k * B.ne + e;
+          const double m = beta1 * mo[k] + omb1 * g[k];
+          const double v = beta2 * vo[k] + omb2 * g[k] * g[k];
+          B.m[ia] = m;
+          B.v[ia] = v;
+          state |= dbits(m) | dbits(v);
+          const double mh = m / bc1;
+          const double vh = v / bc2;
+          r = p[k] - lr * mh / (sqrt(vh) + aeps);
+        }
+        np[k] = fmin(fmax(r, xs[k] - xip), xs[k] + xip);
+        moved |= dbits(np[k]) != dbits(p[k]);
+        // one coordinate at a time: interleaving the three divide and
+        // square-root sequences costs registers, hence occupancy
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      Pn[e] = make_double4(np[0], np[1], np[2], 0.0);
+      // a live row that has not yet done so marks itself and its partners hot
+      mark = (moved || hrow || state != 0) && hotv != 2;
+      if (mark) B.hot[e] = 2;
+    }
+    if (__ballot(mark)) {
+      s_mk[w][lane] = mark ? 1 : 0;
+      wave_sync();
+      for (uint32_t c0 = 0; c0 < total; c0 += 64) {
+        const uint32_t q = c0 + lane;
+        bool app = false;
+        uint32_t o = 0;
+        if (q < total) {
+          int lo = 0, hi = nrow - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_vb[w][mid] <= q)
+              lo = mid;
+            else
+              hi = mid - 1;
+          }
+          if (s_mk[w][lo]) {
+            o = B.col[s_rp[w][lo] + (q - s_vb[w][lo])] & kColRow;
+            uint32_t cold = 0u;
+            // the first marking of a cold row appends it to the worklist
+            // (after the first step, which lists every row and is followed
+            // by a compaction of the hot ones)
+            app = __hip_atomic_compare_exchange_strong(B.hot + o, &cold, 1u, __ATOMIC_RELAXED,
+                                                       __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT) &&
+                  t_step > 0;
+          }
+        }
+        const uint64_t am = __ballot(app);
+        if (am) {
+          const unsigned long long deg = app ? B.row_ptr[o + 1] - B.row_ptr[o] : 0u;
+          const unsigned long long sdeg = wsum(deg);
+          uint32_t base = 0;
+          if (lane == 0) {
+            base = atomicAdd(B.wl_n + job, (uint32_t)__popcll(am));
+            atomicAdd((unsigned long long *)B.inc_n + job, sdeg);
+          }
+          base = __shfl(base, 0, kWave);
+          if (app) B.wl[eoff + base + __popcll(am & ((1ull << lane) - 1ull))] = o;
+        }
+      }
+    }
+    wave_sync();  // LDS of this tile is reused by the next one
+  }
+  flush_rows(B, cjob, cslot, viol, loss);
+}
+
 __global__ void k_hot_init(PgdBufs B, size_t n) {
   const size_t nacc = (size_t)B.njobs * B.acc_slots * 16;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -1045,7 +1379,12 @@ void launch_pgd_step(const PgdGroups *g, const PgdBufs &b, hipStream_t s) {
   if (b.ne) {
     // the loss slots were sized for this many waves
     if (b.nwaves != pgd_step_waves(b.ne)) throw Error(-3, "PGD step grid differs from its loss slots");
-    k_pgd_step<<<b.nwaves / kPgdWaves, 64 * kPgdWaves, 0, s>>>(g);
+    // few incidences per row on average: the chunked kernel with the
+    // buffers as its argument; else the kernel with both evaluations
+    if ((double)b.ninc <= kRowsKernelDegree * (double)b.ne)
+      k_pgd_rows<<<b.nwaves / kPgdWaves, 64 * kPgdWaves, 0, s>>>(b);
+    else
+      k_pgd_step<<<b.nwaves / kPgdWaves, 64 * kPgdWaves, 0, s>>>(g);
   }
 }
 void launch_pgd_finalize(const PgdGroups *g, const PgdBufs &b, hipStream_t s) {
