@@ -485,6 +485,12 @@ def served_line(ctx, ws, specs, args):
                         + "\n")
     if not args.no_verify:
         out["membership_errors"], out["box_violations"] = _verify_many(ctx, ws, res)
+        conv = [k for k in range(len(ws)) if statuses[k] == 0]
+        capped = [k for k in range(len(ws)) if statuses[k] == 1]
+        out["membership_errors_converged_jobs"] = _verify_many(
+            ctx, [ws[k] for k in conv], [res[k] for k in conv])[0]
+        out["membership_errors_capped_jobs"] = _verify_many(
+            ctx, [ws[k] for k in capped], [res[k] for k in capped])[0]
         small = [k for k in range(len(ws)) if ws[k].n <= 200_000]
         picks = small[:: max(1, len(small) // 4)][:4]
         out["oracle_label_mismatches"] = _oracle_labels_check(ws, res, picks)

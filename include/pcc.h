@@ -429,7 +429,7 @@ typedef struct {
   size_t hbm_budget;     /* device bytes the workers may use together; 0 = 80%
                             of the free memory at creation */
   int32_t max_inflight;  /* jobs per batch at most; 0 = 256 */
-  int32_t n_streams;     /* calls in flight at once (slots); 0 = 4 */
+  int32_t n_streams;     /* calls in flight at once (slots), 0 .. 32; 0 = 16 */
 } pcc_server_config;
 
 pcc_status pcc_server_create(pcc_context *ctx, const pcc_server_config *cfg,

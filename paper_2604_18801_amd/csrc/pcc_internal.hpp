@@ -134,6 +134,11 @@ class Arena {
   // release() then forgets the buffer without freeing it.
   void attach(void *base, size_t bytes);
   size_t used() const { return used_; }
+  size_t capacity() const {  // device bytes the arena holds
+    size_t c = 0;
+    for (const auto &k : chunks_) c += k.size;
+    return c;
+  }
   size_t high_water() const { return high_; }  // most bytes in use since reset()
 
  private:

@@ -171,7 +171,11 @@ void worker_main(pcc_server *S, int w) {
       err = PCC_E_DEVICE;
       msg = e.what();
     }
-    if (err == PCC_E_OUT_OF_MEMORY) C.arena.release();  // start the next batch afresh
+    // a workspace grown beyond the slot's share of the budget goes back to
+    // the device (so that idle slots do not hold what running ones need);
+    // after running out of memory the next batch starts afresh
+    if (err == PCC_E_OUT_OF_MEMORY || (double)C.arena.capacity() > S->budget / (double)S->ctx.size())
+      C.arena.release();
     std::lock_guard<std::mutex> lk(S->mu);
     S->reserved -= hold;
     S->cv_work.notify_all();  // memory freed: a waiting job may fit now
@@ -240,13 +244,13 @@ pcc_status pcc_server_create(pcc_context *ctx, const pcc_server_config *cfg, pcc
   pcc_server_config c{};
   if (cfg) c = *cfg;
   if (c.max_inflight < 0 || c.max_inflight > PCC_MAX_BATCH_JOBS || c.n_streams < 0 ||
-      c.n_streams > 16)
-    return fail(PCC_E_INVALID_ARG, "max_inflight >= 0 and n_streams in 0..16");
+      c.n_streams > 32)
+    return fail(PCC_E_INVALID_ARG, "max_inflight >= 0 and n_streams in 0..32");
   try {
     auto *S = new pcc_server;
     S->device = ctx->c.device;
     S->max_inflight = c.max_inflight ? c.max_inflight : 256;
-    const int nw = c.n_streams ? c.n_streams : 4;
+    const int nw = c.n_streams ? c.n_streams : 16;
     if (hipSetDevice(S->device) != hipSuccess) {
       delete S;
       return fail(PCC_E_DEVICE, "hipSetDevice failed");

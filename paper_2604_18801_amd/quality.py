@@ -29,9 +29,11 @@ def _volume(w) -> float:
 
 
 def study(ctx, w, modes=("hf",), caps=(0, 1, 3, 10, 30, 100, None), bins=50, min_members=20,
-          **opts):
+          trace=False, **opts):
     """Yields a row of metrics for every (mode, cap) as it is measured;
-    cap None = to convergence (or the library's safety cap)."""
+    cap None = to convergence (or the library's safety cap).  With trace,
+    each row also holds the loss of Eq. 3 and the violation count at every
+    evaluation (the loss-against-iteration curve)."""
     import torch
     o = torch.from_numpy(np.ascontiguousarray(w.orig)).cuda()
     r = torch.from_numpy(np.ascontiguousarray(w.recon)).cuda()
@@ -51,6 +53,8 @@ def study(ctx, w, modes=("hf",), caps=(0, 1, 3, 10, 30, 100, None), bins=50, min
                 kw["max_iters"] = int(cap)
             torch.cuda.synchronize()
             t = time.perf_counter()
+            if trace:
+                kw["trace"] = (int(cap) + 1) if cap is not None else 100001
             stream, _, st = ctx.correct(o, r, w.b, w.xi, mode=mode, box=w.box, labels=False, **kw)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t
@@ -63,6 +67,9 @@ def study(ctx, w, modes=("hf",), caps=(0, 1, 3, 10, 30, 100, None), bins=50, min
                    "n_active": st["n_active"], "stream_bytes": len(stream),
                    "ms": round(1e3 * dt, 2), "box_violations": box_viol}
             row.update(metrics.all_metrics(lab0, lab, vol, bins, min_members))
+            if trace:
+                row["loss_trace"] = [float(v) for v in st["loss_trace"]]
+                row["viol_trace"] = [int(v) for v in st["viol_trace"]]
             yield row
 
 
@@ -90,6 +97,8 @@ def main(argv=None):
     ap.add_argument("--min-members", type=int, default=20)
     ap.add_argument("--optimizer", default="adam", choices=("adam", "sgd"))
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--trace", action="store_true",
+                    help="add the per-evaluation loss and violation count to every row")
     args = ap.parse_args(argv)
     import paper_2604_18801_amd as pcc
     w = _workload(args.workload)
@@ -97,7 +106,8 @@ def main(argv=None):
     ctx = pcc.Context(0)
     try:
         for row in study(ctx, w, modes=tuple(args.modes.split(",")), caps=caps, bins=args.bins,
-                         min_members=args.min_members, optimizer=args.optimizer, lr=args.lr):
+                         min_members=args.min_members, trace=args.trace,
+                         optimizer=args.optimizer, lr=args.lr):
             row["workload"] = args.workload
             row["optimizer"] = args.optimizer
             print(json.dumps(row), flush=True)
