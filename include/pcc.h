@@ -301,10 +301,15 @@ pcc_status pcc_decode(const uint8_t *stream, size_t len, const pcc_particles *re
 
 /*
  * The same decoding with device arrays (recon and out on the context's GPU):
- * the stream (a host buffer) is parsed on the host -- ZSTD, then the one
- * sequential Huffman bitstream -- and a kernel applies the edits; the output
- * equals pcc_decode's bit for bit.  Work is queued on hip_stream and the call
- * returns when it is done.  Invalidates the context's retained debug data.
+ * the host undoes ZSTD and reads the stream's tables (flag mask, canonical
+ * Huffman code, chunk index); the Huffman bitstream is decoded on the GPU,
+ * one thread per chunk of 4096 symbols starting at the bit the stream's
+ * chunk index gives, and a kernel applies the edits; the output equals
+ * pcc_decode's bit for bit.  A bitstream whose codes do not end exactly at
+ * the next chunk start, or code lengths that no prefix code has, give
+ * PCC_E_INVALID_ARG with the output untouched.  Work is queued on
+ * hip_stream and the call returns when it is done.  Invalidates the
+ * context's retained debug data.
  */
 pcc_status pcc_decode_device(pcc_context *ctx, const uint8_t *stream, size_t len,
                              const pcc_particles *recon, float *out_x, float *out_y,

@@ -582,7 +582,7 @@ static int64_t pgd(int64_t na, const uint32_t *a_i, const uint32_t *a_j,
  * Byte layout (little-endian), shared with the GPU library by specification
  * only:
  *   header, 64 bytes:
- *     u32 magic 0x45434350 | u16 version 1 | u8 m | u8 flags
+ *     u32 magic 0x45434350 | u16 version 2 | u8 m | u8 flags
  *     (bit 0: payload is one ZSTD frame, bit 1: symbols are Huffman coded)
  *     u64 n | u64 flagged | f64 step | f64 offset | u64 raw payload bytes |
  *     u64 stored payload bytes | u32 symbol bits (8 or 16) | u32 0
@@ -591,14 +591,19 @@ static int64_t pgd(int64_t na, const uint32_t *a_i, const uint32_t *a_j,
  *     the symbol sequence: for axis x, y, z, for each flagged particle in
  *     increasing index, its code (m = 32: low 16 bits, then high 16 bits);
  *     Huffman coded: u32 K, K u32 symbols, K u8 code lengths, u64 bit count,
- *     then the bits; canonical codes in (length, symbol) order, each code
- *     emitted most significant bit first, stream bit q at bit (q mod 8) of
- *     byte (q div 8).  Otherwise the symbols as little-endian integers.
+ *     u32 C (symbols per chunk), u32 0, then for each chunk of C symbols
+ *     (the last one may be shorter) the u64 stream bit at which its first
+ *     code starts, then the bits; canonical codes in (length, symbol) order,
+ *     each code emitted most significant bit first, stream bit q at bit
+ *     (q mod 8) of byte (q div 8).  The chunk starts let a decoder begin at
+ *     any chunk.  Otherwise the symbols as little-endian integers.
  *   decode: edit = code * step - offset; x' = float32(x_hat + edit).
  */
 #define ORC_MAGIC 0x45434350u
+#define ORC_VERSION 2
 #define ORC_HDR 64
 #define ORC_MAXLEN 24
+#define ORC_CHUNK 4096
 
 typedef size_t (*zbound_fn)(size_t);
 typedef size_t (*zcomp_fn)(void *, size_t, const void *, size_t, int);
@@ -807,7 +812,8 @@ static int64_t encode(int64_t n, const float *const rec[3], double *const p[3],
     uint64_t nbits = 0;
     for (int64_t s = 0; s < nsym; s++) nbits += sym_len[sym[s]];
     int64_t bbytes = (int64_t)((nbits + 7) / 8);
-    raw_len = nb + 4 + 5 * k + 8 + bbytes;
+    int64_t nchunks = (nsym + ORC_CHUNK - 1) / ORC_CHUNK;
+    raw_len = nb + 4 + 5 * k + 8 + 8 + 8 * nchunks + bbytes;
     payload = (uint8_t *)xcalloc((size_t)raw_len, 1);
     memcpy(payload, flags, (size_t)nb);
     uint8_t *q = payload + nb;
@@ -819,8 +825,13 @@ static int64_t encode(int64_t n, const float *const rec[3], double *const p[3],
     q += k;
     put_u64(q, nbits);
     q += 8;
+    put_u32(q, ORC_CHUNK);
+    q += 8;
+    uint8_t *index = q;
+    q += 8 * nchunks;
     uint64_t pos = 0;
     for (int64_t s = 0; s < nsym; s++) {
+      if (s % ORC_CHUNK == 0) put_u64(index + 8 * (s / ORC_CHUNK), pos);
       uint32_t cd = sym_code[sym[s]];
       int l = sym_len[sym[s]];
       for (int bit = l - 1; bit >= 0; bit--) {
@@ -861,7 +872,7 @@ static int64_t encode(int64_t n, const float *const rec[3], double *const p[3],
   }
   uint8_t *s = (uint8_t *)xcalloc((size_t)(ORC_HDR + stored_len), 1);
   put_u32(s + 0, ORC_MAGIC);
-  put_u16(s + 4, 1);
+  put_u16(s + 4, ORC_VERSION);
   s[6] = (uint8_t)m;
   s[7] = (uint8_t)((zflag ? 1 : 0) | (use_huff ? 2 : 0));
   put_u64(s + 8, (uint64_t)n);
@@ -883,7 +894,8 @@ static int64_t encode(int64_t n, const float *const rec[3], double *const p[3],
  * the dequantised edits to the flagged particles, add them to x_hat. */
 int orc_decode(const uint8_t *stream, int64_t len, int64_t n,
                const float *const rec[3], float *const out[3]) {
-  if (len < ORC_HDR || get_u32(stream) != ORC_MAGIC || get_u16(stream + 4) != 1) return -1;
+  if (len < ORC_HDR || get_u32(stream) != ORC_MAGIC || get_u16(stream + 4) != ORC_VERSION)
+    return -1;
   int m = stream[6], fl = stream[7];
   if ((int64_t)get_u64(stream + 8) != n) return -1;
   int64_t nf = (int64_t)get_u64(stream + 16);
@@ -923,6 +935,17 @@ int orc_decode(const uint8_t *stream, int64_t len, int64_t n,
     q += k;
     uint64_t nbits = get_u64(q);
     q += 8;
+    uint32_t chunk = get_u32(q);
+    q += 8;
+    if (chunk == 0) {
+      free(cl);
+      free(sym);
+      free(payload);
+      return -1;
+    }
+    /* the chunk starts: checked against the positions the decoding reaches */
+    const uint8_t *index = q;
+    q += 8 * (size_t)((nsym + chunk - 1) / chunk);
     uint32_t *code = (uint32_t *)xmalloc(sizeof(uint32_t) * (size_t)(k ? k : 1));
     canonical_codes(k, cl, code);
     /* per length: first canonical code and index of its first symbol */
@@ -945,6 +968,13 @@ int orc_decode(const uint8_t *stream, int64_t len, int64_t n,
     for (int64_t s = 0; s < nsym; s++) {
       uint32_t cd = 0;
       int l = 0;
+      if (s % chunk == 0 && get_u64(index + 8 * (size_t)(s / chunk)) != pos) {
+        free(cl);
+        free(code);
+        free(sym);
+        free(payload);
+        return -1;
+      }
       for (;;) {
         if (pos >= nbits || l >= ORC_MAXLEN) {
           free(cl);

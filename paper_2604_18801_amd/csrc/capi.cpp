@@ -196,6 +196,7 @@ pcc_status pcc_context_destroy(pcc_context *ctx) {
   if (!ctx) return PCC_OK;
   hipSetDevice(ctx->c.device);
   hipDeviceSynchronize();
+  ctx->c.pgd_graph.clear();
   ctx->c.arena.release();
   for (auto &t : ctx->c.bc) hipFree(t.dev);
   for (auto &e : ctx->c.ev)
@@ -332,14 +333,15 @@ pcc_status pcc_decode_device(pcc_context *ctx, const uint8_t *stream, size_t len
   return guarded([&]() -> pcc_status {
     std::string err;
     pcc::ParsedStream ps;
-    const pcc_status st = pcc::parse_stream(stream, len, recon->n, ps, err);
+    const pcc_status st = pcc::parse_stream(stream, len, recon->n, ps, err, false);
     if (st != PCC_OK) return fail(st, err);
     PCC_HIP(hipSetDevice(ctx->c.device));
     ctx->c.arena.reset();
     ctx->c.last.valid = false;  // the arena's contents of the last correction are gone
     const float *rin[3] = {recon->x, recon->y, recon->z};
     float *rout[3] = {out_x, out_y, out_z};
-    pcc::apply_edits_device(ps, rin, rout, ctx->c.arena, pick(ctx, hip_stream));
+    if (!pcc::apply_edits_device(ps, rin, rout, ctx->c.arena, pick(ctx, hip_stream)))
+      return fail(PCC_E_INVALID_ARG, "corrupt Huffman data");
     return PCC_OK;
   });
 }

@@ -196,8 +196,13 @@ __constant__ int8_t kFwd[13][3] = {{1, 0, 0},  {-1, 1, 0}, {0, 1, 0},  {1, 1, 0}
 
 // One thread per (cell, forward offset): the 13 binary searches of a cell
 // run in parallel threads instead of one after another.
+// The thread of offset 0 also records the cell's periodic edges: bit 2a
+// when the cell is the first along periodic axis a, bit 2a + 1 when it is
+// the last (only for jobs whose coordinates lie in their periodic box, where
+// a neighbour cell across an edge stands for one periodic image).
 __global__ void k_neighbors(const JobDev *jobs, const uint32_t *cell_base, int njobs,
-                            const uint32_t *cell_key, const uint32_t *n_cells, int32_t *nbr) {
+                            const uint32_t *cell_key, const uint32_t *n_cells, int32_t *nbr,
+                            uint8_t *edge) {
   const uint32_t U = *n_cells;
   const size_t total = (size_t)U * 13;
   for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
@@ -219,6 +224,16 @@ __global__ void k_neighbors(const JobDev *jobs, const uint32_t *cell_base, int n
     const int64_t c[3] = {(int64_t)(local % (uint32_t)J.nc[0]),
                           (int64_t)((local / (uint32_t)J.nc[0]) % (uint32_t)J.nc[1]),
                           (int64_t)(local / ((uint32_t)J.nc[0] * (uint32_t)J.nc[1]))};
+    if (s == 0) {
+      uint32_t eb = 0;
+      if (J.img)
+        for (int a = 0; a < 3; ++a)
+          if (((J.periodic >> a) & 1) && J.nc[a] >= 3) {
+            if (c[a] == 0) eb |= 1u << (2 * a);
+            if (c[a] == J.nc[a] - 1) eb |= 1u << (2 * a + 1);
+          }
+      edge[u] = (uint8_t)eb;
+    }
     int64_t q[3];
     bool ok = true;
 #pragma unroll
@@ -251,10 +266,10 @@ __global__ void k_neighbors(const JobDev *jobs, const uint32_t *cell_base, int n
 
 void launch_neighbors(const JobDev *jobs, const uint32_t *cell_base, int njobs,
                       const uint32_t *cell_key, const uint32_t *n_cells, size_t max_cells,
-                      int32_t *nbr, hipStream_t s) {
+                      int32_t *nbr, uint8_t *edge, hipStream_t s) {
   if (max_cells)
     k_neighbors<<<blocks_for(max_cells * 13, 256, 65536), 256, 0, s>>>(jobs, cell_base, njobs,
-                                                                       cell_key, n_cells, nbr);
+                                                                       cell_key, n_cells, nbr, edge);
 }
 
 }  // namespace pcc

@@ -4,13 +4,16 @@
 // stored uncompressed when it is missing), stream assembly and decoding.
 //
 // Byte layout (little-endian):
-//   header, 64 bytes: u32 magic 0x45434350 | u16 version 1 | u8 m | u8 flags
+//   header, 64 bytes: u32 magic 0x45434350 | u16 version 2 | u8 m | u8 flags
 //     (bit 0: payload is one ZSTD frame, bit 1: Huffman-coded symbols)
 //     | u64 n | u64 flagged | f64 step | f64 offset | u64 raw payload bytes
 //     | u64 stored payload bytes | u32 symbol bits (8 or 16) | u32 0
 //   payload: ceil(n/8) flag bytes (particle k at bit k mod 8 of byte k / 8),
 //     then for flagged > 0: u32 K | K u32 symbols | K u8 code lengths |
-//     u64 bit count | the bits.  Symbols run x plane, y plane, z plane, each
+//     u64 bit count | u32 C | u32 0 | the u64 stream bit at which each chunk
+//     of C symbols starts (the last chunk may be shorter) | the bits; the
+//     chunk starts let the device decoder give every chunk its own thread.
+//     Symbols run x plane, y plane, z plane, each
 //     over the flagged particles in increasing index; m = 32 codes are a low
 //     then a high 16-bit symbol.  Canonical codes in (length, symbol) order,
 //     most significant bit first; stream bit q is bit q mod 8 of byte q / 8.
@@ -29,6 +32,7 @@ namespace pcc {
 
 namespace {
 constexpr uint32_t kMagic = 0x45434350u;
+constexpr uint16_t kVersion = 2;
 constexpr int kMaxLen = 24;
 constexpr size_t kHeader = 64;
 
@@ -197,19 +201,24 @@ void huffman_build(const uint32_t *hist, int alphabet, HuffTable &out) {
 size_t stream_bound(int64_t n, int m_bits) {
   if (n < 0) n = 0;
   const size_t per = m_bits == 32 ? 2 : 1;
-  const size_t raw = ((size_t)n + 7) / 8 + 4 + 5 * 65536 + 8 + ((size_t)n * 3 * per * kMaxLen + 7) / 8;
+  const size_t nsym = (size_t)n * 3 * per;
+  const size_t raw = ((size_t)n + 7) / 8 + 4 + 5 * 65536 + 8 + 8 +
+                     8 * ((nsym + kHuffChunk - 1) / kHuffChunk) + (nsym * kMaxLen + 7) / 8;
   return kHeader + raw + raw / 128 + 4096;
 }
 
 void assemble_stream(int64_t n, int m_bits, int64_t nflagged, double qstep, double qoffset,
                      const uint8_t *flags, size_t nflag_bytes, const HuffTable *ht,
-                     const uint32_t *words, uint64_t nbits, std::vector<uint8_t> &out,
-                     size_t *payload_raw) {
+                     const uint32_t *words, uint64_t nbits, const uint64_t *chunk_bits,
+                     size_t nchunks, std::vector<uint8_t> &out, size_t *payload_raw) {
   std::vector<uint8_t> pay;
   const size_t nb = ((size_t)n + 7) / 8;
   const bool huff = nflagged > 0 && ht && !ht->syms.empty();
+  const size_t nsym = (size_t)nflagged * 3 * (m_bits == 32 ? 2 : 1);
+  if (huff && nchunks != (nsym + kHuffChunk - 1) / kHuffChunk)
+    throw Error(PCC_E_DEVICE, "chunk index does not match the symbol count");
   size_t raw = nb;
-  if (huff) raw += 4 + 5 * ht->syms.size() + 8 + (size_t)((nbits + 7) / 8);
+  if (huff) raw += 4 + 5 * ht->syms.size() + 8 + 8 + 8 * nchunks + (size_t)((nbits + 7) / 8);
   pay.assign(raw, 0);
   if (nb) std::memcpy(pay.data(), flags, std::min(nb, nflag_bytes));
   if (huff) {
@@ -223,6 +232,9 @@ void assemble_stream(int64_t n, int m_bits, int64_t nflagged, double qstep, doub
     for (uint8_t l : ht->lens) pay[at++] = l;
     put<uint64_t>(pay, at, nbits);
     at += 8;
+    put<uint32_t>(pay, at, kHuffChunk);
+    at += 8;
+    for (size_t c = 0; c < nchunks; ++c, at += 8) put<uint64_t>(pay, at, chunk_bits[c]);
     std::memcpy(pay.data() + at, words, (size_t)((nbits + 7) / 8));
   }
   *payload_raw = raw;
@@ -231,7 +243,7 @@ void assemble_stream(int64_t n, int m_bits, int64_t nflagged, double qstep, doub
   const std::vector<uint8_t> &stored = zok ? z : pay;
   out.assign(kHeader + stored.size(), 0);
   put<uint32_t>(out, 0, kMagic);
-  put<uint16_t>(out, 4, 1);
+  put<uint16_t>(out, 4, kVersion);
   out[6] = (uint8_t)m_bits;
   out[7] = (uint8_t)((zok ? 1 : 0) | (huff ? 2 : 0));
   put<uint64_t>(out, 8, (uint64_t)n);
@@ -245,9 +257,11 @@ void assemble_stream(int64_t n, int m_bits, int64_t nflagged, double qstep, doub
 }
 
 pcc_status parse_stream(const uint8_t *s, size_t len, int64_t n, ParsedStream &out,
-                        std::string &err) {
-  if (len < kHeader || get<uint32_t>(s) != kMagic || get<uint16_t>(s + 4) != 1)
+                        std::string &err, bool huffman_on_host) {
+  if (len < kHeader || get<uint32_t>(s) != kMagic)
     return err = "not an edit stream", PCC_E_INVALID_ARG;
+  if (get<uint16_t>(s + 4) != kVersion)
+    return err = "edit stream of another format version", PCC_E_INVALID_ARG;
   const int m = s[6], fl = s[7];
   if ((int64_t)get<uint64_t>(s + 8) != n) return err = "particle count differs from the stream", PCC_E_INVALID_ARG;
   const uint64_t nf = get<uint64_t>(s + 16);
@@ -271,7 +285,7 @@ pcc_status parse_stream(const uint8_t *s, size_t len, int64_t n, ParsedStream &o
   const int per = m == 32 ? 2 : 1;
   const size_t nsym = (size_t)nf * 3 * per;
   std::vector<uint32_t> &sym = out.sym;
-  sym.assign(nsym, 0);
+  sym.assign((fl & 2) && !huffman_on_host ? 0 : nsym, 0);
   const uint8_t *p = pay.data() + nb, *end = pay.data() + raw;
   if (nsym && (fl & 2)) {
     if (end - p < 4) return err = "payload too short", PCC_E_INVALID_ARG;
@@ -286,7 +300,21 @@ pcc_status parse_stream(const uint8_t *s, size_t len, int64_t n, ParsedStream &o
     p += k;
     const uint64_t nbits = get<uint64_t>(p);
     p += 8;
+    if (end - p < 8) return err = "payload too short", PCC_E_INVALID_ARG;
+    const uint32_t chunk = get<uint32_t>(p);
+    p += 8;
+    if (chunk == 0) return err = "corrupt chunk index", PCC_E_INVALID_ARG;
+    const size_t nchunks = (nsym + chunk - 1) / chunk;
+    if ((size_t)(end - p) / 8 < nchunks) return err = "payload too short", PCC_E_INVALID_ARG;
+    const uint8_t *index = p;
+    p += 8 * nchunks;
     if ((uint64_t)(end - p) * 8 < nbits) return err = "payload too short", PCC_E_INVALID_ARG;
+    // chunk starts: from bit 0, non-decreasing, inside the bitstream
+    for (size_t c = 0; c < nchunks; ++c) {
+      const uint64_t b = get<uint64_t>(index + 8 * c);
+      if ((c == 0 && b != 0) || (c > 0 && b < get<uint64_t>(index + 8 * (c - 1))) || b > nbits)
+        return err = "corrupt chunk index", PCC_E_INVALID_ARG;
+    }
     // symbols in canonical order: by length, then symbol value
     std::vector<uint32_t> order(k);
     for (uint32_t i = 0; i < k; ++i) {
@@ -297,8 +325,22 @@ pcc_status parse_stream(const uint8_t *s, size_t len, int64_t n, ParsedStream &o
     std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
       return lens[a] != lens[b] ? lens[a] < lens[b] : syms[a] < syms[b];
     });
+    out.huff = true;
+    out.canon_sym.resize(k);
+    out.canon_len.resize(k);
+    for (uint32_t r = 0; r < k; ++r) {
+      out.canon_sym[r] = syms[order[r]];
+      out.canon_len[r] = lens[order[r]];
+    }
+    out.nbits = nbits;
+    out.chunk = chunk;
+    out.nchunks = nchunks;
+    out.index_at = (size_t)(index - pay.data());
+    out.bits_at = (size_t)(p - pay.data());
     uint64_t q = 0;
-    for (size_t t = 0; t < nsym; ++t) {
+    for (size_t t = 0; huffman_on_host && t < nsym; ++t) {
+      if (t % chunk == 0 && get<uint64_t>(index + 8 * (t / chunk)) != q)
+        return err = "corrupt chunk index", PCC_E_INVALID_ARG;
       // walk the code lengths: codes of length l are a contiguous range
       int64_t code = 0, first = 0, index = 0;
       int l = 1;
@@ -342,7 +384,7 @@ pcc_status parse_stream(const uint8_t *s, size_t len, int64_t n, ParsedStream &o
 pcc_status decode_stream(const uint8_t *s, size_t len, int64_t n, const float *rx, const float *ry,
                          const float *rz, float *ox, float *oy, float *oz, std::string &err) {
   ParsedStream ps;
-  const pcc_status st = parse_stream(s, len, n, ps, err);
+  const pcc_status st = parse_stream(s, len, n, ps, err, true);
   if (st != PCC_OK) return st;
   const std::vector<uint8_t> &pay = ps.payload;
   const std::vector<uint32_t> &sym = ps.sym;

@@ -68,6 +68,26 @@ struct KernelTimer {
 
 class PgdEngine;
 
+// The instantiated PGD graph of the last call, kept for the next call whose
+// launches are identical (same buffers and sizes: the same job shapes on a
+// workspace laid out the same way), which then skips capture and
+// instantiation.
+struct PgdGraphCache {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  PgdBufs bufs{};
+  const PgdGroups *groups = nullptr;
+  int steps = 0;
+  void clear() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    groups = nullptr;
+    steps = 0;
+  }
+};
+
 struct Context {
   int device = 0;
   // served form: the shared PGD loop this context's calls join (none for a
@@ -81,6 +101,7 @@ struct Context {
   int dense_cell = 32;   // cells with at least this many particles take the dense pair path
   std::vector<BcTable> bc;
   hipStream_t own = nullptr;
+  PgdGraphCache pgd_graph;
   Arena arena;
   LastCall last;
   hipEvent_t ev[12] = {};
@@ -142,10 +163,12 @@ bool zstd_compress(const uint8_t *src, size_t len, std::vector<uint8_t> &dst, in
 bool zstd_decompress(const uint8_t *src, size_t len, uint8_t *dst, size_t raw_len);
 size_t stream_bound(int64_t n, int m_bits);
 // header + payload assembly
+// symbols per chunk of the Huffman bitstream's chunk index
+constexpr uint32_t kHuffChunk = 4096;
 void assemble_stream(int64_t n, int m_bits, int64_t nflagged, double qstep, double qoffset,
                      const uint8_t *flags, size_t nflag_bytes, const HuffTable *ht,
-                     const uint32_t *words, uint64_t nbits, std::vector<uint8_t> &out,
-                     size_t *payload_raw);
+                     const uint32_t *words, uint64_t nbits, const uint64_t *chunk_bits,
+                     size_t nchunks, std::vector<uint8_t> &out, size_t *payload_raw);
 // a stream's flags (first flag_bytes bytes of payload, bit k of byte k/8)
 // and its symbols (planes x, y, z over the flagged particles in increasing
 // index; m = 32 codes are a low then a high 16-bit symbol)
@@ -156,12 +179,25 @@ struct ParsedStream {
   double step = 0.0, offset = 0.0;
   size_t flag_bytes = 0;
   std::vector<uint8_t> payload;
+  // symbols: decoded on the host, or (Huffman left to the device) empty
   std::vector<uint32_t> sym;
+  // Huffman section: the symbols in canonical order (length, then value)
+  // with their code lengths, the bitstream and its chunk index, both at
+  // byte offsets of payload
+  bool huff = false;
+  std::vector<uint32_t> canon_sym;
+  std::vector<uint8_t> canon_len;
+  uint64_t nbits = 0;
+  uint32_t chunk = 0;
+  size_t nchunks = 0, index_at = 0, bits_at = 0;
 };
+// huffman_on_host: decode the Huffman bitstream here (else only its tables
+// and chunk index are parsed, for the device decoder)
 pcc_status parse_stream(const uint8_t *stream, size_t len, int64_t n, ParsedStream &out,
-                        std::string &err);
-// applies a parsed stream to a device reconstruction (decode.hip)
-void apply_edits_device(const ParsedStream &ps, const float *const rin[3], float *const rout[3],
+                        std::string &err, bool huffman_on_host);
+// applies a parsed stream to a device reconstruction (decode.hip), the
+// Huffman bitstream decoded on the device; false when it is corrupt
+bool apply_edits_device(const ParsedStream &ps, const float *const rin[3], float *const rout[3],
                         Arena &ar, hipStream_t s);
 pcc_status decode_stream(const uint8_t *stream, size_t len, int64_t n, const float *rx,
                          const float *ry, const float *rz, float *ox, float *oy, float *oz,

@@ -37,7 +37,7 @@ void build_cells(const uint32_t *keys, size_t n, uint32_t *cell_of, uint32_t *ce
                  uint32_t *cell_key, uint32_t *n_cells, Arena &ar, hipStream_t s);
 void launch_neighbors(const JobDev *jobs, const uint32_t *cell_base, int njobs,
                       const uint32_t *cell_key, const uint32_t *n_cells, size_t max_cells,
-                      int32_t *nbr, hipStream_t s);
+                      int32_t *nbr, uint8_t *edge, hipStream_t s);
 
 // pairs.hip
 struct PairBufs {
@@ -48,6 +48,7 @@ struct PairBufs {
   const float4 *pos, *rec;
   const uint32_t *cell_of, *cell_start;
   const int32_t *nbr;
+  const uint8_t *cell_edge;              // periodic edges of each cell (image shifts)
   uint32_t *safe_par, *fof_par;          // union-find parents (sorted space)
   uint32_t *cnt_pb, *cnt_pc;             // pass 1: pb and pc pairs of each home particle
   uint32_t *cnt_a, *cnt_f;               // pass 2: active and forest pairs (exact path);

@@ -115,8 +115,9 @@ struct JobPair {
   double rs2, b2, rv2, bm2;
   double L[3], hL[3];
   float Lf[3], hLf[3];
-  float rv2f;
+  float f_rs_lo, f_rs_hi, f_b_lo, f_b_hi, f_rv_lo, f_rv_hi;
   int mode;
+  int img;
 };
 
 __device__ inline JobPair load_job(const JobDev &J) {
@@ -132,8 +133,14 @@ __device__ inline JobPair load_job(const JobDev &J) {
     q.Lf[a] = J.Lf[a];
     q.hLf[a] = J.hLf[a];
   }
-  q.rv2f = J.rv2_f32;
+  q.f_rs_lo = J.f_rs_lo;
+  q.f_rs_hi = J.f_rs_hi;
+  q.f_b_lo = J.f_b_lo;
+  q.f_b_hi = J.f_b_hi;
+  q.f_rv_lo = J.f_rv_lo;
+  q.f_rv_hi = J.rv2_f32;
   q.mode = J.mode;
+  q.img = J.img;
   return q;
 }
 
@@ -160,6 +167,63 @@ __device__ inline double dist2_exact(const float4 &a, const float4 &b, const Job
   return (dx * dx + dy * dy) + dz * dz;
 }
 
+// Offset (dx, dy, dz) of forward neighbour cell s = 0 .. 12, in the order of
+// the neighbour table: (1,0,0), then (-1..1, 1, 0), then (-1..1, -1..1, 1).
+__device__ inline void fwd_offset(int s, int &dx, int &dy, int &dz) {
+  if (s == 0) {
+    dx = 1;
+    dy = 0;
+    dz = 0;
+  } else if (s < 4) {
+    dx = s - 2;
+    dy = 1;
+    dz = 0;
+  } else {
+    const int t = s - 4;
+    dx = t % 3 - 1;
+    dy = t / 3 - 1;
+    dz = 1;
+  }
+}
+__device__ inline float axis_shift(int d, uint32_t edge, int a, float L) {
+  if (d > 0 && ((edge >> (2 * a + 1)) & 1u)) return L;  // home on the high edge
+  if (d < 0 && ((edge >> (2 * a)) & 1u)) return -L;     // home on the low edge
+  return 0.f;
+}
+// Periodic image of forward neighbour s of a cell with edge bits `edge`: a
+// partner's displacement is (home - partner) - shift on every axis.  Zero
+// unless the job's coordinates lie in its periodic box (the edge bits are
+// then clear and each candidate is wrapped instead).
+__device__ inline float3 image_shift(int s, uint32_t edge, const JobPair &q) {
+  int dx, dy, dz;
+  fwd_offset(s, dx, dy, dz);
+  return make_float3(axis_shift(dx, edge, 0, q.Lf[0]), axis_shift(dy, edge, 1, q.Lf[1]),
+                     axis_shift(dz, edge, 2, q.Lf[2]));
+}
+
+// Class of a candidate pair: a float32 squared distance decides whenever it
+// lies outside the guard band of every threshold; inside a band, the exact
+// float64 squared distance of the oracle decides.
+__device__ inline int classify(const JobPair &q, const float4 &pi, const float4 &pj,
+                               const float3 &sh) {
+  float dx = (pi.x - pj.x) - sh.x;
+  float dy = (pi.y - pj.y) - sh.y;
+  float dz = (pi.z - pj.z) - sh.z;
+  if (!q.img) {
+    dx = wrap_f(dx, q.Lf[0], q.hLf[0]);
+    dy = wrap_f(dy, q.Lf[1], q.hLf[1]);
+    dz = wrap_f(dz, q.Lf[2], q.hLf[2]);
+  }
+  const float d2f = (dx * dx + dy * dy) + dz * dz;
+  if (d2f > q.f_rv_hi) return kNone;
+  if (d2f < q.f_rs_lo) return kSafe;
+  if (d2f > q.f_rs_hi && d2f < q.f_b_lo) return kPb;
+  if (d2f > q.f_b_hi && d2f < q.f_rv_lo) return kPc;
+  const double d2 = dist2_exact(pi, pj, q);
+  if (d2 > q.rv2) return kNone;
+  return d2 <= q.rs2 ? kSafe : (d2 <= q.b2 ? kPb : kPc);
+}
+
 // State of one home particle k during a pass.
 struct Home {
   uint32_t k;
@@ -167,6 +231,7 @@ struct Home {
   uint32_t sk, fk;     // safe and FoF roots (passes 2 and 3); root guesses (pass 1)
   uint64_t wa, wf;     // write cursors (pass 3)
   uint32_t ca, cf;     // counts: pass 1 pc and pb pairs, pass 2 active and forest pairs
+  uint32_t cs;         // pass 1: safe pairs
 };
 
 template <int PASS>
@@ -182,7 +247,7 @@ __device__ inline void home_begin(const PairBufs &B, Home &h, uint32_t k) {
   if (PASS == 3) h.ri = B.rec[k];
   h.wa = PASS == 3 ? B.off_a[k] : 0;
   h.wf = PASS == 3 ? B.off_f[k] : 0;
-  h.ca = h.cf = 0;
+  h.ca = h.cf = h.cs = 0;
 }
 
 template <int PASS>
@@ -209,204 +274,21 @@ __device__ inline void home_end(const PairBufs &B, const Home &h) {
   }
 }
 
-// One candidate partner j of the home particle: float32 prefilter, exact
-// float64 class, then the work of the pass.
-template <int PASS>
-__device__ inline void visit(const PairBufs &B, const JobPair &q, Home &h, uint32_t j,
-                             const float4 &pj, unsigned long long (&cnt)[3]) {
-  const float dx = wrap_f(h.pi.x - pj.x, q.Lf[0], q.hLf[0]);
-  const float dy = wrap_f(h.pi.y - pj.y, q.Lf[1], q.hLf[1]);
-  const float dz = wrap_f(h.pi.z - pj.z, q.Lf[2], q.hLf[2]);
-  const float d2f = (dx * dx + dy * dy) + dz * dz;
-  if (d2f > q.rv2f) return;
-  const double d2 = dist2_exact(h.pi, pj, q);
-  if (d2 > q.rv2) return;
-  const int cls = d2 <= q.rs2 ? kSafe : (d2 <= q.b2 ? kPb : kPc);
-  if (PASS == 1) {
-    // h.sk / h.fk hold an ancestor of k in each forest: a partner whose
-    // parent is that node is already in k's set and needs no union
-    if (cls == kSafe) {
-      cnt[0]++;
-      if (B.safe_par[j] != h.sk) h.sk = uf_union(B.safe_par, h.sk, j);
-      if (B.fof_par[j] != h.fk) h.fk = uf_union(B.fof_par, h.fk, j);
-    } else if (cls == kPb) {
-      cnt[1]++;
-      h.cf++;
-      if (B.fof_par[j] != h.fk) h.fk = uf_union(B.fof_par, h.fk, j);
-    } else {
-      cnt[2]++;
-      h.ca++;
-    }
-    return;
-  }
-  if (cls == kSafe) return;
-  bool to_a = false, to_f = false;
-  if (q.mode == 0) {
-    to_a = true;
-  } else if (q.mode == 1) {
-    to_a = B.safe_par[j] != h.sk;
-  } else if (cls == kPc) {
-    to_a = B.fof_par[j] != h.fk;
-  } else {
-    to_f = B.safe_par[j] != h.sk;
-  }
-  if (PASS == 2) {
-    h.ca += to_a;
-    h.cf += to_f;
-    return;
-  }
-  if (to_a) {
-    B.a_i[h.wa] = h.k;
-    B.a_j[h.wa] = j;
-    B.a_t[h.wa] = (uint8_t)cls;
-    h.wa++;
-  }
-  if (to_f) {
-    const float4 rj = B.rec[j];
-    const double ex = wrap_d((double)h.ri.x - (double)rj.x, q.L[0], q.hL[0]);
-    const double ey = wrap_d((double)h.ri.y - (double)rj.y, q.L[1], q.hL[1]);
-    const double ez = wrap_d((double)h.ri.z - (double)rj.z, q.L[2], q.hL[2]);
-    const uint64_t viol0 = ((ex * ex + ey * ey) + ez * ez) > q.bm2 ? 1ull : 0ull;
-    const uint32_t li = __float_as_uint(h.pi.w), lj = __float_as_uint(pj.w);
-    const uint64_t lo = li < lj ? li : lj, hi = li < lj ? lj : li;
-    B.f_key[h.wf] = (viol0 << 62) | (lo << 31) | hi;
-    B.f_u[h.wf] = h.sk;
-    B.f_v[h.wf] = B.safe_par[j];
-    h.wf++;
-  }
-}
-
-// Sparse cells: one thread per particle (list of particles of cells below
-// the dense-cell threshold, ordered by the candidate count of their cell).
-// Partners: later particles of its own cell, then every particle of
-// the 13 forward cells, in index order.  The walk over those ranges is one
-// flat loop, one candidate per lane per iteration, so a lane stays busy until
-// its own candidates run out (nested loops over the ranges would idle every
-// lane whose current range is shorter than the longest one in the wave); the
-// next candidate's position is loaded before the current one is examined.
-// moves (j, e) to the next non-empty candidate range when the current one is
-// exhausted; s counts the forward cells entered so far
-__device__ inline void next_range(const uint32_t *cs, const int32_t *nbr, uint32_t &j,
-                                  uint32_t &e, int &s) {
-  while (j >= e && s < 13) {
-    const int32_t nb = nbr[s++];
-    if (nb >= 0) {
-      j = cs[nb];
-      e = cs[nb + 1];
-    }
-  }
-}
-
-template <int PASS>
-__global__ void __launch_bounds__(256) k_pairs_sparse(PairBufs B, const uint32_t *list, size_t m) {
-  unsigned long long cnt[3] = {0ull, 0ull, 0ull};  // safe, pb, pc
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int cjob = t < m ? job_of(B.p_off, B.njobs, (int64_t)list[t]) : -1;
-  if (t < m) {
-    const uint32_t k = list[t];
-    const JobPair q = load_job(B.jobs[cjob]);
-    Home h;
-    home_begin<PASS>(B, h, k);
-    const uint32_t cell = B.cell_of[k];
-    const int32_t *nbr = B.nbr + (size_t)cell * 13;
-    const uint32_t *cs = B.cell_start;
-    // (j, e): the current range; s: forward cells entered so far
-    int s = 0;
-    uint32_t j = k + 1, e = cs[cell + 1];
-    next_range(cs, nbr, j, e, s);
-    float4 pj = B.pos[j < e ? j : k];  // (index k: any valid load)
-    while (j < e) {
-      uint32_t jn = j + 1, en = e;
-      int sn = s;
-      next_range(cs, nbr, jn, en, sn);
-      const float4 pn = B.pos[jn < en ? jn : k];
-      visit<PASS>(B, q, h, j, pj, cnt);
-      j = jn;
-      e = en;
-      s = sn;
-      pj = pn;
-    }
-    home_end<PASS>(B, h);
-  }
-  if (PASS == 1) job_add<3>(B.job_counts, B.count_slots, cjob, cjob >= 0, cnt);
-}
-
-constexpr int kPairWaves = 4;
-
-// Dense cells: one wave per 64 home particles of one cell.  Each partner
-// cell is staged through LDS 64 particles at a time with coalesced loads;
-// every lane then runs over the same staged particles (broadcast reads), so
-// the lanes of a wave never diverge on trip counts.  Every home particle
-// sees its partners in the same order as in the sparse kernel.
-template <int PASS>
-__global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense(PairBufs B, const uint32_t *ucell,
-                                                                 const uint32_t *uchunk, size_t m) {
-  __shared__ float4 stage[kPairWaves][64];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const size_t unit = (size_t)blockIdx.x * kPairWaves + w;
-  if (unit >= m) return;  // the whole wave leaves together
-  const uint32_t cell = ucell[unit];
-  const uint32_t cs = B.cell_start[cell], ce = B.cell_start[cell + 1];
-  const uint32_t k0 = cs + 64u * uchunk[unit];
-  const uint32_t nh = (ce - k0) < 64u ? (ce - k0) : 64u;
-  const bool valid = (uint32_t)lane < nh;
-  const int job = __builtin_amdgcn_readfirstlane(job_of(B.p_off, B.njobs, (int64_t)k0));
-  const JobPair q = load_job(B.jobs[job]);
-  unsigned long long cnt[3] = {0ull, 0ull, 0ull};
-  Home h;
-  home_begin<PASS>(B, h, valid ? k0 + lane : k0);
-  for (int s = 0; s < 14; ++s) {
-    uint32_t j0, j1;
-    if (s == 0) {
-      j0 = k0 + 1;  // later particles of the home cell
-      j1 = ce;
-    } else {
-      const int32_t nb = B.nbr[(size_t)cell * 13 + s - 1];
-      if (nb < 0) continue;
-      j0 = B.cell_start[nb];
-      j1 = B.cell_start[nb + 1];
-    }
-    for (uint32_t t0 = j0; t0 < j1; t0 += 64) {
-      const uint32_t cnt_t = (j1 - t0) < 64u ? (j1 - t0) : 64u;
-      if ((uint32_t)lane < cnt_t) stage[w][lane] = B.pos[t0 + lane];
-      wave_sync();
-      if (valid) {
-        for (uint32_t t = 0; t < cnt_t; ++t) {
-          const uint32_t j = t0 + t;
-          if (s == 0 && j <= h.k) continue;
-          visit<PASS>(B, q, h, j, stage[w][t], cnt);
-        }
-      }
-      wave_sync();
-    }
-  }
-  if (valid) home_end<PASS>(B, h);
-  if (PASS == 1) job_add<3>(B.job_counts, B.count_slots, job, valid, cnt);
-}
-
-// Mode filter of one partner j of a home particle in the write pass (the
-// exact class first): to_a for the active list, to_f for HF's forest
-// candidates.
-__device__ inline void write_filter(const PairBufs &B, const JobPair &q, const Home &h, uint32_t j,
-                                    const float4 &pj, int &cls, bool &to_a, bool &to_f) {
+// Mode filter of a vulnerable pair (Sec. 3.2): to_a for the active list,
+// to_f for the halo forest's candidates.  spj / fpj: the partner's safe and
+// FoF roots.
+__device__ inline void mode_filter(const JobPair &q, const Home &h, int cls, uint32_t spj,
+                                   uint32_t fpj, bool &to_a, bool &to_f) {
   to_a = to_f = false;
-  cls = kNone;
-  const float dx = wrap_f(h.pi.x - pj.x, q.Lf[0], q.hLf[0]);
-  const float dy = wrap_f(h.pi.y - pj.y, q.Lf[1], q.hLf[1]);
-  const float dz = wrap_f(h.pi.z - pj.z, q.Lf[2], q.hLf[2]);
-  if ((dx * dx + dy * dy) + dz * dz > q.rv2f) return;
-  const double d2 = dist2_exact(h.pi, pj, q);
-  if (d2 > q.rv2 || d2 <= q.rs2) return;
-  cls = d2 <= q.b2 ? kPb : kPc;
-  if (q.mode == 0) {
+  if (cls == kNone || cls == kSafe) return;
+  if (q.mode == 0)
     to_a = true;
-  } else if (q.mode == 1) {
-    to_a = B.safe_par[j] != h.sk;
-  } else if (cls == kPc) {
-    to_a = B.fof_par[j] != h.fk;
-  } else {
-    to_f = B.safe_par[j] != h.sk;
-  }
+  else if (q.mode == 1)
+    to_a = spj != h.sk;
+  else if (cls == kPc)
+    to_a = fpj != h.fk;
+  else
+    to_f = spj != h.sk;
 }
 
 // Forest key of a candidate: links already broken in the reconstruction
@@ -423,6 +305,193 @@ __device__ inline uint64_t forest_key(const PairBufs &B, const JobPair &q, const
   return (viol0 << 62) | (lo << 31) | hi;
 }
 
+// One candidate partner j of the home particle: its class, then the work of
+// the pass.  With STAGED the partner's parents come from the caller (staged
+// with its position), else they are read when needed.  In pass 1 a parent
+// only serves to skip a union that is already done: a node's parent only
+// ever moves to an ancestor, so a stale value equal to the home's root guess
+// still means both are in one set, and any other value leads to a union.
+template <int PASS, bool STAGED>
+__device__ inline void visit(const PairBufs &B, const JobPair &q, Home &h, uint32_t j,
+                             const float4 &pj, const float3 &sh, uint32_t sj, uint32_t fj) {
+  const int cls = classify(q, h.pi, pj, sh);
+  if (cls == kNone) return;
+  auto spar = [&]() { return STAGED ? sj : B.safe_par[j]; };
+  auto fpar = [&]() { return STAGED ? fj : B.fof_par[j]; };
+  if (PASS == 1) {
+    // h.sk / h.fk hold an ancestor of k in each forest: a partner whose
+    // parent is that node is already in k's set and needs no union
+    if (cls == kSafe) {
+      h.cs++;
+      if (spar() != h.sk) h.sk = uf_union(B.safe_par, h.sk, j);
+      if (fpar() != h.fk) h.fk = uf_union(B.fof_par, h.fk, j);
+    } else if (cls == kPb) {
+      h.cf++;
+      if (fpar() != h.fk) h.fk = uf_union(B.fof_par, h.fk, j);
+    } else {
+      h.ca++;
+    }
+    return;
+  }
+  if (cls == kSafe) return;
+  bool to_a, to_f;
+  const uint32_t spj = (q.mode == 0 || (q.mode == 2 && cls == kPc)) ? 0u : spar();
+  const uint32_t fpj = (q.mode == 2 && cls == kPc) ? fpar() : 0u;
+  mode_filter(q, h, cls, spj, fpj, to_a, to_f);
+  if (PASS == 2) {
+    h.ca += to_a;
+    h.cf += to_f;
+    return;
+  }
+  if (to_a) {
+    B.a_i[h.wa] = h.k;
+    B.a_j[h.wa] = j;
+    B.a_t[h.wa] = (uint8_t)cls;
+    h.wa++;
+  }
+  if (to_f) {
+    B.f_key[h.wf] = forest_key(B, q, h, j, pj);
+    B.f_u[h.wf] = h.sk;
+    B.f_v[h.wf] = spj;
+    h.wf++;
+  }
+}
+
+__device__ inline void pass1_counts(const Home &h, bool valid, unsigned long long (&cnt)[3]) {
+  cnt[0] = valid ? h.cs : 0u;
+  cnt[1] = valid ? h.cf : 0u;
+  cnt[2] = valid ? h.ca : 0u;
+}
+
+// Sparse cells: one thread per particle (list of particles of cells below
+// the dense-cell threshold, ordered by the candidate count of their cell).
+// Partners: later particles of its own cell, then every particle of
+// the 13 forward cells, in index order.  The walk over those ranges is one
+// flat loop, one candidate per lane per iteration, so a lane stays busy until
+// its own candidates run out (nested loops over the ranges would idle every
+// lane whose current range is shorter than the longest one in the wave); the
+// next candidate's position is loaded before the current one is examined.
+// moves (j, e) to the next non-empty candidate range when the current one is
+// exhausted; s counts the forward cells entered so far, sh is the periodic
+// image of the range's cell
+__device__ inline void next_range(const uint32_t *cs, const int32_t *nbr, uint32_t edge,
+                                  const JobPair &q, uint32_t &j, uint32_t &e, int &s,
+                                  float3 &sh) {
+  while (j >= e && s < 13) {
+    const int32_t nb = nbr[s];
+    if (nb >= 0) {
+      j = cs[nb];
+      e = cs[nb + 1];
+      sh = image_shift(s, edge, q);
+    }
+    ++s;
+  }
+}
+
+template <int PASS>
+__global__ void __launch_bounds__(256) k_pairs_sparse(PairBufs B, const uint32_t *list, size_t m) {
+  unsigned long long cnt[3] = {0ull, 0ull, 0ull};  // safe, pb, pc
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int cjob = t < m ? job_of(B.p_off, B.njobs, (int64_t)list[t]) : -1;
+  if (t < m) {
+    const uint32_t k = list[t];
+    const JobPair q = load_job(B.jobs[cjob]);
+    Home h;
+    home_begin<PASS>(B, h, k);
+    const uint32_t cell = B.cell_of[k];
+    const int32_t *nbr = B.nbr + (size_t)cell * 13;
+    const uint32_t *cs = B.cell_start;
+    const uint32_t edge = B.cell_edge[cell];
+    // (j, e): the current range; s: forward cells entered so far
+    int s = 0;
+    uint32_t j = k + 1, e = cs[cell + 1];
+    float3 sh = make_float3(0.f, 0.f, 0.f);
+    next_range(cs, nbr, edge, q, j, e, s, sh);
+    float4 pj = B.pos[j < e ? j : k];  // (index k: any valid load)
+    while (j < e) {
+      uint32_t jn = j + 1, en = e;
+      int sn = s;
+      float3 shn = sh;
+      next_range(cs, nbr, edge, q, jn, en, sn, shn);
+      const float4 pn = B.pos[jn < en ? jn : k];
+      visit<PASS, false>(B, q, h, j, pj, sh, 0u, 0u);
+      j = jn;
+      e = en;
+      s = sn;
+      sh = shn;
+      pj = pn;
+    }
+    home_end<PASS>(B, h);
+    if (PASS == 1) pass1_counts(h, true, cnt);
+  }
+  if (PASS == 1) job_add<3>(B.job_counts, B.count_slots, cjob, cjob >= 0, cnt);
+}
+
+constexpr int kPairWaves = 4;
+
+// Dense cells: one wave per 64 home particles of one cell.  Each partner
+// cell is staged through LDS 64 particles at a time with coalesced loads
+// (positions and both parents); every lane then runs over the same staged
+// particles (broadcast reads), so the lanes of a wave never diverge on trip
+// counts, and the periodic image of a partner cell is one shift for the
+// whole wave.  Every home particle sees its partners in the same order as in
+// the sparse kernel.
+template <int PASS>
+__global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense(PairBufs B, const uint32_t *ucell,
+                                                                 const uint32_t *uchunk, size_t m) {
+  __shared__ float4 stage[kPairWaves][64];
+  __shared__ uint32_t ssp[kPairWaves][64], sfp[kPairWaves][64];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const size_t unit = (size_t)blockIdx.x * kPairWaves + w;
+  if (unit >= m) return;  // the whole wave leaves together
+  const uint32_t cell = ucell[unit];
+  const uint32_t cs = B.cell_start[cell], ce = B.cell_start[cell + 1];
+  const uint32_t k0 = cs + 64u * uchunk[unit];
+  const uint32_t nh = (ce - k0) < 64u ? (ce - k0) : 64u;
+  const bool valid = (uint32_t)lane < nh;
+  const int job = __builtin_amdgcn_readfirstlane(job_of(B.p_off, B.njobs, (int64_t)k0));
+  const JobPair q = load_job(B.jobs[job]);
+  const uint32_t edge = B.cell_edge[cell];
+  Home h;
+  home_begin<PASS>(B, h, valid ? k0 + lane : k0);
+  for (int s = 0; s < 14; ++s) {
+    uint32_t j0, j1;
+    float3 sh = make_float3(0.f, 0.f, 0.f);
+    if (s == 0) {
+      j0 = k0 + 1;  // later particles of the home cell
+      j1 = ce;
+    } else {
+      const int32_t nb = B.nbr[(size_t)cell * 13 + s - 1];
+      if (nb < 0) continue;
+      j0 = B.cell_start[nb];
+      j1 = B.cell_start[nb + 1];
+      sh = image_shift(s - 1, edge, q);
+    }
+    for (uint32_t t0 = j0; t0 < j1; t0 += 64) {
+      const uint32_t cnt_t = (j1 - t0) < 64u ? (j1 - t0) : 64u;
+      if ((uint32_t)lane < cnt_t) {
+        stage[w][lane] = B.pos[t0 + lane];
+        ssp[w][lane] = B.safe_par[t0 + lane];
+        sfp[w][lane] = B.fof_par[t0 + lane];
+      }
+      wave_sync();
+      if (valid) {
+        // in the home cell only the partners after k
+        const uint32_t tb = (s == 0 && h.k >= t0) ? (h.k + 1 - t0) : 0u;
+        for (uint32_t t = tb; t < cnt_t; ++t)
+          visit<PASS, true>(B, q, h, t0 + t, stage[w][t], sh, ssp[w][t], sfp[w][t]);
+      }
+      wave_sync();
+    }
+  }
+  if (valid) home_end<PASS>(B, h);
+  if (PASS == 1) {
+    unsigned long long cnt[3];
+    pass1_counts(h, valid, cnt);
+    job_add<3>(B.job_counts, B.count_slots, job, valid, cnt);
+  }
+}
+
 // Write pass over dense cells.  The 64 home particles of a unit are
 // consecutive, so their slots form one block; the kept pairs are appended
 // to that block at a wave-wide cursor (ballot and prefix count), in the
@@ -434,6 +503,7 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense_write(PairBufs 
                                                                        const uint32_t *uchunk,
                                                                        size_t m) {
   __shared__ float4 stage[kPairWaves][64];
+  __shared__ uint32_t ssp[kPairWaves][64], sfp[kPairWaves][64];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const size_t unit = (size_t)blockIdx.x * kPairWaves + w;
   if (unit >= m) return;  // the whole wave leaves together
@@ -444,6 +514,7 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense_write(PairBufs 
   const bool valid = (uint32_t)lane < nh;
   const int job = __builtin_amdgcn_readfirstlane(job_of(B.p_off, B.njobs, (int64_t)k0));
   const JobPair q = load_job(B.jobs[job]);
+  const uint32_t edge = B.cell_edge[cell];
   Home h;
   home_begin<3>(B, h, valid ? k0 + lane : k0);
   const uint64_t a0 = B.off_a[k0], f0 = B.off_f[k0];
@@ -451,6 +522,7 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense_write(PairBufs 
   const uint64_t below = (1ull << lane) - 1ull;
   for (int s = 0; s < 14; ++s) {
     uint32_t j0, j1;
+    float3 sh = make_float3(0.f, 0.f, 0.f);
     if (s == 0) {
       j0 = k0 + 1;  // later particles of the home cell
       j1 = ce;
@@ -459,17 +531,25 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense_write(PairBufs 
       if (nb < 0) continue;
       j0 = B.cell_start[nb];
       j1 = B.cell_start[nb + 1];
+      sh = image_shift(s - 1, edge, q);
     }
     for (uint32_t t0 = j0; t0 < j1; t0 += 64) {
       const uint32_t cnt_t = (j1 - t0) < 64u ? (j1 - t0) : 64u;
-      if ((uint32_t)lane < cnt_t) stage[w][lane] = B.pos[t0 + lane];
+      if ((uint32_t)lane < cnt_t) {
+        stage[w][lane] = B.pos[t0 + lane];
+        ssp[w][lane] = B.safe_par[t0 + lane];
+        sfp[w][lane] = B.fof_par[t0 + lane];
+      }
       wave_sync();
       for (uint32_t t = 0; t < cnt_t; ++t) {
         const uint32_t j = t0 + t;
         const float4 pj = stage[w][t];
         int cls = kNone;
         bool ta = false, tf = false;
-        if (valid && !(s == 0 && j <= h.k)) write_filter(B, q, h, j, pj, cls, ta, tf);
+        if (valid && !(s == 0 && j <= h.k)) {
+          cls = classify(q, h.pi, pj, sh);
+          mode_filter(q, h, cls, ssp[w][t], sfp[w][t], ta, tf);
+        }
         const uint64_t ba = __ballot(ta), bf = __ballot(tf);
         if (ta) {
           const uint64_t d = wa + (uint64_t)__popcll(ba & below);
@@ -481,7 +561,7 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense_write(PairBufs 
           const uint64_t d = wf + (uint64_t)__popcll(bf & below);
           B.f_key[d] = forest_key(B, q, h, j, pj);
           B.f_u[d] = h.sk;
-          B.f_v[d] = B.safe_par[j];
+          B.f_v[d] = ssp[w][t];
         }
         wa += (uint64_t)__popcll(ba);
         wf += (uint64_t)__popcll(bf);

@@ -44,7 +44,15 @@ struct JobDev {
   int64_t n;            // particles
   // pair predicates, squared distances in float64 (Sec. 3.1, 3.2)
   double rs2, b2, rv2;  // rs2 < 0 when b - 2 sqrt(3) xi <= 0 (no safe links)
-  float rv2_f32;        // conservative float32 prefilter of d^2 <= rv2
+  // float32 classification bands of the three thresholds: a float32 d^2
+  // below *_lo (above *_hi) is below (above) the threshold in the exact
+  // float64 predicate; in between, the float64 predicate decides
+  float f_rs_lo, f_rs_hi, f_b_lo, f_b_hi, f_rv_lo;
+  float rv2_f32;        // f_rv_hi: conservative float32 prefilter of d^2 <= rv2
+  // every periodic coordinate of the originals lies in [0, L): a partner's
+  // periodic image is fixed per neighbour cell (cell edge bits), and no
+  // candidate needs the per-pair minimum-image wrap
+  int32_t img;
   int32_t mode;
   // periodic axes: side and half side (half = +inf on open axes)
   double L[3], hL[3];
@@ -140,6 +148,12 @@ class Arena {
     return c;
   }
   size_t high_water() const { return high_; }  // most bytes in use since reset()
+  bool fixed() const { return fixed_; }  // serving from a borrowed buffer
+  size_t spare() const {  // held bytes not yet handed out in this call
+    size_t c = 0;
+    for (const auto &k : chunks_) c += k.size - k.off;
+    return c;
+  }
 
  private:
   struct Chunk {

@@ -171,12 +171,35 @@ int job_constants(const pcc_params &p, const ScanPart &agg, int64_t n, int cell_
     }
   }
   ncell = cells;
-  // float32 prefilter: every pair with exact d <= r_v passes (see DESIGN)
+  // periodic images per neighbour cell when every periodic coordinate lies
+  // in [0, L)
+  J.img = 1;
+  for (int a = 0; a < 3; ++a)
+    if (((J.periodic >> a) & 1) && n > 0 &&
+        !((double)agg.mn[a] >= 0.0 && (double)agg.mx[a] < J.L[a]))
+      J.img = 0;
+  // float32 classification: e bounds the distance error of the float32
+  // displacement (two roundings per axis, the float32 side and any image
+  // shift included); the factors 1 -+ 2^-17 cover the float32 rounding of
+  // the squares and sums and the float64 rounding of the exact predicate
   const double e = 4.0 * ulp_f32((double)agg.maxabs + lmax + 1.0);
-  const double thr = (rv + e) * (rv + e) * (1.0 + std::ldexp(1.0, -18));
-  float f = (float)thr;
-  if ((double)f < thr) f = std::nextafter(f, std::numeric_limits<float>::infinity());
-  J.rv2_f32 = f;
+  const float finf = std::numeric_limits<float>::infinity();
+  auto band = [&](double T, float &lo, float &hi) {
+    if (T < 0.0) {  // no such class: every d^2 lies above
+      lo = hi = -1.0f;
+      return;
+    }
+    const double r = std::sqrt(T);
+    const double l = r > 2.0 * e ? (r - e) * (r - e) * (1.0 - std::ldexp(1.0, -17)) : -1.0;
+    const double h = (r + e) * (r + e) * (1.0 + std::ldexp(1.0, -17));
+    lo = (float)l;
+    if ((double)lo > l) lo = std::nextafter(lo, -finf);
+    hi = (float)h;
+    if ((double)hi < h) hi = std::nextafter(hi, finf);
+  };
+  band(J.rs2, J.f_rs_lo, J.f_rs_hi);
+  band(J.b2, J.f_b_lo, J.f_b_hi);
+  band(J.rv2, J.f_rv_lo, J.rv2_f32);
   return 0;
 }
 
@@ -630,7 +653,7 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
       size_t raw = 0;
       if (!labels_only) {
         assemble_stream(0, j.params.m_bits, 0, h->dev.qstep, h->dev.qoffset, nullptr, 0, nullptr,
-                        nullptr, 0, strm, &raw);
+                        nullptr, 0, nullptr, 0, strm, &raw);
         if (j.out.stream_len) *j.out.stream_len = strm.size();
         if (j.out.stream_cap >= strm.size() && j.out.stream)
           std::memcpy(j.out.stream, strm.data(), strm.size());
@@ -690,7 +713,8 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   uint32_t *cell_key = dev<uint32_t>(ar, n), *n_cells = dev<uint32_t>(ar, 1);
   build_cells(keys, n, cell_of, cell_start, cell_key, n_cells, ar, s);
   int32_t *nbr = dev<int32_t>(ar, n * 13);
-  launch_neighbors(d_jobs, d_cbase, J, cell_key, n_cells, n, nbr, s);
+  uint8_t *cell_edge = dev<uint8_t>(ar, n);
+  launch_neighbors(d_jobs, d_cbase, J, cell_key, n_cells, n, nbr, cell_edge, s);
   PairPlan plan;
   plan_pairs(plan, cell_of, cell_start, nbr, n_cells, n, (uint32_t)C.dense_cell, ar, s);
   mark(2, "cell build");
@@ -708,6 +732,7 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   pb.cell_of = cell_of;
   pb.cell_start = cell_start;
   pb.nbr = nbr;
+  pb.cell_edge = cell_edge;
   pb.safe_par = dev<uint32_t>(ar, n);
   pb.fof_par = dev<uint32_t>(ar, n);
   pb.cnt_pb = dev<uint32_t>(ar, n);
@@ -808,10 +833,14 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
       if (res[k].status < 0 && first == PCC_OK) first = res[k].status;
     return first;
   }
+  // the slotted path when its slots take at most half of the memory still
+  // available: free device memory plus what the workspace holds unused (a
+  // warm workspace keeps the previous call's memory)
   size_t free_b = 0, total_b = 0;
   PCC_HIP(hipMemGetInfo(&free_b, &total_b));
+  const double avail = (ar.fixed() ? 0.0 : (double)free_b) + (double)ar.spare();
   const double slot_bytes = 9.0 * (double)htot[0] * (all_vp ? 1.0 : 2.0) + 16.0 * (double)htot[1];
-  pb.slotted = slot_bytes <= 0.5 * (double)free_b && !C.force_exact_pairs;
+  pb.slotted = slot_bytes <= 0.5 * avail && !C.force_exact_pairs;
   size_t na_direct = 0, nf = 0;
   uint32_t *a_i = nullptr, *a_j = nullptr;
   uint8_t *a_t = nullptr;
@@ -1030,26 +1059,41 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
     // bracketed by two events outside the graph and its time is split evenly
     // over its K steps (a step launch and its finalize launch together):
     // event nodes inside the graph would serialise it and slow it down.
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    PCC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    try {
-      for (int k = 0; k < K; ++k) {
-        launch_pgd_step(d_grp, gb, s);
-        launch_pgd_finalize(d_grp, gb, s);
+    PgdGraphCache &G = C.pgd_graph;
+    PgdBufs key;
+    std::memset(&key, 0, sizeof key);
+    key = gb;
+    const bool reuse = G.exec && G.steps == K && G.groups == d_grp &&
+                       std::memcmp(&G.bufs, &key, sizeof key) == 0;
+    if (!reuse) {
+      G.clear();
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      PCC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      try {
+        for (int k = 0; k < K; ++k) {
+          launch_pgd_step(d_grp, gb, s);
+          launch_pgd_finalize(d_grp, gb, s);
+        }
+      } catch (...) {
+        // leave the stream out of capture mode before reporting the error
+        hipGraph_t partial = nullptr;
+        if (hipStreamEndCapture(s, &partial) == hipSuccess && partial) hipGraphDestroy(partial);
+        throw;
       }
-    } catch (...) {
-      // leave the stream out of capture mode before reporting the error
-      hipGraph_t partial = nullptr;
-      if (hipStreamEndCapture(s, &partial) == hipSuccess && partial) hipGraphDestroy(partial);
-      throw;
+      PCC_HIP(hipStreamEndCapture(s, &graph));
+      hipError_t ge = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (ge != hipSuccess) {
+        hipGraphDestroy(graph);
+        hip_fail(ge, "hipGraphInstantiate", __FILE__, __LINE__);
+      }
+      G.graph = graph;
+      G.exec = exec;
+      G.bufs = key;
+      G.groups = d_grp;
+      G.steps = K;
     }
-    PCC_HIP(hipStreamEndCapture(s, &graph));
-    hipError_t ge = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (ge != hipSuccess) {
-      hipGraphDestroy(graph);
-      hip_fail(ge, "hipGraphInstantiate", __FILE__, __LINE__);
-    }
+    hipGraphExec_t exec = G.exec;
     int32_t *h_act = (int32_t *)st.get(sizeof(int32_t));
     try {
       int at = -1;  // events of the last replay, when timed
@@ -1068,12 +1112,9 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
         kt.bracket_end(at, s);
       }
     } catch (...) {
-      hipGraphExecDestroy(exec);
-      hipGraphDestroy(graph);
+      G.clear();
       throw;
     }
-    hipGraphExecDestroy(exec);
-    hipGraphDestroy(graph);
   }
   std::vector<JobLoop> lp(J);
   st.fetch(lp.data(), gb.loop, J);
@@ -1176,6 +1217,27 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
       k_gather_u64<<<(J + 256) / 256, 256, 0, s>>>(bitpos, d_idx, J + 1, btot, nsym, d_jb);
       st.fetch(jb.data(), d_jb, J + 1);
     }
+    // chunk index of every job's bitstream: the job-local bit at which each
+    // run of kHuffChunk symbols starts
+    std::vector<size_t> cb_off(J + 1, 0);
+    for (int q = 0; q < J; ++q)
+      cb_off[q + 1] = cb_off[q] + (size_t)((so[q + 1] - so[q] + kHuffChunk - 1) / kHuffChunk);
+    std::vector<uint64_t> cbits(cb_off[J]);
+    if (cb_off[J]) {
+      std::vector<int64_t> cidx(cb_off[J]);
+      for (int q = 0; q < J; ++q)
+        for (size_t c = 0; c < cb_off[q + 1] - cb_off[q]; ++c)
+          cidx[cb_off[q] + c] = (int64_t)(so[q] + (uint64_t)c * kHuffChunk);
+      int64_t *d_cidx = dev<int64_t>(ar, cidx.size());
+      uint64_t *d_cb = dev<uint64_t>(ar, cidx.size());
+      PCC_HIP(hipMemcpyAsync(d_cidx, cidx.data(), cidx.size() * sizeof(int64_t),
+                             hipMemcpyHostToDevice, s));
+      const int m = (int)cidx.size();
+      k_gather_u64<<<(m + 255) / 256, 256, 0, s>>>(bitpos, d_cidx, m, 0, nsym, d_cb);
+      st.fetch(cbits.data(), d_cb, cbits.size());
+      for (int q = 0; q < J; ++q)
+        for (size_t c = cb_off[q]; c < cb_off[q + 1]; ++c) cbits[c] -= jb[q];
+    }
     std::vector<uint64_t> w0(J + 1, 0);
     for (int q = 0; q < J; ++q) w0[q + 1] = w0[q] + (jb[q + 1] - jb[q] + 31) / 32 + 1;
     uint64_t *d_jb0 = dev<uint64_t>(ar, J + 1), *d_w0 = dev<uint64_t>(ar, J + 1);
@@ -1223,7 +1285,7 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
       assemble_stream(h.n, j.params.m_bits, h.st.n_flagged, h.dev.qstep, h.dev.qoffset,
                       hflags.data() + fb[q], fb[q + 1] - fb[q],
                       h.st.n_flagged ? &ht[q] : nullptr, hwords.data() + w0[q], jb[q + 1] - jb[q],
-                      strm, &raw);
+                      cbits.data() + cb_off[q], cb_off[q + 1] - cb_off[q], strm, &raw);
       h.st.bytes_stream = (int64_t)strm.size();
       if (j.out.stream_len) *j.out.stream_len = strm.size();
       if (j.out.stream && j.out.stream_cap >= strm.size())

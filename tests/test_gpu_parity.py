@@ -120,6 +120,48 @@ def test_periodic_cosmology_parity(ctx, mode, k):
     _compare(ctx, w, mode, max_iters=k)
 
 
+def _threshold_pairs(layout, seed=5):
+    """Isolated pairs whose distances sit within a few float32 ulps of the
+    three class thresholds b - 2 sqrt(3) xi, b and b + 2 sqrt(3) xi (Sec. 3.1),
+    about half of them straddling a face of the periodic box.  layout:
+    'box' (periodic, coordinates in [0, L)), 'shifted' (periodic, coordinates
+    in [-L/2, L/2)) or 'open'."""
+    rng = np.random.default_rng(seed)
+    b, xi, L = 0.2, 0.02, 12.0
+    r3 = 2.0 * np.sqrt(3.0) * xi
+    thr = np.array([b - r3, b, b + r3])
+    g = np.arange(12) + 0.5
+    c = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    m = len(c)
+    if layout != "open":
+        c[c == 0.5] = 0.0  # the first layer on every axis sits on the box face
+    d = thr[np.arange(m) % 3] * (1.0 + rng.integers(-8, 9, m) * 2.0 ** -20)
+    u = rng.normal(size=(m, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    p = np.concatenate([c - 0.5 * d[:, None] * u, c + 0.5 * d[:, None] * u])
+    if layout != "open":
+        p = np.mod(p, L)
+        if layout == "shifted":
+            p -= 0.5 * L
+    p = p[rng.permutation(len(p))]
+    orig = np.ascontiguousarray(p.T.astype(np.float32))
+    if layout == "box":
+        orig[orig >= np.float32(L)] = 0.0
+    box = (0.0, 0.0, 0.0) if layout == "open" else (L, L, L)
+    return synth.Workload("thr_" + layout, orig, synth.grid_reconstruction(orig, xi), b, xi, box)
+
+
+@pytest.mark.parametrize("layout", ["box", "shifted", "open"])
+@pytest.mark.parametrize("mode", ["vp", "hf"])
+def test_pair_classes_at_the_thresholds(ctx, layout, mode):
+    """The float32 classification with guard bands (and the per-cell
+    periodic images inside the box) gives the oracle's classes for pairs at
+    the thresholds, inside and outside the box and on open axes."""
+    w = _threshold_pairs(layout)
+    ref, stream, st = _compare(ctx, w, mode)
+    assert ref.stats["n_pb"] > 0 and ref.stats["n_pc"] > 0 and ref.stats["n_safe"] > 0
+
+
 @pytest.mark.parametrize("m", [8, 32])
 def test_bit_depths(ctx, m):
     import paper_2604_18801_amd as pcc

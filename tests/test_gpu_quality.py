@@ -4,6 +4,7 @@ import pytest
 
 import oracle
 import synth
+from stream_cases import huffman_stream
 
 pytestmark = pytest.mark.gpu
 
@@ -38,6 +39,35 @@ def test_device_decoder_of_oracle_stream(ctx):
     ref = oracle.correct(w.orig, w.recon, w.b, w.xi, mode="hf")
     x_dev = ctx.decode_device(ref.stream, _dev(w.recon)).cpu().numpy()
     np.testing.assert_array_equal(x_dev, oracle.decode(ref.stream, w.recon))
+
+
+def test_device_decoder_on_hand_assembled_huffman_stream(ctx):
+    """Two chunks (4 symbols, then 2) decoded by their own threads from the
+    chunk starts, codes of 1 to 3 bits."""
+    import paper_2604_18801_amd as pcc
+    rec = np.array([[1.0, 2.0, 3.0, 4.0], [0.5] * 4, [-1.0] * 4], dtype=np.float32)
+    stream, step, offset, codes = huffman_stream([0, 9])
+    x = ctx.decode_device(stream, _dev(rec)).cpu().numpy()
+    expect = rec.copy()
+    for a in range(3):
+        for k, pid in enumerate((0, 3)):
+            expect[a, pid] = np.float32(float(rec[a, pid]) + codes[a][k] * step - offset)
+    np.testing.assert_array_equal(x, expect)
+    np.testing.assert_array_equal(pcc.decode(stream, rec), expect)
+
+
+@pytest.mark.parametrize("starts,lengths", [([0, 8], (1, 2, 3, 3)), ([0, 10], (1, 2, 3, 3)),
+                                            ([0, 12], (1, 2, 3, 3)), ([0, 9], (1, 1, 3, 3))])
+def test_decoders_reject_corrupt_huffman_data(ctx, starts, lengths):
+    """A chunk start that the codes do not reach, one past the bitstream, or
+    code lengths that no prefix code has."""
+    import paper_2604_18801_amd as pcc
+    rec = np.zeros((3, 4), np.float32)
+    stream, *_ = huffman_stream(starts, lengths)
+    with pytest.raises(pcc.PccError):
+        ctx.decode_device(stream, _dev(rec))
+    with pytest.raises(pcc.PccError):
+        pcc.decode(stream, rec)
 
 
 def test_quality_study_rows(ctx):

@@ -114,3 +114,6 @@ def test_large_stream_decodes_with_both_decoders(ctx):
     x2 = oracle.decode(stream, w.recon)
     np.testing.assert_array_equal(x1, x2)
     assert np.abs(x1.astype(np.float64) - w.orig).max() <= w.xi
+    # the device decoder: one thread per chunk of the Huffman bitstream
+    x3 = ctx.decode_device(stream, _dev(w.recon)).cpu().numpy()
+    np.testing.assert_array_equal(x3, x1)

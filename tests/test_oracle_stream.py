@@ -13,6 +13,7 @@ from scipy.spatial import cKDTree
 import oracle
 import bruteforce as bf
 import synth
+from stream_cases import huffman_stream
 
 
 def _fof(pos, b, box):
@@ -42,7 +43,7 @@ def test_decoder_on_hand_assembled_stream():
     codes = {0: [0, 255], 1: [128, 127], 2: [200, 1]}  # per axis, per flagged particle
     sym = bytes(codes[0] + codes[1] + codes[2])
     payload = flags + sym
-    hdr = struct.pack("<IHBBQQddQQII", 0x45434350, 1, m, 0, n, 2, step, offset,
+    hdr = struct.pack("<IHBBQQddQQII", 0x45434350, 2, m, 0, n, 2, step, offset,
                       len(payload), len(payload), 8, 0)
     out = oracle.decode(hdr + payload, rec)
     expect = rec.copy()
@@ -50,6 +51,24 @@ def test_decoder_on_hand_assembled_stream():
         for k, pid in enumerate((1, 4)):
             expect[a, pid] = np.float32(float(rec[a, pid]) + codes[a][k] * step - offset)
     np.testing.assert_array_equal(out, expect)
+
+
+def test_decoder_on_hand_assembled_huffman_stream():
+    rec = np.array([[1.0, 2.0, 3.0, 4.0], [0.5] * 4, [-1.0] * 4], dtype=np.float32)
+    stream, step, offset, codes = huffman_stream([0, 9])
+    out = oracle.decode(stream, rec)
+    expect = rec.copy()
+    for a in range(3):
+        for k, pid in enumerate((0, 3)):
+            expect[a, pid] = np.float32(float(rec[a, pid]) + codes[a][k] * step - offset)
+    np.testing.assert_array_equal(out, expect)
+
+
+def test_decoder_rejects_a_wrong_chunk_start():
+    rec = np.zeros((3, 4), np.float32)
+    stream, *_ = huffman_stream([0, 8])
+    with pytest.raises(ValueError):
+        oracle.decode(stream, rec)
 
 
 @pytest.mark.parametrize("m", [8, 16, 32])
