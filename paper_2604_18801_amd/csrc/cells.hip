@@ -200,9 +200,30 @@ __constant__ int8_t kFwd[13][3] = {{1, 0, 0},  {-1, 1, 0}, {0, 1, 0},  {1, 1, 0}
 // when the cell is the first along periodic axis a, bit 2a + 1 when it is
 // the last (only for jobs whose coordinates lie in their periodic box, where
 // a neighbour cell across an edge stands for one periodic image).
+// blk[b] = first cell whose key is at least b << shift (a coarse index of
+// the sorted keys: a neighbour's search then covers the few cells of one
+// block instead of all of them)
+__global__ void k_key_blocks(const uint32_t *cell_key, const uint32_t *n_cells, size_t nblk,
+                             int shift, uint32_t *blk) {
+  const uint32_t U = *n_cells;
+  for (size_t b = (size_t)blockIdx.x * blockDim.x + threadIdx.x; b <= nblk;
+       b += (size_t)gridDim.x * blockDim.x) {
+    const uint64_t want = (uint64_t)b << shift;
+    uint32_t a = 0, c = U;
+    while (a < c) {
+      const uint32_t m = (a + c) >> 1;
+      if ((uint64_t)cell_key[m] < want)
+        a = m + 1;
+      else
+        c = m;
+    }
+    blk[b] = a;
+  }
+}
+
 __global__ void k_neighbors(const JobDev *jobs, const uint32_t *cell_base, int njobs,
-                            const uint32_t *cell_key, const uint32_t *n_cells, int32_t *nbr,
-                            uint8_t *edge) {
+                            const uint32_t *cell_key, const uint32_t *n_cells,
+                            const uint32_t *blk, int shift, int32_t *nbr, uint8_t *edge) {
   const uint32_t U = *n_cells;
   const size_t total = (size_t)U * 13;
   for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
@@ -250,7 +271,7 @@ __global__ void k_neighbors(const JobDev *jobs, const uint32_t *cell_base, int n
     int32_t found = -1;
     if (ok) {
       const uint32_t want = J.cell_base + (uint32_t)((q[2] * J.nc[1] + q[1]) * J.nc[0] + q[0]);
-      uint32_t a = 0, b = U;
+      uint32_t a = blk[want >> shift], b = blk[(want >> shift) + 1];
       while (a < b) {
         uint32_t m = (a + b) >> 1;
         if (cell_key[m] < want)
@@ -266,10 +287,17 @@ __global__ void k_neighbors(const JobDev *jobs, const uint32_t *cell_base, int n
 
 void launch_neighbors(const JobDev *jobs, const uint32_t *cell_base, int njobs,
                       const uint32_t *cell_key, const uint32_t *n_cells, size_t max_cells,
-                      int32_t *nbr, uint8_t *edge, hipStream_t s) {
-  if (max_cells)
-    k_neighbors<<<blocks_for(max_cells * 13, 256, 65536), 256, 0, s>>>(jobs, cell_base, njobs,
-                                                                       cell_key, n_cells, nbr, edge);
+                      uint64_t key_space, int32_t *nbr, uint8_t *edge, Arena &ar,
+                      hipStream_t s) {
+  if (!max_cells) return;
+  // about four keys' blocks per particle at most
+  int shift = 0;
+  while ((key_space >> shift) > max_cells / 4 + 1) ++shift;
+  const size_t nblk = (size_t)(key_space >> shift) + 1;
+  uint32_t *blk = ar.get<uint32_t>(nblk + 1);
+  k_key_blocks<<<blocks_for(nblk + 1, 256, 65536), 256, 0, s>>>(cell_key, n_cells, nblk, shift, blk);
+  k_neighbors<<<blocks_for(max_cells * 13, 256, 65536), 256, 0, s>>>(
+      jobs, cell_base, njobs, cell_key, n_cells, blk, shift, nbr, edge);
 }
 
 }  // namespace pcc

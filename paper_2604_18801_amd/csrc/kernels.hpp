@@ -35,9 +35,10 @@ void launch_gather(const uint32_t *perm, const int64_t *p_off, int njobs,
 // unique cells of the sorted keys; returns device counter of unique cells
 void build_cells(const uint32_t *keys, size_t n, uint32_t *cell_of, uint32_t *cell_start,
                  uint32_t *cell_key, uint32_t *n_cells, Arena &ar, hipStream_t s);
+// key_space: one more than the largest cell key of any job
 void launch_neighbors(const JobDev *jobs, const uint32_t *cell_base, int njobs,
                       const uint32_t *cell_key, const uint32_t *n_cells, size_t max_cells,
-                      int32_t *nbr, uint8_t *edge, hipStream_t s);
+                      uint64_t key_space, int32_t *nbr, uint8_t *edge, Arena &ar, hipStream_t s);
 
 // pairs.hip
 struct PairBufs {

@@ -366,32 +366,29 @@ __device__ inline void pass1_counts(const Home &h, bool valid, unsigned long lon
 // Sparse cells: one thread per particle (list of particles of cells below
 // the dense-cell threshold, ordered by the candidate count of their cell).
 // Partners: later particles of its own cell, then every particle of
-// the 13 forward cells, in index order.  The walk over those ranges is one
-// flat loop, one candidate per lane per iteration, so a lane stays busy until
-// its own candidates run out (nested loops over the ranges would idle every
-// lane whose current range is shorter than the longest one in the wave); the
-// next candidate's position is loaded before the current one is examined.
-// moves (j, e) to the next non-empty candidate range when the current one is
-// exhausted; s counts the forward cells entered so far, sh is the periodic
-// image of the range's cell
-__device__ inline void next_range(const uint32_t *cs, const int32_t *nbr, uint32_t edge,
-                                  const JobPair &q, uint32_t &j, uint32_t &e, int &s,
-                                  float3 &sh) {
-  while (j >= e && s < 13) {
-    const int32_t nb = nbr[s];
-    if (nb >= 0) {
-      j = cs[nb];
-      e = cs[nb + 1];
-      sh = image_shift(s, edge, q);
-    }
-    ++s;
-  }
-}
+// the 13 forward cells, in index order.  The ranges are found first, all at
+// once (the 13 neighbour entries, then the 26 cell bounds, each batch of
+// loads in flight together), and kept in LDS; the walk over them is one
+// flat loop, one candidate per lane per iteration, so a lane stays busy
+// until its own candidates run out (nested loops over the ranges would idle
+// every lane whose current range is shorter than the longest one in the
+// wave); the next candidate's position is loaded before the current one is
+// examined.
+constexpr int kSparseThreads = 256;
+constexpr int kRanges = 14;      // the home cell and 13 forward cells
+constexpr uint8_t kHomeRange = 13;  // range tag of the home cell (no image shift)
 
 template <int PASS>
-__global__ void __launch_bounds__(256) k_pairs_sparse(PairBufs B, const uint32_t *list, size_t m) {
+__global__ void __launch_bounds__(kSparseThreads) k_pairs_sparse(PairBufs B, const uint32_t *list,
+                                                                 size_t m) {
+  // candidate ranges of each thread: [lo, hi) and the forward index of its
+  // cell (kHomeRange for the home cell); [range][thread], so a wave's
+  // accesses to one range fall in distinct banks
+  __shared__ uint32_t r_lo[kRanges][kSparseThreads], r_hi[kRanges][kSparseThreads];
+  __shared__ uint8_t r_s[kRanges][kSparseThreads];
   unsigned long long cnt[3] = {0ull, 0ull, 0ull};  // safe, pb, pc
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int tid = threadIdx.x;
+  const size_t t = (size_t)blockIdx.x * blockDim.x + tid;
   const int cjob = t < m ? job_of(B.p_off, B.njobs, (int64_t)list[t]) : -1;
   if (t < m) {
     const uint32_t k = list[t];
@@ -402,22 +399,52 @@ __global__ void __launch_bounds__(256) k_pairs_sparse(PairBufs B, const uint32_t
     const int32_t *nbr = B.nbr + (size_t)cell * 13;
     const uint32_t *cs = B.cell_start;
     const uint32_t edge = B.cell_edge[cell];
-    // (j, e): the current range; s: forward cells entered so far
-    int s = 0;
-    uint32_t j = k + 1, e = cs[cell + 1];
+    // range 0: the later particles of the home cell; range s + 1: forward
+    // cell s (empty when the cell holds no particle); the loads of a batch
+    // are all in flight before the first is used
+    r_lo[0][tid] = k + 1;
+    r_hi[0][tid] = cs[cell + 1];
+    r_s[0][tid] = kHomeRange;
+    for (int s0 = 0; s0 < 13; s0 += 7) {
+      const int ns = s0 + 7 < 13 ? 7 : 13 - s0;
+      int32_t nb[7];
+#pragma unroll
+      for (int i = 0; i < 7; ++i)
+        if (i < ns) nb[i] = nbr[s0 + i];
+#pragma unroll
+      for (int i = 0; i < 7; ++i)
+        if (i < ns) {
+          const uint32_t c = nb[i] >= 0 ? (uint32_t)nb[i] : 0u;
+          const uint32_t a = cs[c], b = cs[c + 1];
+          r_lo[s0 + i + 1][tid] = a;
+          r_hi[s0 + i + 1][tid] = nb[i] >= 0 ? b : a;
+          r_s[s0 + i + 1][tid] = (uint8_t)(s0 + i);
+        }
+    }
+    const int nr = kRanges;
+    auto enter = [&](int r, uint32_t &j, uint32_t &e, float3 &sh) {
+      j = r_lo[r][tid];
+      e = r_hi[r][tid];
+      const int s = r_s[r][tid];
+      sh = s == kHomeRange ? make_float3(0.f, 0.f, 0.f) : image_shift(s, edge, q);
+    };
+    // (j, e): the current range r; empty ranges are passed over
+    int r = 0;
+    uint32_t j = 0, e = 0;
     float3 sh = make_float3(0.f, 0.f, 0.f);
-    next_range(cs, nbr, edge, q, j, e, s, sh);
-    float4 pj = B.pos[j < e ? j : k];  // (index k: any valid load)
-    while (j < e) {
+    enter(0, j, e, sh);
+    while (j >= e && ++r < nr) enter(r, j, e, sh);
+    float4 pj = B.pos[r < nr ? j : k];  // (index k: any valid load)
+    while (r < nr) {
       uint32_t jn = j + 1, en = e;
-      int sn = s;
+      int rn = r;
       float3 shn = sh;
-      next_range(cs, nbr, edge, q, jn, en, sn, shn);
-      const float4 pn = B.pos[jn < en ? jn : k];
+      while (jn >= en && ++rn < nr) enter(rn, jn, en, shn);
+      const float4 pn = B.pos[rn < nr ? jn : k];
       visit<PASS, false>(B, q, h, j, pj, sh, 0u, 0u);
       j = jn;
       e = en;
-      s = sn;
+      r = rn;
       sh = shn;
       pj = pn;
     }
@@ -681,8 +708,8 @@ void plan_pairs(PairPlan &pl, const uint32_t *cell_of, const uint32_t *cell_star
 template <int PASS>
 static void launch_pairs(const PairBufs &b, const PairPlan &pl, hipStream_t s) {
   if (pl.n_sparse)
-    k_pairs_sparse<PASS><<<blocks_for(pl.n_sparse, 256, 1 << 30), 256, 0, s>>>(b, pl.sparse,
-                                                                                pl.n_sparse);
+    k_pairs_sparse<PASS><<<blocks_for(pl.n_sparse, kSparseThreads, 1 << 30), kSparseThreads, 0,
+                           s>>>(b, pl.sparse, pl.n_sparse);
   if (pl.n_units) {
     const unsigned nb = (unsigned)((pl.n_units + kPairWaves - 1) / kPairWaves);
     if (PASS == 3)

@@ -714,7 +714,7 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   build_cells(keys, n, cell_of, cell_start, cell_key, n_cells, ar, s);
   int32_t *nbr = dev<int32_t>(ar, n * 13);
   uint8_t *cell_edge = dev<uint8_t>(ar, n);
-  launch_neighbors(d_jobs, d_cbase, J, cell_key, n_cells, n, nbr, cell_edge, s);
+  launch_neighbors(d_jobs, d_cbase, J, cell_key, n_cells, n, cell_total, nbr, cell_edge, ar, s);
   PairPlan plan;
   plan_pairs(plan, cell_of, cell_start, nbr, n_cells, n, (uint32_t)C.dense_cell, ar, s);
   mark(2, "cell build");

@@ -256,32 +256,40 @@ k_sort_hist(const uint32_t *keys, size_t n, int shift, uint32_t mask, uint32_t *
 // Items of a tile are taken in index order (round i, then thread); within a
 // round the rank of a key among equal digits is its lane rank inside its
 // wave (ballot match) plus the counts of earlier waves, plus the counts of
-// earlier rounds: a stable order.
+// earlier rounds: a stable order.  The tile is then reordered by digit in
+// LDS and written out in that order, so the items of one digit (a run of
+// consecutive output positions) leave in consecutive lanes: whole cache
+// lines instead of one scattered word per digit and round.
 __global__ void __launch_bounds__(kSortThreads)
 k_sort_scatter(const uint32_t *keys, const uint32_t *vals, uint32_t *okeys, uint32_t *ovals,
                size_t n, int shift, int nbits, const uint32_t *offsets, size_t nblocks) {
   __shared__ uint32_t base_off[kRadix];
   __shared__ uint32_t run[kRadix];
+  __shared__ uint32_t tstart[kRadix];
   __shared__ uint32_t wcnt[kSortThreads / kWave][kRadix];
+  __shared__ uint32_t scan_lds[kSortThreads / kWave];
+  __shared__ uint32_t lk[kSortTile], lv[kSortTile];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const uint32_t mask = (1u << nbits) - 1u;
   base_off[t] = offsets[(size_t)t * nblocks + blockIdx.x];
   run[t] = 0;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const size_t base = (size_t)blockIdx.x * kSortTile;
-#pragma unroll 1
+  const uint32_t tile_n = (uint32_t)(n - base < kSortTile ? n - base : kSortTile);
+  uint32_t key[kSortItems], val[kSortItems], rk[kSortItems];
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const size_t idx = base + (size_t)i * kSortThreads + t;
+    key[i] = idx < n ? keys[idx] : 0u;
+    val[i] = idx < n ? vals[idx] : 0u;
+  }
+#pragma unroll
   for (int i = 0; i < kSortItems; ++i) {
 #pragma unroll
     for (int k = 0; k < kSortThreads / kWave; ++k) wcnt[k][t] = 0;
     __syncthreads();
-    const size_t idx = base + (size_t)i * kSortThreads + t;
-    const bool valid = idx < n;
-    uint32_t key = 0, val = 0, d = 0;
-    if (valid) {
-      key = keys[idx];
-      val = vals[idx];
-      d = (key >> shift) & mask;
-    }
+    const bool valid = (uint32_t)(i * kSortThreads + t) < tile_n;
+    const uint32_t d = (key[i] >> shift) & mask;
     uint64_t peers = __ballot(valid);
     for (int bit = 0; bit < nbits; ++bit) {
       const uint64_t bm = __ballot((d >> bit) & 1u);
@@ -292,17 +300,37 @@ k_sort_scatter(const uint32_t *keys, const uint32_t *vals, uint32_t *okeys, uint
     const int leader = 63 - __clzll(peers);
     if (valid && lane == leader) wcnt[w][d] = cnt;
     __syncthreads();
-    if (valid) {
-      uint32_t pos = base_off[d] + run[d] + rank;
-      for (int k = 0; k < w; ++k) pos += wcnt[k][d];
-      okeys[pos] = key;
-      ovals[pos] = val;
-    }
+    // rank among the tile's items of digit d that come before this one
+    uint32_t r = run[d] + rank;
+    for (int k = 0; k < w; ++k) r += wcnt[k][d];
+    rk[i] = r;
     __syncthreads();
     uint32_t add = 0;
 #pragma unroll
     for (int k = 0; k < kSortThreads / kWave; ++k) add += wcnt[k][t];
     run[t] += add;
+  }
+  __syncthreads();
+  // first tile slot of each digit
+  uint32_t tot;
+  tstart[t] = block_excl_scan<uint32_t>(run[t], tot, scan_lds);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    if ((uint32_t)(i * kSortThreads + t) < tile_n) {
+      const uint32_t d = (key[i] >> shift) & mask;
+      const uint32_t at = tstart[d] + rk[i];
+      lk[at] = key[i];
+      lv[at] = val[i];
+    }
+  }
+  __syncthreads();
+  for (uint32_t at = t; at < tile_n; at += kSortThreads) {
+    const uint32_t k2 = lk[at];
+    const uint32_t d = (k2 >> shift) & mask;
+    const uint32_t pos = base_off[d] + (at - tstart[d]);
+    okeys[pos] = k2;
+    ovals[pos] = lv[at];
   }
 }
 
