@@ -375,8 +375,11 @@ int64_t pcc_fof_labels_noalloc_max_n(void);
  *   PCC_DBG_CELL_START      uint32 [cells + 1] first sorted particle of each
  *                                              non-empty cell of the call (all
  *                                              jobs), then the particle count
- *   PCC_DBG_NEIGHBORS       int32  [13 cells]  the 13 forward neighbour cells
- *                                              of each cell, -1 where none
+ *   PCC_DBG_NEIGHBORS       uint32 [18 cells]  the 13 forward neighbour cells
+ *                                              of each cell as 9 ranges
+ *                                              (first, end) of sorted
+ *                                              particles, first == end
+ *                                              where empty
  * *count receives the element count; nothing is copied if cap < count.
  */
 enum {

@@ -495,7 +495,7 @@ class Context:
         code = {"active_i": 1, "active_j": 2, "active_type": 3, "safe_labels": 4,
                 "editable": 5, "active_thr": 6, "cell_start": 7, "neighbors": 8}[what]
         dtype = {1: np.uint32, 2: np.uint32, 3: np.uint8, 4: np.int32, 5: np.uint32,
-                 6: np.uint8, 7: np.uint32, 8: np.int32}[code]
+                 6: np.uint8, 7: np.uint32, 8: np.uint32}[code]
         cnt = C.c_int64(0)
         _check(lib().pcc_debug_fetch(self._h, int(job), code, None, 0, C.byref(cnt)))
         buf = np.zeros(max(cnt.value, 1), dtype=dtype)

@@ -437,10 +437,11 @@ extern "C" pcc_status pcc_debug_fetch(pcc_context *ctx, int32_t job, int32_t wha
         PCC_HIP(hipMemcpyAsync(&u, L.n_cells, sizeof u, hipMemcpyDeviceToHost, s));
         PCC_HIP(hipStreamSynchronize(s));
       }
-      const int64_t m = what == PCC_DBG_CELL_START ? (int64_t)u + 1 : 13 * (int64_t)u;
+      const int64_t m = what == PCC_DBG_CELL_START ? (int64_t)u + 1 : 2 * pcc::kNbrSlots * (int64_t)u;
       *count = L.n ? m : 0;
       if (!host_dst || cap < *count || !*count) return PCC_OK;
-      const void *src = what == PCC_DBG_CELL_START ? (const void *)L.cell_start : (const void *)L.nbr;
+      const void *src =
+          what == PCC_DBG_CELL_START ? (const void *)L.cell_start : (const void *)L.nrange;
       PCC_HIP(hipMemcpyAsync(host_dst, src, (size_t)m * 4, hipMemcpyDeviceToHost, s));
       PCC_HIP(hipStreamSynchronize(s));
       return PCC_OK;

@@ -189,17 +189,6 @@ void build_cells(const uint32_t *keys, size_t n, uint32_t *cell_of, uint32_t *ce
   k_cell_starts<<<nb, 256, 0, s>>>(keys, flag, cid, n, cell_of, cell_start, cell_key, n_cells);
 }
 
-// the 13 offsets (dx, dy, dz) that come after (0, 0, 0) in z-major order
-__constant__ int8_t kFwd[13][3] = {{1, 0, 0},  {-1, 1, 0}, {0, 1, 0},  {1, 1, 0},  {-1, -1, 1},
-                                   {0, -1, 1}, {1, -1, 1}, {-1, 0, 1}, {0, 0, 1},  {1, 0, 1},
-                                   {-1, 1, 1}, {0, 1, 1},  {1, 1, 1}};
-
-// One thread per (cell, forward offset): the 13 binary searches of a cell
-// run in parallel threads instead of one after another.
-// The thread of offset 0 also records the cell's periodic edges: bit 2a
-// when the cell is the first along periodic axis a, bit 2a + 1 when it is
-// the last (only for jobs whose coordinates lie in their periodic box, where
-// a neighbour cell across an edge stands for one periodic image).
 // blk[b] = first cell whose key is at least b << shift (a coarse index of
 // the sorted keys: a neighbour's search then covers the few cells of one
 // block instead of all of them)
@@ -221,15 +210,43 @@ __global__ void k_key_blocks(const uint32_t *cell_key, const uint32_t *n_cells, 
   }
 }
 
-__global__ void k_neighbors(const JobDev *jobs, const uint32_t *cell_base, int njobs,
-                            const uint32_t *cell_key, const uint32_t *n_cells,
-                            const uint32_t *blk, int shift, int32_t *nbr, uint8_t *edge) {
+// The 13 forward neighbour cells of a cell (x, y, z), grouped into runs of
+// consecutive keys: slot 0 is the cell (x + 1, y, z); each of the four rows
+// (dy, dz) = (1, 0), (-1, 1), (0, 1), (1, 1) holds the cells x - 1 .. x + 1
+// at (y + dy, z + dz), whose keys are consecutive unless the row crosses a
+// periodic x face: slot 2g - 1 is the part inside [0, nx), slot 2g the cell
+// across the face (x = 0: cell nx - 1; x = nx - 1: cell 0), if any.  The
+// cells are sorted by key, so each slot is one range of sorted particles.
+__device__ inline int cell_bound(const uint32_t *cell_key, uint32_t U, const uint32_t *blk,
+                                 int shift, uint64_t key) {
+  // first cell whose key is at least `key` (key <= the key space)
+  uint32_t a = blk[key >> shift], b = blk[(key >> shift) + 1];
+  if (b > U) b = U;
+  while (a < b) {
+    const uint32_t m = (a + b) >> 1;
+    if ((uint64_t)cell_key[m] < key)
+      a = m + 1;
+    else
+      b = m;
+  }
+  return (int)a;
+}
+
+// One thread per (cell, slot).  The thread of slot 0 also records the
+// cell's periodic faces: bit 2a when the cell is the first along periodic
+// axis a, bit 2a + 1 when it is the last (only for jobs whose coordinates
+// lie in their periodic box, where a neighbour cell across a face stands for
+// one periodic image).
+__global__ void k_neighbor_ranges(const JobDev *jobs, const uint32_t *cell_base, int njobs,
+                                  const uint32_t *cell_key, const uint32_t *n_cells,
+                                  const uint32_t *cell_start, const uint32_t *blk, int shift,
+                                  uint2 *nrange, uint8_t *edge) {
   const uint32_t U = *n_cells;
-  const size_t total = (size_t)U * 13;
+  const size_t total = (size_t)U * kNbrSlots;
   for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (size_t)gridDim.x * blockDim.x) {
-    const size_t u = t / 13;
-    const int s = (int)(t - u * 13);
+    const size_t u = t / kNbrSlots;
+    const int slot = (int)(t - u * kNbrSlots);
     const uint32_t key = cell_key[u];
     // job whose key range holds this cell
     int lo = 0, hi = njobs - 1;
@@ -242,10 +259,11 @@ __global__ void k_neighbors(const JobDev *jobs, const uint32_t *cell_base, int n
     }
     const JobDev &J = jobs[lo];
     const uint32_t local = key - J.cell_base;
-    const int64_t c[3] = {(int64_t)(local % (uint32_t)J.nc[0]),
-                          (int64_t)((local / (uint32_t)J.nc[0]) % (uint32_t)J.nc[1]),
-                          (int64_t)(local / ((uint32_t)J.nc[0] * (uint32_t)J.nc[1]))};
-    if (s == 0) {
+    const int64_t nx = J.nc[0], ny = J.nc[1], nz = J.nc[2];
+    const int64_t c[3] = {(int64_t)(local % (uint32_t)nx),
+                          (int64_t)((local / (uint32_t)nx) % (uint32_t)ny),
+                          (int64_t)(local / ((uint32_t)nx * (uint32_t)ny))};
+    if (slot == 0) {
       uint32_t eb = 0;
       if (J.img)
         for (int a = 0; a < 3; ++a)
@@ -255,40 +273,63 @@ __global__ void k_neighbors(const JobDev *jobs, const uint32_t *cell_base, int n
           }
       edge[u] = (uint8_t)eb;
     }
-    int64_t q[3];
-    bool ok = true;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      q[a] = c[a] + kFwd[s][a];
-      const int nc = J.nc[a];
-      if (q[a] < 0 || q[a] >= nc) {
-        if (((J.periodic >> a) & 1) && nc >= 3)
-          q[a] = (q[a] + nc) % nc;
-        else
-          ok = false;
+    const bool px = (J.periodic & 1) && nx >= 3;
+    int dy = 0, dz = 0;
+    int64_t x0, x1;  // the slot's cells x0 .. x1 (empty when x0 > x1)
+    if (slot == 0) {
+      if (c[0] + 1 < nx) {
+        x0 = x1 = c[0] + 1;
+      } else if (px) {
+        x0 = x1 = 0;
+      } else {  // the last cell of an open axis has no x + 1
+        x0 = 1;
+        x1 = 0;
+      }
+    } else {
+      const int g = (slot - 1) >> 1;
+      dy = g == 0 ? 1 : (g == 1 ? -1 : (g == 2 ? 0 : 1));
+      dz = g == 0 ? 0 : 1;
+      if (slot & 1) {
+        x0 = c[0] > 0 ? c[0] - 1 : 0;
+        x1 = c[0] + 1 < nx ? c[0] + 1 : nx - 1;
+      } else if (px && c[0] == 0) {
+        x0 = x1 = nx - 1;
+      } else if (px && c[0] == nx - 1) {
+        x0 = x1 = 0;
+      } else {
+        x0 = 1;
+        x1 = 0;
       }
     }
-    int32_t found = -1;
+    int64_t y = c[1] + dy, z = c[2] + dz;
+    bool ok = x0 <= x1;
+    if (y < 0 || y >= ny) {
+      if ((J.periodic & 2) && ny >= 3)
+        y = (y + ny) % ny;
+      else
+        ok = false;
+    }
+    if (z < 0 || z >= nz) {
+      if ((J.periodic & 4) && nz >= 3)
+        z = (z + nz) % nz;
+      else
+        ok = false;
+    }
+    uint2 r = make_uint2(0u, 0u);
     if (ok) {
-      const uint32_t want = J.cell_base + (uint32_t)((q[2] * J.nc[1] + q[1]) * J.nc[0] + q[0]);
-      uint32_t a = blk[want >> shift], b = blk[(want >> shift) + 1];
-      while (a < b) {
-        uint32_t m = (a + b) >> 1;
-        if (cell_key[m] < want)
-          a = m + 1;
-        else
-          b = m;
-      }
-      if (a < U && cell_key[a] == want) found = (int32_t)a;
+      const uint64_t row = (uint64_t)J.cell_base + (uint64_t)((z * ny + y) * nx);
+      const int a = cell_bound(cell_key, U, blk, shift, row + (uint64_t)x0);
+      const int b = cell_bound(cell_key, U, blk, shift, row + (uint64_t)x1 + 1);
+      r = make_uint2(cell_start[a], cell_start[b]);
     }
-    nbr[t] = found;
+    nrange[t] = r;
   }
 }
 
 void launch_neighbors(const JobDev *jobs, const uint32_t *cell_base, int njobs,
-                      const uint32_t *cell_key, const uint32_t *n_cells, size_t max_cells,
-                      uint64_t key_space, int32_t *nbr, uint8_t *edge, Arena &ar,
-                      hipStream_t s) {
+                      const uint32_t *cell_key, const uint32_t *n_cells, const uint32_t *cell_start,
+                      size_t max_cells, uint64_t key_space, uint2 *nrange, uint8_t *edge,
+                      Arena &ar, hipStream_t s) {
   if (!max_cells) return;
   // about four keys' blocks per particle at most
   int shift = 0;
@@ -296,8 +337,8 @@ void launch_neighbors(const JobDev *jobs, const uint32_t *cell_base, int njobs,
   const size_t nblk = (size_t)(key_space >> shift) + 1;
   uint32_t *blk = ar.get<uint32_t>(nblk + 1);
   k_key_blocks<<<blocks_for(nblk + 1, 256, 65536), 256, 0, s>>>(cell_key, n_cells, nblk, shift, blk);
-  k_neighbors<<<blocks_for(max_cells * 13, 256, 65536), 256, 0, s>>>(
-      jobs, cell_base, njobs, cell_key, n_cells, blk, shift, nbr, edge);
+  k_neighbor_ranges<<<blocks_for(max_cells * kNbrSlots, 256, 65536), 256, 0, s>>>(
+      jobs, cell_base, njobs, cell_key, n_cells, cell_start, blk, shift, nrange, edge);
 }
 
 }  // namespace pcc

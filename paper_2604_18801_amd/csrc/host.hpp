@@ -27,7 +27,7 @@ struct LastCall {
   // cell list of the call (all jobs): cell starts [n_cells + 1] and the 13
   // forward neighbour cells of each cell (-1: none)
   const uint32_t *cell_start = nullptr;
-  const int32_t *nbr = nullptr;
+  const uint2 *nrange = nullptr;  // [cells][kNbrSlots]
   const uint32_t *n_cells = nullptr;
 };
 

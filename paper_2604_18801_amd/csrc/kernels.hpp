@@ -35,10 +35,14 @@ void launch_gather(const uint32_t *perm, const int64_t *p_off, int njobs,
 // unique cells of the sorted keys; returns device counter of unique cells
 void build_cells(const uint32_t *keys, size_t n, uint32_t *cell_of, uint32_t *cell_start,
                  uint32_t *cell_key, uint32_t *n_cells, Arena &ar, hipStream_t s);
-// key_space: one more than the largest cell key of any job
+// Forward neighbours of each cell as kNbrSlots particle ranges [x, y) of the
+// sorted order (empty when x == y); key_space: one more than the largest
+// cell key of any job
+constexpr int kNbrSlots = 9;
 void launch_neighbors(const JobDev *jobs, const uint32_t *cell_base, int njobs,
-                      const uint32_t *cell_key, const uint32_t *n_cells, size_t max_cells,
-                      uint64_t key_space, int32_t *nbr, uint8_t *edge, Arena &ar, hipStream_t s);
+                      const uint32_t *cell_key, const uint32_t *n_cells, const uint32_t *cell_start,
+                      size_t max_cells, uint64_t key_space, uint2 *nrange, uint8_t *edge,
+                      Arena &ar, hipStream_t s);
 
 // pairs.hip
 struct PairBufs {
@@ -48,8 +52,8 @@ struct PairBufs {
   size_t n;
   const float4 *pos, *rec;
   const uint32_t *cell_of, *cell_start;
-  const int32_t *nbr;
-  const uint8_t *cell_edge;              // periodic edges of each cell (image shifts)
+  const uint2 *nrange;                   // [cell][kNbrSlots] forward neighbour particle ranges
+  const uint8_t *cell_edge;              // periodic faces of each cell (image shifts)
   uint32_t *safe_par, *fof_par;          // union-find parents (sorted space)
   uint32_t *cnt_pb, *cnt_pc;             // pass 1: pb and pc pairs of each home particle
   uint32_t *cnt_a, *cnt_f;               // pass 2: active and forest pairs (exact path);
@@ -75,7 +79,7 @@ struct PairPlan {
 // dense: cells with at least this many particles take the dense path (one
 // wave per 64 home particles), the others the sparse one (a thread each)
 void plan_pairs(PairPlan &pl, const uint32_t *cell_of, const uint32_t *cell_start,
-                const int32_t *nbr, const uint32_t *n_cells, size_t n, uint32_t dense, Arena &ar,
+                const uint2 *nrange, const uint32_t *n_cells, size_t n, uint32_t dense, Arena &ar,
                 hipStream_t s);
 // the plan without the sparse homes that found no vulnerable pair in pass 1
 void plan_vulnerable(const PairPlan &pl, const uint32_t *cnt_pb, const uint32_t *cnt_pc,

@@ -167,38 +167,32 @@ __device__ inline double dist2_exact(const float4 &a, const float4 &b, const Job
   return (dx * dx + dy * dy) + dz * dz;
 }
 
-// Offset (dx, dy, dz) of forward neighbour cell s = 0 .. 12, in the order of
-// the neighbour table: (1,0,0), then (-1..1, 1, 0), then (-1..1, -1..1, 1).
-__device__ inline void fwd_offset(int s, int &dx, int &dy, int &dz) {
-  if (s == 0) {
-    dx = 1;
-    dy = 0;
-    dz = 0;
-  } else if (s < 4) {
-    dx = s - 2;
-    dy = 1;
-    dz = 0;
-  } else {
-    const int t = s - 4;
-    dx = t % 3 - 1;
-    dy = t / 3 - 1;
-    dz = 1;
-  }
-}
 __device__ inline float axis_shift(int d, uint32_t edge, int a, float L) {
   if (d > 0 && ((edge >> (2 * a + 1)) & 1u)) return L;  // home on the high edge
   if (d < 0 && ((edge >> (2 * a)) & 1u)) return -L;     // home on the low edge
   return 0.f;
 }
-// Periodic image of forward neighbour s of a cell with edge bits `edge`: a
-// partner's displacement is (home - partner) - shift on every axis.  Zero
-// unless the job's coordinates lie in its periodic box (the edge bits are
-// then clear and each candidate is wrapped instead).
-__device__ inline float3 image_shift(int s, uint32_t edge, const JobPair &q) {
-  int dx, dy, dz;
-  fwd_offset(s, dx, dy, dz);
-  return make_float3(axis_shift(dx, edge, 0, q.Lf[0]), axis_shift(dy, edge, 1, q.Lf[1]),
-                     axis_shift(dz, edge, 2, q.Lf[2]));
+// Periodic image of neighbour slot `slot` (the neighbour table's order: the
+// cell x + 1; then for the rows (dy, dz) = (1, 0), (-1, 1), (0, 1), (1, 1)
+// the cells x - 1 .. x + 1 inside [0, nx) and the one across the x face) of
+// a cell with face bits `edge`: a partner's displacement is (home - partner)
+// - shift on every axis.  Zero unless the job's coordinates lie in its
+// periodic box (the face bits are then clear and each candidate is wrapped
+// instead).
+__device__ inline float3 image_shift(int slot, uint32_t edge, const JobPair &q) {
+  float sx;
+  int dy = 0, dz = 0;
+  if (slot == 0) {
+    sx = axis_shift(1, edge, 0, q.Lf[0]);
+  } else {
+    const int g = (slot - 1) >> 1;
+    dy = g == 0 ? 1 : (g == 1 ? -1 : (g == 2 ? 0 : 1));
+    dz = g == 0 ? 0 : 1;
+    // the cell across the x face: home on the low face (partner near L) or
+    // on the high face (partner near 0)
+    sx = (slot & 1) ? 0.f : ((edge & 1u) ? -q.Lf[0] : ((edge & 2u) ? q.Lf[0] : 0.f));
+  }
+  return make_float3(sx, axis_shift(dy, edge, 1, q.Lf[1]), axis_shift(dz, edge, 2, q.Lf[2]));
 }
 
 // Class of a candidate pair: a float32 squared distance decides whenever it
@@ -365,27 +359,25 @@ __device__ inline void pass1_counts(const Home &h, bool valid, unsigned long lon
 
 // Sparse cells: one thread per particle (list of particles of cells below
 // the dense-cell threshold, ordered by the candidate count of their cell).
-// Partners: later particles of its own cell, then every particle of
-// the 13 forward cells, in index order.  The ranges are found first, all at
-// once (the 13 neighbour entries, then the 26 cell bounds, each batch of
-// loads in flight together), and kept in LDS; the walk over them is one
-// flat loop, one candidate per lane per iteration, so a lane stays busy
-// until its own candidates run out (nested loops over the ranges would idle
-// every lane whose current range is shorter than the longest one in the
-// wave); the next candidate's position is loaded before the current one is
-// examined.
+// Partners: later particles of its own cell, then the particles of the 13
+// forward cells, which the neighbour table gives as kNbrSlots ranges of the
+// sorted order (runs of cells with consecutive keys).  The ranges are read
+// at once (one contiguous row of the table) and kept in LDS; the walk over
+// them is one flat loop, one candidate per lane per iteration, so a lane
+// stays busy until its own candidates run out (nested loops over the
+// ranges would idle every lane whose current range is shorter than the
+// longest one in the wave); the next candidate's position is loaded before
+// the current one is examined.
 constexpr int kSparseThreads = 256;
-constexpr int kRanges = 14;      // the home cell and 13 forward cells
-constexpr uint8_t kHomeRange = 13;  // range tag of the home cell (no image shift)
+constexpr int kRanges = 1 + kNbrSlots;  // the home cell, then the neighbour slots
 
 template <int PASS>
 __global__ void __launch_bounds__(kSparseThreads) k_pairs_sparse(PairBufs B, const uint32_t *list,
                                                                  size_t m) {
-  // candidate ranges of each thread: [lo, hi) and the forward index of its
-  // cell (kHomeRange for the home cell); [range][thread], so a wave's
-  // accesses to one range fall in distinct banks
+  // candidate ranges [lo, hi) of each thread: range 0 the home cell, range
+  // r > 0 neighbour slot r - 1; [range][thread], so a wave's accesses to one
+  // range fall in distinct banks
   __shared__ uint32_t r_lo[kRanges][kSparseThreads], r_hi[kRanges][kSparseThreads];
-  __shared__ uint8_t r_s[kRanges][kSparseThreads];
   unsigned long long cnt[3] = {0ull, 0ull, 0ull};  // safe, pb, pc
   const int tid = threadIdx.x;
   const size_t t = (size_t)blockIdx.x * blockDim.x + tid;
@@ -396,51 +388,34 @@ __global__ void __launch_bounds__(kSparseThreads) k_pairs_sparse(PairBufs B, con
     Home h;
     home_begin<PASS>(B, h, k);
     const uint32_t cell = B.cell_of[k];
-    const int32_t *nbr = B.nbr + (size_t)cell * 13;
-    const uint32_t *cs = B.cell_start;
+    const uint2 *nr_row = B.nrange + (size_t)cell * kNbrSlots;
     const uint32_t edge = B.cell_edge[cell];
-    // range 0: the later particles of the home cell; range s + 1: forward
-    // cell s (empty when the cell holds no particle); the loads of a batch
-    // are all in flight before the first is used
     r_lo[0][tid] = k + 1;
-    r_hi[0][tid] = cs[cell + 1];
-    r_s[0][tid] = kHomeRange;
-    for (int s0 = 0; s0 < 13; s0 += 7) {
-      const int ns = s0 + 7 < 13 ? 7 : 13 - s0;
-      int32_t nb[7];
+    r_hi[0][tid] = B.cell_start[cell + 1];
 #pragma unroll
-      for (int i = 0; i < 7; ++i)
-        if (i < ns) nb[i] = nbr[s0 + i];
-#pragma unroll
-      for (int i = 0; i < 7; ++i)
-        if (i < ns) {
-          const uint32_t c = nb[i] >= 0 ? (uint32_t)nb[i] : 0u;
-          const uint32_t a = cs[c], b = cs[c + 1];
-          r_lo[s0 + i + 1][tid] = a;
-          r_hi[s0 + i + 1][tid] = nb[i] >= 0 ? b : a;
-          r_s[s0 + i + 1][tid] = (uint8_t)(s0 + i);
-        }
+    for (int i = 0; i < kNbrSlots; ++i) {
+      const uint2 v = nr_row[i];
+      r_lo[i + 1][tid] = v.x;
+      r_hi[i + 1][tid] = v.y;
     }
-    const int nr = kRanges;
     auto enter = [&](int r, uint32_t &j, uint32_t &e, float3 &sh) {
       j = r_lo[r][tid];
       e = r_hi[r][tid];
-      const int s = r_s[r][tid];
-      sh = s == kHomeRange ? make_float3(0.f, 0.f, 0.f) : image_shift(s, edge, q);
+      sh = r == 0 ? make_float3(0.f, 0.f, 0.f) : image_shift(r - 1, edge, q);
     };
     // (j, e): the current range r; empty ranges are passed over
     int r = 0;
     uint32_t j = 0, e = 0;
     float3 sh = make_float3(0.f, 0.f, 0.f);
     enter(0, j, e, sh);
-    while (j >= e && ++r < nr) enter(r, j, e, sh);
-    float4 pj = B.pos[r < nr ? j : k];  // (index k: any valid load)
-    while (r < nr) {
+    while (j >= e && ++r < kRanges) enter(r, j, e, sh);
+    float4 pj = B.pos[r < kRanges ? j : k];  // (index k: any valid load)
+    while (r < kRanges) {
       uint32_t jn = j + 1, en = e;
       int rn = r;
       float3 shn = sh;
-      while (jn >= en && ++rn < nr) enter(rn, jn, en, shn);
-      const float4 pn = B.pos[rn < nr ? jn : k];
+      while (jn >= en && ++rn < kRanges) enter(rn, jn, en, shn);
+      const float4 pn = B.pos[rn < kRanges ? jn : k];
       visit<PASS, false>(B, q, h, j, pj, sh, 0u, 0u);
       j = jn;
       e = en;
@@ -456,13 +431,13 @@ __global__ void __launch_bounds__(kSparseThreads) k_pairs_sparse(PairBufs B, con
 
 constexpr int kPairWaves = 4;
 
-// Dense cells: one wave per 64 home particles of one cell.  Each partner
-// cell is staged through LDS 64 particles at a time with coalesced loads
-// (positions and both parents); every lane then runs over the same staged
-// particles (broadcast reads), so the lanes of a wave never diverge on trip
-// counts, and the periodic image of a partner cell is one shift for the
-// whole wave.  Every home particle sees its partners in the same order as in
-// the sparse kernel.
+// Dense cells: one wave per 64 home particles of one cell.  Each neighbour
+// range (a run of forward cells with consecutive keys) is staged through
+// LDS 64 particles at a time with coalesced loads (positions and both
+// parents); every lane then runs over the same staged particles (broadcast
+// reads), so the lanes of a wave never diverge on trip counts, and the
+// periodic image of a range is one shift for the whole wave.  Every home
+// particle sees its partners in the same order as in the sparse kernel.
 template <int PASS>
 __global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense(PairBufs B, const uint32_t *ucell,
                                                                  const uint32_t *uchunk, size_t m) {
@@ -481,17 +456,17 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense(PairBufs B, con
   const uint32_t edge = B.cell_edge[cell];
   Home h;
   home_begin<PASS>(B, h, valid ? k0 + lane : k0);
-  for (int s = 0; s < 14; ++s) {
+  for (int s = 0; s <= kNbrSlots; ++s) {
     uint32_t j0, j1;
     float3 sh = make_float3(0.f, 0.f, 0.f);
     if (s == 0) {
       j0 = k0 + 1;  // later particles of the home cell
       j1 = ce;
     } else {
-      const int32_t nb = B.nbr[(size_t)cell * 13 + s - 1];
-      if (nb < 0) continue;
-      j0 = B.cell_start[nb];
-      j1 = B.cell_start[nb + 1];
+      const uint2 v = B.nrange[(size_t)cell * kNbrSlots + s - 1];
+      if (v.x >= v.y) continue;
+      j0 = v.x;
+      j1 = v.y;
       sh = image_shift(s - 1, edge, q);
     }
     for (uint32_t t0 = j0; t0 < j1; t0 += 64) {
@@ -547,17 +522,17 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense_write(PairBufs 
   const uint64_t a0 = B.off_a[k0], f0 = B.off_f[k0];
   uint64_t wa = a0, wf = f0;
   const uint64_t below = (1ull << lane) - 1ull;
-  for (int s = 0; s < 14; ++s) {
+  for (int s = 0; s <= kNbrSlots; ++s) {
     uint32_t j0, j1;
     float3 sh = make_float3(0.f, 0.f, 0.f);
     if (s == 0) {
       j0 = k0 + 1;  // later particles of the home cell
       j1 = ce;
     } else {
-      const int32_t nb = B.nbr[(size_t)cell * 13 + s - 1];
-      if (nb < 0) continue;
-      j0 = B.cell_start[nb];
-      j1 = B.cell_start[nb + 1];
+      const uint2 v = B.nrange[(size_t)cell * kNbrSlots + s - 1];
+      if (v.x >= v.y) continue;
+      j0 = v.x;
+      j1 = v.y;
       sh = image_shift(s - 1, edge, q);
     }
     for (uint32_t t0 = j0; t0 < j1; t0 += 64) {
@@ -629,14 +604,14 @@ __global__ void k_sparse_list(const uint8_t *flag, const uint32_t *pos32, size_t
 // first: the lanes of a wave then have similar trip counts, while within a
 // bucket the particles keep their (spatial) order for cache reuse.
 __global__ void k_sparse_keys(const uint32_t *list, size_t m, const uint32_t *cell_of,
-                              const uint32_t *cell_start, const int32_t *nbr, uint32_t *key) {
+                              const uint32_t *cell_start, const uint2 *nrange, uint32_t *key) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
        i += (size_t)gridDim.x * blockDim.x) {
     const uint32_t c = cell_of[list[i]];
     uint32_t cost = cell_start[c + 1] - cell_start[c];
-    for (int s = 0; s < 13; ++s) {
-      const int32_t nb = nbr[(size_t)c * 13 + s];
-      if (nb >= 0) cost += cell_start[nb + 1] - cell_start[nb];
+    for (int s = 0; s < kNbrSlots; ++s) {
+      const uint2 v = nrange[(size_t)c * kNbrSlots + s];
+      cost += v.y - v.x;
     }
     const uint32_t lg = 31u - (uint32_t)__clz(cost | 1u);  // floor(log2), 0 for cost <= 1
     key[i] = 15u - (lg < 15u ? lg : 15u);
@@ -667,7 +642,7 @@ __global__ void k_unit_list(const uint32_t *units, const uint32_t *uoff, size_t 
 }
 
 void plan_pairs(PairPlan &pl, const uint32_t *cell_of, const uint32_t *cell_start,
-                const int32_t *nbr, const uint32_t *n_cells, size_t n, uint32_t dense, Arena &ar,
+                const uint2 *nrange, const uint32_t *n_cells, size_t n, uint32_t dense, Arena &ar,
                 hipStream_t s) {
   if (dense < 1) dense = 1;
   uint8_t *flag = ar.get<uint8_t>(n ? n : 1);
@@ -689,7 +664,7 @@ void plan_pairs(PairPlan &pl, const uint32_t *cell_of, const uint32_t *cell_star
     if (ns > 1) {
       uint32_t *key = ar.get<uint32_t>(ns);
       k_sparse_keys<<<blocks_for(ns, 256, 65536), 256, 0, s>>>(pl.sparse, ns, cell_of, cell_start,
-                                                               nbr, key);
+                                                               nrange, key);
       radix_sort_u32(key, pl.sparse, ns, 4, ar, s);
     }
     k_unit_counts<<<nb, 256, 0, s>>>(cell_start, n_cells, n, dense, units);

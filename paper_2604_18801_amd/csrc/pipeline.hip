@@ -712,11 +712,12 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   uint32_t *cell_of = dev<uint32_t>(ar, n), *cell_start = dev<uint32_t>(ar, n + 1);
   uint32_t *cell_key = dev<uint32_t>(ar, n), *n_cells = dev<uint32_t>(ar, 1);
   build_cells(keys, n, cell_of, cell_start, cell_key, n_cells, ar, s);
-  int32_t *nbr = dev<int32_t>(ar, n * 13);
+  uint2 *nrange = dev<uint2>(ar, n * kNbrSlots);
   uint8_t *cell_edge = dev<uint8_t>(ar, n);
-  launch_neighbors(d_jobs, d_cbase, J, cell_key, n_cells, n, cell_total, nbr, cell_edge, ar, s);
+  launch_neighbors(d_jobs, d_cbase, J, cell_key, n_cells, cell_start, n, cell_total, nrange,
+                   cell_edge, ar, s);
   PairPlan plan;
-  plan_pairs(plan, cell_of, cell_start, nbr, n_cells, n, (uint32_t)C.dense_cell, ar, s);
+  plan_pairs(plan, cell_of, cell_start, nrange, n_cells, n, (uint32_t)C.dense_cell, ar, s);
   mark(2, "cell build");
 
   // ------------------------------------------------------------------
@@ -731,7 +732,7 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   pb.rec = rec;
   pb.cell_of = cell_of;
   pb.cell_start = cell_start;
-  pb.nbr = nbr;
+  pb.nrange = nrange;
   pb.cell_edge = cell_edge;
   pb.safe_par = dev<uint32_t>(ar, n);
   pb.fof_par = dev<uint32_t>(ar, n);
@@ -1332,7 +1333,7 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   C.last.pos = pos;
   C.last.e_list = e_list;
   C.last.cell_start = cell_start;
-  C.last.nbr = nbr;
+  C.last.nrange = nrange;
   C.last.n_cells = n_cells;
 
   pcc_status first = PCC_OK;

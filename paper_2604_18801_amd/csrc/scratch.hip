@@ -16,11 +16,12 @@
 namespace {
 
 constexpr size_t kScratchBytes = (size_t)128 << 20;
-// The labels-only path takes at most ~215 bytes per particle from its arena
+// The labels-only path takes at most ~240 bytes per particle from its arena
 // (inputs copied from the host 24, cell keys and sort 48, sorted positions
-// 32, cell tables 64, pair plan 37, union-finds and counts 24, labels 8),
-// plus a few kB of per-call tables and 256-byte rounding: 256 per particle
-// and 1 MiB bound it.
+// 32, cell tables 86 (starts, keys, cell of each particle, nine neighbour
+// ranges, face bits, coarse key index), pair plan 37, union-finds and
+// counts 24, labels 8), plus a few kB of per-call tables and 256-byte
+// rounding: 256 per particle and 1 MiB bound it.
 constexpr size_t kBytesPerParticle = 256;
 constexpr size_t kFixedBytes = (size_t)1 << 20;
 constexpr int64_t kMaxParticles = (int64_t)((kScratchBytes - kFixedBytes) / kBytesPerParticle);

@@ -440,24 +440,27 @@ def test_workspace_query_bounds_the_call(ctx, kind, mode):
 
 
 def test_cell_list_tables_stay_in_bounds(ctx):
-    # the cell starts and forward-neighbour table every pair pass indexes:
-    # starts nondecreasing from 0 to n, every neighbour entry -1 or a cell
+    # the cell starts and forward-neighbour ranges every pair pass indexes:
+    # starts strictly increasing from 0 to n; nine particle ranges per cell,
+    # each empty or running between two cell starts
+    def check(cs, nb, n):
+        u = len(cs) - 1
+        assert cs[0] == 0 and cs[-1] == n and np.all(np.diff(cs) >= 1)
+        assert len(nb) == 2 * 9 * u
+        lo, hi = nb[0::2], nb[1::2]
+        assert np.all(lo <= hi) and np.all(hi <= n)
+        full = hi > lo
+        assert np.all(np.isin(lo[full], cs)) and np.all(np.isin(hi[full], cs))
     cases = [(synth.cosmology(24, seed=16, xi=0.05), "hf"), (synth.md_block(30000, 17), "sc"),
              (synth.plain_blobs(), "vp"), (synth.plain_blobs(2, seed=18), "hf")]
     for w, m in cases:
         print("case cell tables", w.name, flush=True)
         ctx.correct(_dev(w.orig), _dev(w.recon), w.b, w.xi, mode=m, box=w.box, max_iters=5)
-        cs = ctx.debug_fetch(0, "cell_start").astype(np.int64)
-        nb = ctx.debug_fetch(0, "neighbors").astype(np.int64)
-        u = len(cs) - 1
-        assert cs[0] == 0 and cs[-1] == w.n and np.all(np.diff(cs) >= 1)
-        assert len(nb) == 13 * u and np.all((nb == -1) | ((nb >= 0) & (nb < u)))
+        check(ctx.debug_fetch(0, "cell_start").astype(np.int64),
+              ctx.debug_fetch(0, "neighbors").astype(np.int64), w.n)
     # several jobs in one index space
     ws = [synth.plain_blobs(3000, seed=19), synth.cosmology(16, seed=20, xi=0.05)]
     ctx.correct_batch([dict(orig=_dev(w.orig), recon=_dev(w.recon), b=w.b, xi=w.xi, mode="hf",
                             box=w.box) for w in ws])
-    cs = ctx.debug_fetch(0, "cell_start").astype(np.int64)
-    nb = ctx.debug_fetch(1, "neighbors").astype(np.int64)
-    u = len(cs) - 1
-    assert cs[-1] == sum(w.n for w in ws) and np.all(np.diff(cs) >= 1)
-    assert np.all((nb == -1) | ((nb >= 0) & (nb < u)))
+    check(ctx.debug_fetch(0, "cell_start").astype(np.int64),
+          ctx.debug_fetch(1, "neighbors").astype(np.int64), sum(w.n for w in ws))
