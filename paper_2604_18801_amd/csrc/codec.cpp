@@ -21,6 +21,7 @@
 #include <dlfcn.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <mutex>
 #include <queue>
@@ -88,42 +89,58 @@ bool zstd_available() { return zstd().ok; }
 
 // Inputs from kZstdParallelMin on are cut into pieces compressed on host
 // threads as independent frames; the frames are concatenated, which one
-// ZSTD decompression call reads back as a whole.
-bool zstd_compress(const uint8_t *src, size_t len, std::vector<uint8_t> &dst, int level) {
+// ZSTD decompression call reads back as a whole.  The input is a list of
+// segments (the payload's parts where they already are), so the payload is
+// never assembled in one buffer; frames are written after `at` bytes of dst.
+struct Segment {
+  const uint8_t *p;
+  size_t n;
+};
+static bool zstd_compress_segments(const std::vector<Segment> &segs, size_t at,
+                                   std::vector<uint8_t> &dst, int level) {
   Zstd &z = zstd();
-  if (!z.ok || len == 0) return false;
-  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-  size_t pieces = 1;
-  if (len >= kZstdParallelMin && hw > 1)
-    pieces = std::min<size_t>(std::min(16u, hw), (len + kZstdJob - 1) / kZstdJob);
-  const size_t step = (len + pieces - 1) / pieces;
-  std::vector<std::vector<uint8_t>> out(pieces);
-  std::vector<size_t> got(pieces, 0);
-  auto work = [&](size_t p) {
-    const size_t a = p * step, b = std::min(len, a + step);
-    out[p].resize(z.bound(b - a));
-    got[p] = z.compress(out[p].data(), out[p].size(), src + a, b - a, level);
+  if (!z.ok) return false;
+  // the pieces: each segment cut into runs of at most kZstdJob bytes once
+  // the payload reaches kZstdParallelMin
+  size_t len = 0;
+  for (const Segment &g : segs) len += g.n;
+  if (len == 0) return false;
+  std::vector<Segment> pieces;
+  const size_t cut = len >= kZstdParallelMin ? kZstdJob : len;
+  for (const Segment &g : segs)
+    for (size_t a = 0; a < g.n; a += cut) pieces.push_back({g.p + a, std::min(cut, g.n - a)});
+  const size_t np = pieces.size();
+  std::vector<std::vector<uint8_t>> out(np);
+  std::vector<size_t> got(np, 0);
+  std::atomic<size_t> next{0};
+  auto work = [&]() {
+    for (size_t p; (p = next.fetch_add(1)) < np;) {
+      out[p].resize(z.bound(pieces[p].n));
+      got[p] = z.compress(out[p].data(), out[p].size(), pieces[p].p, pieces[p].n, level);
+    }
   };
-  if (pieces == 1) {
-    work(0);
-  } else {
-    std::vector<std::thread> th;
-    for (size_t p = 1; p < pieces; ++p) th.emplace_back(work, p);
-    work(0);
-    for (auto &t : th) t.join();
-  }
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const size_t nth = std::min<size_t>(std::min<size_t>(16, hw), np);
+  std::vector<std::thread> th;
+  for (size_t t = 1; t < nth; ++t) th.emplace_back(work);
+  work();
+  for (auto &t : th) t.join();
   size_t total = 0;
-  for (size_t p = 0; p < pieces; ++p) {
+  for (size_t p = 0; p < np; ++p) {
     if (z.is_error(got[p])) return false;
     total += got[p];
   }
-  dst.resize(total);
-  size_t at = 0;
-  for (size_t p = 0; p < pieces; ++p) {
+  dst.resize(at + total);
+  for (size_t p = 0; p < np; ++p) {
     std::memcpy(dst.data() + at, out[p].data(), got[p]);
     at += got[p];
   }
   return true;
+}
+
+bool zstd_compress(const uint8_t *src, size_t len, std::vector<uint8_t> &dst, int level) {
+  dst.clear();
+  return zstd_compress_segments({{src, len}}, 0, dst, level);
 }
 
 bool zstd_decompress(const uint8_t *src, size_t len, uint8_t *dst, size_t raw_len) {
@@ -211,37 +228,51 @@ void assemble_stream(int64_t n, int m_bits, int64_t nflagged, double qstep, doub
                      const uint8_t *flags, size_t nflag_bytes, const HuffTable *ht,
                      const uint32_t *words, uint64_t nbits, const uint64_t *chunk_bits,
                      size_t nchunks, std::vector<uint8_t> &out, size_t *payload_raw) {
-  std::vector<uint8_t> pay;
   const size_t nb = ((size_t)n + 7) / 8;
   const bool huff = nflagged > 0 && ht && !ht->syms.empty();
   const size_t nsym = (size_t)nflagged * 3 * (m_bits == 32 ? 2 : 1);
   if (huff && nchunks != (nsym + kHuffChunk - 1) / kHuffChunk)
     throw Error(PCC_E_DEVICE, "chunk index does not match the symbol count");
-  size_t raw = nb;
-  if (huff) raw += 4 + 5 * ht->syms.size() + 8 + 8 + 8 * nchunks + (size_t)((nbits + 7) / 8);
-  pay.assign(raw, 0);
-  if (nb) std::memcpy(pay.data(), flags, std::min(nb, nflag_bytes));
+  // the payload's parts: flag bytes, the code table and chunk index, the bits
+  std::vector<uint8_t> flag_tail;  // flag bytes the caller did not supply
+  if (nflag_bytes < nb) flag_tail.assign(nb - nflag_bytes, 0);
+  std::vector<uint8_t> tab;
   if (huff) {
-    size_t at = nb;
-    put<uint32_t>(pay, at, (uint32_t)ht->syms.size());
+    tab.assign(4 + 5 * ht->syms.size() + 8 + 8 + 8 * nchunks, 0);
+    size_t at = 0;
+    put<uint32_t>(tab, at, (uint32_t)ht->syms.size());
     at += 4;
     for (uint32_t sy : ht->syms) {
-      put<uint32_t>(pay, at, sy);
+      put<uint32_t>(tab, at, sy);
       at += 4;
     }
-    for (uint8_t l : ht->lens) pay[at++] = l;
-    put<uint64_t>(pay, at, nbits);
+    for (uint8_t l : ht->lens) tab[at++] = l;
+    put<uint64_t>(tab, at, nbits);
     at += 8;
-    put<uint32_t>(pay, at, kHuffChunk);
+    put<uint32_t>(tab, at, kHuffChunk);
     at += 8;
-    for (size_t c = 0; c < nchunks; ++c, at += 8) put<uint64_t>(pay, at, chunk_bits[c]);
-    std::memcpy(pay.data() + at, words, (size_t)((nbits + 7) / 8));
+    for (size_t c = 0; c < nchunks; ++c, at += 8) put<uint64_t>(tab, at, chunk_bits[c]);
   }
+  std::vector<Segment> segs;
+  if (nb) segs.push_back({flags, std::min(nb, nflag_bytes)});
+  if (!flag_tail.empty()) segs.push_back({flag_tail.data(), flag_tail.size()});
+  if (huff) {
+    segs.push_back({tab.data(), tab.size()});
+    segs.push_back({reinterpret_cast<const uint8_t *>(words), (size_t)((nbits + 7) / 8)});
+  }
+  size_t raw = 0;
+  for (const Segment &g : segs) raw += g.n;
   *payload_raw = raw;
-  std::vector<uint8_t> z;
-  const bool zok = zstd_compress(pay.data(), pay.size(), z, kZstdLevelDefault);
-  const std::vector<uint8_t> &stored = zok ? z : pay;
-  out.assign(kHeader + stored.size(), 0);
+  const bool zok = zstd_compress_segments(segs, kHeader, out, kZstdLevelDefault);
+  if (!zok) {
+    out.assign(kHeader + raw, 0);
+    size_t at = kHeader;
+    for (const Segment &g : segs) {
+      if (g.n) std::memcpy(out.data() + at, g.p, g.n);
+      at += g.n;
+    }
+  }
+  const size_t stored = out.size() - kHeader;
   put<uint32_t>(out, 0, kMagic);
   put<uint16_t>(out, 4, kVersion);
   out[6] = (uint8_t)m_bits;
@@ -251,9 +282,9 @@ void assemble_stream(int64_t n, int m_bits, int64_t nflagged, double qstep, doub
   put<double>(out, 24, qstep);
   put<double>(out, 32, qoffset);
   put<uint64_t>(out, 40, (uint64_t)raw);
-  put<uint64_t>(out, 48, (uint64_t)stored.size());
+  put<uint64_t>(out, 48, (uint64_t)stored);
   put<uint32_t>(out, 56, (uint32_t)(m_bits == 8 ? 8 : 16));
-  if (!stored.empty()) std::memcpy(out.data() + kHeader, stored.data(), stored.size());
+  put<uint32_t>(out, 60, 0u);
 }
 
 pcc_status parse_stream(const uint8_t *s, size_t len, int64_t n, ParsedStream &out,

@@ -207,10 +207,14 @@ void list_editable(const uint8_t *is_e, const uint32_t *eid, size_t n, uint32_t 
 // e_list and eid are updated in place
 void order_rows(uint32_t *e_list, size_t ne, uint32_t *eid, const float4 *pos, const JobDev *jobs,
                 const int64_t *p_off, int njobs, Arena &ar, hipStream_t s);
-// col entries: partner row | kColPc for created pairs | threshold << kColThrShift
+// col entries: partner row | kColPc for created pairs | threshold << kColThrShift;
+// every row in increasing (partner's original index, threshold): by a
+// stable sort of pairs already in that order (pairs_sorted), else by a rank
+// within each row
 void build_csr(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t, const uint8_t *a_k,
-               size_t na, const uint32_t *eid, uint32_t ne, uint32_t *row_ptr, uint32_t *col,
-               Arena &ar, hipStream_t s);
+               size_t na, const uint32_t *eid, uint32_t ne, const uint32_t *e_list,
+               const float4 *pos, bool pairs_sorted, uint32_t *row_ptr, uint32_t *col, Arena &ar,
+               hipStream_t s);
 void launch_pgd_init(const uint32_t *e_list, size_t ne, const float4 *pos, const float4 *rec,
                      double *P0, float4 *xo, double *m, double *v, hipStream_t s);
 // worklist of the first step: every row; no row hot yet

@@ -238,9 +238,40 @@ void order_rows(uint32_t *e_list, size_t ne, uint32_t *eid, const float4 *pos, c
   k_row_apply<<<nb, 256, 0, s>>>(old, order, ne, e_list, eid);
 }
 
+// job-local original index of each row's particle
+__global__ void k_row_origs(const uint32_t *e_list, size_t ne, const float4 *pos, uint32_t *orig) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne;
+       e += (size_t)gridDim.x * blockDim.x)
+    orig[e] = __float_as_uint(pos[e_list[e]].w);
+}
+// order key of an incidence within its row: the partner's original index,
+// then the threshold index
+__global__ void k_inc_keys(const uint32_t *col, size_t m, const uint32_t *orig, uint64_t *ikey) {
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < m;
+       q += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t c = col[q];
+    ikey[q] = ((uint64_t)orig[c & kColRow] << 3) | ((c >> kColThrShift) & 7u);
+  }
+}
+// Each incidence goes to its rank among the incidences of its row (keys are
+// distinct within a row), so every row ends in order of its keys.
+__global__ void k_row_rank(const uint32_t *rows, const uint32_t *row_ptr, const uint64_t *ikey,
+                           const uint32_t *col, size_t m, uint32_t *out) {
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < m;
+       q += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t r = rows[q];
+    const uint32_t a = row_ptr[r], b = row_ptr[r + 1];
+    const uint64_t k = ikey[q];
+    uint32_t rank = 0;
+    for (uint32_t t = a; t < b; ++t) rank += ikey[t] < k ? 1u : 0u;
+    out[a + rank] = col[q];
+  }
+}
+
 void build_csr(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t, const uint8_t *a_k,
-               size_t na, const uint32_t *eid, uint32_t ne, uint32_t *row_ptr, uint32_t *col,
-               Arena &ar, hipStream_t s) {
+               size_t na, const uint32_t *eid, uint32_t ne, const uint32_t *e_list,
+               const float4 *pos, bool pairs_sorted, uint32_t *row_ptr, uint32_t *col, Arena &ar,
+               hipStream_t s) {
   if (ne > kColRow) throw Error(-6, "more than 2^28 editable particles in one call");
   if (!na) {
     fill_u32(row_ptr, 0, (size_t)ne + 1, s);
@@ -249,9 +280,19 @@ void build_csr(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t, con
   const size_t m = 2 * na;
   if (m > 0xffffffffull) throw Error(-6, "more than 2^31 active pairs in one call");
   uint32_t *keys = ar.get<uint32_t>(m);
-  k_incid<<<blocks_for(na, 256, 65536), 256, 0, s>>>(a_i, a_j, a_t, a_k, na, eid, keys, col);
-  radix_sort_u32(keys, col, m, bits_for(ne ? ne - 1 : 0), ar, s);
+  uint32_t *c1 = pairs_sorted ? col : ar.get<uint32_t>(m);
+  k_incid<<<blocks_for(na, 256, 65536), 256, 0, s>>>(a_i, a_j, a_t, a_k, na, eid, keys, c1);
+  radix_sort_u32(keys, c1, m, bits_for(ne ? ne - 1 : 0), ar, s);
   k_row_ptr<<<blocks_for(m, 256, 65536), 256, 0, s>>>(keys, m, ne, row_ptr);
+  if (!pairs_sorted) {
+    // the stable sort by row kept the pair list's order inside each row;
+    // each row is put in increasing (partner index, threshold) instead
+    uint32_t *orig = ar.get<uint32_t>(ne);
+    uint64_t *ikey = ar.get<uint64_t>(m);
+    k_row_origs<<<blocks_for(ne, 256, 65536), 256, 0, s>>>(e_list, ne, pos, orig);
+    k_inc_keys<<<blocks_for(m, 256, 65536), 256, 0, s>>>(c1, m, orig, ikey);
+    k_row_rank<<<blocks_for(m, 256, 65536), 256, 0, s>>>(keys, row_ptr, ikey, c1, m, col);
+  }
 }
 
 __global__ void k_pgd_init(const uint32_t *e_list, size_t ne, const float4 *pos, const float4 *rec,
@@ -293,12 +334,12 @@ void launch_loop_init(const JobDev *jobs, JobLoop *loop, int njobs, int32_t *n_a
 // ----------------------------------------------------------------------------
 // the fused step
 // ----------------------------------------------------------------------------
+// Minimum image of a difference on a periodic axis (hL = +inf on an open
+// one): d - L above hL, d + L below -hL.  Both candidates are formed and one
+// is selected, so the wave does not branch per coordinate.
 __device__ inline double wrapd(double d, double L, double hL) {
-  if (d > hL)
-    d -= L;
-  else if (d < -hL)
-    d += L;
-  return d;
+  const double lo = d - L, hi = d + L;
+  return d > hL ? lo : (d < -hL ? hi : d);
 }
 
 __device__ inline unsigned long long wsum(unsigned long long v) {
@@ -886,6 +927,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_rows(
   __shared__ uint32_t s_vb[kPgdWaves][64];  // first slot of each row in the tile's work list
   __shared__ uint32_t s_e[kPgdWaves][64];   // row index
   __shared__ uint8_t s_mk[kPgdWaves][64];   // the row marks its partners hot
+  __shared__ int8_t s_own[kPgdWaves][64];   // row starting at each slot of a chunk
   // loss thresholds b -+ delta_t and their squares per linking length of a
   // multi-threshold job (read from LDS: a memory load in the evaluation
   // would make the gathers already in flight complete first)
@@ -950,20 +992,30 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_rows(
     wave_sync();
     double gx = 0.0, gy = 0.0, gz = 0.0;
     bool hrow = false;  // some constraint of the row is violated
-    // owner row of slot q (last r with s_vb[r] <= q) and its column entry;
-    // each chunk loads the next chunk's entries before it waits for its own
-    // gathers
-    auto locate = [&](uint32_t q, int &r, uint32_t &col) {
-      int lo = 0, hi = nrow - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_vb[w][mid] <= q)
-          lo = mid;
-        else
-          hi = mid - 1;
+    // Owner row of slot q = c + lane of the chunk starting at slot c (the
+    // last row starting at or before q) and its column entry.  The rows
+    // that start inside the chunk mark their first slot, and a running
+    // maximum over the lanes, seeded with the owner of the slot before the
+    // chunk (carry), gives every slot its row; chunks are located in order.
+    // Each chunk loads the next chunk's entries before it waits for its own
+    // gathers.
+    int carry = 0;
+    auto locate = [&](uint32_t c, int &r, uint32_t &col) {
+      s_own[w][lane] = -1;
+      wave_sync();
+      if (len > 0 && vb >= c && vb < c + 64) s_own[w][vb - c] = (int8_t)lane;
+      wave_sync();
+      int o = s_own[w][lane];
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(o, d, kWave);
+        if (lane >= d) o = t > o ? t : o;
       }
-      r = lo;
-      col = B.col[s_rp[w][lo] + (q - s_vb[w][lo])];
+      o = carry > o ? carry : o;
+      carry = __shfl(o, 63, kWave);
+      r = o;
+      const uint32_t q = c + lane;
+      col = q < total ? B.col[s_rp[w][o] + (q - s_vb[w][o])] : 0u;
     };
     // two-deep pipeline: while chunk c is evaluated, the partner gather of
     // chunk c + 1 and the column entries of chunk c + 2 are in flight
@@ -974,11 +1026,11 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_rows(
     int r_nx = 0, r_nx2 = 0;
     uint32_t col_nx = 0, col_nx2 = 0;
     double3 po_nx = make_double3(0.0, 0.0, 0.0);
-    if ((uint32_t)lane < total) {
-      locate(lane, r_nx, col_nx);
-      po_nx = gather(col_nx);
+    if (total > 0) {
+      locate(0, r_nx, col_nx);
+      if ((uint32_t)lane < total) po_nx = gather(col_nx);
     }
-    if ((uint32_t)lane + 64 < total) locate(lane + 64, r_nx2, col_nx2);
+    if (total > 64) locate(64, r_nx2, col_nx2);
     for (uint32_t c0 = 0; c0 < total; c0 += 64) {
       const uint32_t q = c0 + lane;
       double tx = 0.0, ty = 0.0, tz = 0.0;
@@ -989,7 +1041,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_rows(
       r_nx = r_nx2;
       col_nx = col_nx2;
       if (q + 64 < total) po_nx = gather(col_nx);
-      if (q + 128 < total) locate(q + 128, r_nx2, col_nx2);
+      if (c0 + 128 < total) locate(c0 + 128, r_nx2, col_nx2);
       if (q < total) {
         const uint32_t o = col & kColRow;
         const uint32_t er = s_e[w][r];

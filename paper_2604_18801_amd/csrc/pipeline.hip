@@ -17,6 +17,9 @@ namespace {
 
 constexpr int64_t kTileInputs = 1 << 13;  // 2048 blocks for 16.8M inputs
 constexpr int kGraphIters = 8;
+// calls with at most this many incidences per editable row on average
+// order each row by a rank within the row; others sort the pair list
+constexpr double kRankRowsDegree = 16.0;
 
 double ulp_f32(double a) {
   int e;
@@ -930,19 +933,24 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   // ------------------------------------------------------------------
   // editable set and incidence lists
   // ------------------------------------------------------------------
-  {
-    int64_t nmax = 1;
-    for (auto *h : act) nmax = std::max(nmax, h->n);
-    const int at = kt.start(6, s);
-    sort_pairs(a_i, a_j, a_t, a_k, na, pos, bits_for((uint64_t)(nmax - 1)), ar, s);
-    kt.stop(at, s);
-  }
   uint8_t *is_e = dev<uint8_t>(ar, n);
   uint32_t *eid = dev<uint32_t>(ar, n);
   uint32_t *ne_dev = dev<uint32_t>(ar, 1);
   mark_editable(a_i, a_j, na, n, is_e, eid, ne_dev, ar, s);
   uint32_t ne = 0;
   st.fetch(&ne, ne_dev, 1);
+  // The incidences of a row are ordered by partner index: for rows of a few
+  // incidences by a rank within the row after the sort by row (work per row
+  // grows with the square of its length), for long rows by sorting the pair
+  // list first.
+  const bool pairs_sorted = 2.0 * (double)na > kRankRowsDegree * (double)ne;
+  if (pairs_sorted) {
+    int64_t nmax = 1;
+    for (auto *h : act) nmax = std::max(nmax, h->n);
+    const int at = kt.start(6, s);
+    sort_pairs(a_i, a_j, a_t, a_k, na, pos, bits_for((uint64_t)(nmax - 1)), ar, s);
+    kt.stop(at, s);
+  }
   uint32_t *e_list = dev<uint32_t>(ar, ne);
   uint32_t *row_ptr = dev<uint32_t>(ar, (size_t)ne + 1);
   uint32_t *col = dev<uint32_t>(ar, 2 * na);
@@ -952,7 +960,7 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   {
     const int at = kt.start(6, s);
     order_rows(e_list, ne, eid, pos, d_jobs, d_poff, J, ar, s);
-    build_csr(a_i, a_j, a_t, a_k, na, eid, ne, row_ptr, col, ar, s);
+    build_csr(a_i, a_j, a_t, a_k, na, eid, ne, e_list, pos, pairs_sorted, row_ptr, col, ar, s);
     kt.stop(at, s);
   }
   std::vector<int64_t> e_off(J + 1);
