@@ -216,9 +216,82 @@ void scan_u32_u64(const uint32_t *in, uint64_t *out, size_t n, uint64_t *total, 
                   hipStream_t s) {
   scan_impl<uint32_t, uint64_t>(in, out, n, total, ar, s);
 }
+// Byte counts (flags) to 32-bit offsets, the common case: every thread takes
+// 16 consecutive bytes with one 16-byte load and writes their 16 offsets with
+// four 16-byte stores, so a block scans 4096 items with one block-wide scan.
+constexpr int kScan8Items = 16;
+constexpr size_t kScan8Tile = (size_t)kScanThreads * kScan8Items;
+
+__device__ inline void load16(const uint8_t *in, size_t base, size_t n, uint32_t (&b)[16]) {
+  if (base + 16 <= n) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(in + base);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 16; ++i) b[i] = (w[i >> 2] >> (8 * (i & 3))) & 0xffu;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) b[i] = base + i < n ? (uint32_t)in[base + i] : 0u;
+  }
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan8_reduce(const uint8_t *in, size_t n,
+                                                               uint32_t *part) {
+  __shared__ uint32_t lds[kScanThreads / kWave];
+  uint32_t b[16];
+  load16(in, (size_t)blockIdx.x * kScan8Tile + (size_t)threadIdx.x * 16, n, b);
+  uint32_t acc = 0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc += b[i];
+  uint32_t tot;
+  block_excl_scan<uint32_t>(acc, tot, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan8_down(const uint8_t *in, uint32_t *out,
+                                                             size_t n, const uint32_t *block_off,
+                                                             uint32_t *total, size_t nblocks) {
+  __shared__ uint32_t lds[kScanThreads / kWave];
+  const size_t base = (size_t)blockIdx.x * kScan8Tile + (size_t)threadIdx.x * 16;
+  uint32_t b[16];
+  load16(in, base, n, b);
+  uint32_t acc = 0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const uint32_t v = b[i];
+    b[i] = acc;  // exclusive prefix inside the thread's 16
+    acc += v;
+  }
+  uint32_t tot;
+  const uint32_t run = (block_off ? block_off[blockIdx.x] : 0u) + block_excl_scan<uint32_t>(acc, tot, lds);
+  if (base + 16 <= n) {
+    uint4 *o = reinterpret_cast<uint4 *>(out + base);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      o[i] = make_uint4(run + b[4 * i], run + b[4 * i + 1], run + b[4 * i + 2], run + b[4 * i + 3]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (base + i < n) out[base + i] = run + b[i];
+  }
+  if (total && blockIdx.x == nblocks - 1 && threadIdx.x == kScanThreads - 1)
+    *total = (block_off ? block_off[blockIdx.x] : 0u) + tot;
+}
+
 void scan_u8_u32(const uint8_t *in, uint32_t *out, size_t n, uint32_t *total, Arena &ar,
                  hipStream_t s) {
-  scan_impl<uint8_t, uint32_t>(in, out, n, total, ar, s);
+  if (n == 0 || ((uintptr_t)in & 15u) || ((uintptr_t)out & 15u)) {
+    scan_impl<uint8_t, uint32_t>(in, out, n, total, ar, s);
+    return;
+  }
+  const size_t nb = (n + kScan8Tile - 1) / kScan8Tile;
+  if (nb == 1) {
+    k_scan8_down<<<1, kScanThreads, 0, s>>>(in, out, n, nullptr, total, 1);
+    return;
+  }
+  uint32_t *part = ar.get<uint32_t>(nb);
+  k_scan8_reduce<<<(unsigned)nb, kScanThreads, 0, s>>>(in, n, part);
+  scan_impl<uint32_t, uint32_t>(part, part, nb, (uint32_t *)nullptr, ar, s);
+  k_scan8_down<<<(unsigned)nb, kScanThreads, 0, s>>>(in, out, n, part, total, nb);
 }
 void scan_u32_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *total, Arena &ar,
                   hipStream_t s) {
