@@ -683,23 +683,28 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES)
         if (q + 64 < total) gather(col_nx, ax, ay, az);
         if (q + 128 < total) locate(q + 128, r_nx2, col_nx2);
         if (q < total) hit = eval(col, ox, oy, oz, S.px[r], S.py[r], S.pz[r], S.e[r], tx, ty, tz);
+        const uint64_t hb = __ballot(hit);
+        if (hb == 0) continue;  // no term of this chunk is nonzero
         S.tx[lane] = tx;
         S.ty[lane] = ty;
         S.tz[lane] = tz;
-        const uint64_t hb = __ballot(hit);
         wave_sync();
-        // the row's lane adds its terms that fall in this chunk, in order
+        // the row's lane adds its violated terms that fall in this chunk, in
+        // order (a satisfied constraint's +0.0 would leave the sum unchanged)
         const uint32_t a = vb > c0 ? vb : c0;
         const uint32_t b = vend < c0 + 64 ? vend : c0 + 64;
-        for (uint32_t t = a; t < b; ++t) {
-          gx += S.tx[t - c0];
-          gy += S.ty[t - c0];
-          gz += S.tz[t - c0];
-        }
         if (b > a) {
           const uint32_t wd = b - a;
           const uint64_t mask = (wd >= 64 ? ~0ull : ((1ull << wd) - 1ull)) << (a - c0);
-          hrow |= (hb & mask) != 0;
+          uint64_t mine = hb & mask;
+          hrow |= mine != 0;
+          while (mine) {
+            const int t = __builtin_ctzll(mine);
+            gx += S.tx[t];
+            gy += S.ty[t];
+            gz += S.tz[t];
+            mine &= mine - 1;
+          }
         }
         wave_sync();
       }
@@ -1096,24 +1101,31 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_rows(
         if (hit && o > er) loss += h * h;
         hit_once = hit && o > er;
       }
+      const uint64_t hb = __ballot(hit);
+      viol += (unsigned)__popcll(__ballot(hit_once));
+      if (hb == 0) continue;  // no term of this chunk is nonzero
       s_term[w][0][lane] = tx;
       s_term[w][1][lane] = ty;
       s_term[w][2][lane] = tz;
-      const uint64_t hb = __ballot(hit);
-      viol += (unsigned)__popcll(__ballot(hit_once));
       wave_sync();
-      // the owner adds the terms of its row that fall in this chunk, in order
+      // The owner adds the violated terms of its row that fall in this
+      // chunk, in order.  A satisfied constraint contributes +0.0, which
+      // leaves a running sum that starts at +0.0 bitwise unchanged, so
+      // skipping it gives the same sum as adding every term.
       const uint32_t a = vb > c0 ? vb : c0;
       const uint32_t b = vb + len < c0 + 64 ? vb + len : c0 + 64;
-      for (uint32_t t = a; t < b; ++t) {
-        gx += s_term[w][0][t - c0];
-        gy += s_term[w][1][t - c0];
-        gz += s_term[w][2][t - c0];
-      }
       if (b > a) {
         const uint32_t wd = b - a;
         const uint64_t mask = (wd >= 64 ? ~0ull : ((1ull << wd) - 1ull)) << (a - c0);
-        hrow |= (hb & mask) != 0;
+        uint64_t mine = hb & mask;
+        hrow |= mine != 0;
+        while (mine) {
+          const int t = __builtin_ctzll(mine);
+          gx += s_term[w][0][t];
+          gy += s_term[w][1][t];
+          gz += s_term[w][2][t];
+          mine &= mine - 1;
+        }
       }
       wave_sync();
     }
