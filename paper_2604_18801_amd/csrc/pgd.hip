@@ -296,12 +296,12 @@ void build_csr(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t, con
 }
 
 __global__ void k_pgd_init(const uint32_t *e_list, size_t ne, const float4 *pos, const float4 *rec,
-                           double *P0, float4 *xo, double *m, double *v) {
+                           double *P0, int stride, float4 *xo, double *m, double *v) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne;
        e += (size_t)gridDim.x * blockDim.x) {
     const uint32_t k = e_list[e];
     const float4 r = rec[k];
-    store_p(P0, e, (double)r.x, (double)r.y, (double)r.z);
+    store_p(P0, e, stride, (double)r.x, (double)r.y, (double)r.z);
     xo[e] = pos[k];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -312,8 +312,9 @@ __global__ void k_pgd_init(const uint32_t *e_list, size_t ne, const float4 *pos,
 }
 
 void launch_pgd_init(const uint32_t *e_list, size_t ne, const float4 *pos, const float4 *rec,
-                     double *P0, float4 *xo, double *m, double *v, hipStream_t s) {
-  if (ne) k_pgd_init<<<blocks_for(ne, 256, 65536), 256, 0, s>>>(e_list, ne, pos, rec, P0, xo, m, v);
+                     double *P0, int stride, float4 *xo, double *m, double *v, hipStream_t s) {
+  if (ne)
+    k_pgd_init<<<blocks_for(ne, 256, 65536), 256, 0, s>>>(e_list, ne, pos, rec, P0, stride, xo, m, v);
 }
 
 __global__ void k_loop_init(const JobDev *jobs, JobLoop *loop, int njobs, int32_t *n_active) {
@@ -380,7 +381,7 @@ constexpr uint32_t kChunkPerLane = 24;
 // calls with at most this many incidences per row on average take the
 // chunked-only kernel (k_pgd_rows)
 constexpr double kRowsKernelDegree = 12.0;
-static_assert(kPStride == 4, "k_pgd_rows reads the iterates as double4 records");
+bool pgd_rows_kernel(size_t ninc, size_t ne) { return (double)ninc <= kRowsKernelDegree * (double)ne; }
 
 // group of a tile (or of a finalize block): the last with base <= x
 template <typename T>
@@ -529,7 +530,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES)
         e = B.wl[eoff + w0 + lane];
         q0 = B.row_ptr[e];
         len = B.row_ptr[e + 1] - q0;
-        load_p(Pc, e, pex, pey, pez);
+        load_p(Pc, e, kPStrideStep, pex, pey, pez);
       }
       uint32_t incl = len;  // inclusive prefix sum of len over the wave
 #pragma unroll
@@ -622,7 +623,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES)
       return true;
     };
     auto gather = [&](uint32_t col, double &x, double &y, double &z) {
-      load_p(Pc, col & kColRow, x, y, z);
+      load_p(Pc, col & kColRow, kPStrideStep, x, y, z);
     };
     // this lane's rows [r0, r1) in the balanced walk: those whose first
     // incidence lies in [ta, tb)
@@ -825,7 +826,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES)
         // square-root sequences costs registers, hence occupancy
         __builtin_amdgcn_sched_barrier(0);
       }
-      store_p(Pn, e, np[0], np[1], np[2]);
+      store_p(Pn, e, kPStrideStep, np[0], np[1], np[2]);
       // a live row that has not yet done so marks itself and its partners hot
       mark = (moved || S.hit[lane] || state != 0) && hotv != 2;
       if (mark) B.hot[e] = 2;
@@ -960,8 +961,8 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_rows(
     const bool valid = lane < nrow;
     const JobDev &J = B.jobs[job];
     const int cur = (int)(t_step & 1);
-    const double4 *__restrict__ Pc = reinterpret_cast<const double4 *>(cur ? B.P1 : B.P0);
-    double4 *__restrict__ Pn = reinterpret_cast<double4 *>(cur ? B.P0 : B.P1);
+    const double *__restrict__ Pc = cur ? B.P1 : B.P0;
+    double *__restrict__ Pn = cur ? B.P0 : B.P1;
     const double L0 = J.L[0], L1 = J.L[1], L2 = J.L[2];
     const double h0 = J.hL[0], h1 = J.hL[1], h2 = J.hL[2];
     const double bm = J.bm, bp = J.bp, bm2 = J.bm2, bp2 = J.bp2;
@@ -974,7 +975,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_rows(
       e = B.wl[eoff + w0 + lane];
       q0 = B.row_ptr[e];
       len = B.row_ptr[e + 1] - q0;
-      pe = Pc[e];
+      load_p(Pc, e, kPStrideRows, pe.x, pe.y, pe.z);
     }
     uint32_t incl = len;  // inclusive prefix sum of len over the wave
 #pragma unroll
@@ -1025,7 +1026,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_rows(
     // two-deep pipeline: while chunk c is evaluated, the partner gather of
     // chunk c + 1 and the column entries of chunk c + 2 are in flight
     auto gather = [&](uint32_t col) {
-      const double *pp = reinterpret_cast<const double *>(Pc + (col & kColRow));
+      const double *pp = Pc + (size_t)kPStrideRows * (col & kColRow);
       return make_double3(pp[0], pp[1], pp[2]);
     };
     int r_nx = 0, r_nx2 = 0;
@@ -1175,7 +1176,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_rows(
         // square-root sequences costs registers, hence occupancy
         __builtin_amdgcn_sched_barrier(0);
       }
-      Pn[e] = make_double4(np[0], np[1], np[2], 0.0);
+      store_p(Pn, e, kPStrideRows, np[0], np[1], np[2]);
       // a live row that has not yet done so marks itself and its partners hot
       mark = (moved || hrow || state != 0) && hotv != 2;
       if (mark) B.hot[e] = 2;
@@ -1280,16 +1281,17 @@ struct RowPerm {
   double *nm, *nv;
   float4 *nxo;
   uint32_t *nhot, *ne_list, *nlen, *wl;
+  int stride;  // of the iterate records
 };
 
 __global__ void k_permute_rows(RowPerm R, size_t ne) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne;
        e += (size_t)gridDim.x * blockDim.x) {
     const uint32_t r = R.new_id[e];
-#pragma unroll
-    for (int k = 0; k < kPStride; ++k) {
-      R.nP0[(size_t)kPStride * r + k] = R.P0[(size_t)kPStride * e + k];
-      R.nP1[(size_t)kPStride * r + k] = R.P1[(size_t)kPStride * e + k];
+    const size_t S = (size_t)R.stride;
+    for (size_t k = 0; k < S; ++k) {
+      R.nP0[S * r + k] = R.P0[S * e + k];
+      R.nP1[S * r + k] = R.P1[S * e + k];
     }
     R.nxo[r] = R.xo[e];
 #pragma unroll
@@ -1351,8 +1353,9 @@ void renumber_hot(PgdBufs &b, uint32_t *&e_list, Arena &ar, hipStream_t s) {
   R.hot = b.hot;
   R.e_list = e_list;
   R.row_ptr = b.row_ptr;
-  R.nP0 = ar.get<double>(kPStride * ne);
-  R.nP1 = ar.get<double>(kPStride * ne);
+  R.stride = b.pstride;
+  R.nP0 = ar.get<double>((size_t)b.pstride * ne);
+  R.nP1 = ar.get<double>((size_t)b.pstride * ne);
   R.nm = ar.get<double>(3 * ne);
   R.nv = ar.get<double>(3 * ne);
   R.nxo = ar.get<float4>(ne);
@@ -1443,12 +1446,15 @@ void launch_pgd_step(const PgdGroups *g, const PgdBufs &b, hipStream_t s) {
   if (b.ne) {
     // the loss slots were sized for this many waves
     if (b.nwaves != pgd_step_waves(b.ne)) throw Error(-3, "PGD step grid differs from its loss slots");
-    // few incidences per row on average: the chunked kernel with the
-    // buffers as its argument; else the kernel with both evaluations
-    if ((double)b.ninc <= kRowsKernelDegree * (double)b.ne)
+    // few incidences per row on average (packed records): the chunked
+    // kernel with the buffers as its argument; else the kernel with both
+    // evaluations
+    if (b.pstride == kPStrideRows)
       k_pgd_rows<<<b.nwaves / kPgdWaves, 64 * kPgdWaves, 0, s>>>(b);
-    else
+    else if (b.pstride == kPStrideStep)
       k_pgd_step<<<b.nwaves / kPgdWaves, 64 * kPgdWaves, 0, s>>>(g);
+    else
+      throw Error(-3, "PGD iterate records of an unknown size");
   }
 }
 void launch_pgd_finalize(const PgdGroups *g, const PgdBufs &b, hipStream_t s) {
