@@ -218,6 +218,68 @@ __device__ inline int classify(const JobPair &q, const float4 &pi, const float4 
   return d2 <= q.rs2 ? kSafe : (d2 <= q.b2 ? kPb : kPc);
 }
 
+// Float32 squared distance from a home to a partner staged with the image
+// shift of its range already added (ps = pj + shift, rounded once per
+// staged partner): per axis pi - ps, again two roundings, and the squares
+// summed with fused multiply-adds.  Its error stays inside the bound of the
+// guard bands (one and a half float32 ulps per axis of max|x| + L + 1).
+__device__ inline float dist2_staged(const JobPair &q, const float4 &pi, const float4 &ps) {
+  float dx = pi.x - ps.x, dy = pi.y - ps.y, dz = pi.z - ps.z;
+  if (!q.img) {
+    dx = wrap_f(dx, q.Lf[0], q.hLf[0]);
+    dy = wrap_f(dy, q.Lf[1], q.hLf[1]);
+    dz = wrap_f(dz, q.Lf[2], q.hLf[2]);
+  }
+  return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+}
+// class from such a distance; inside a band the exact predicate decides on
+// the partner's unshifted position
+__device__ inline int class_staged(const JobPair &q, float d2f, const float4 &pi,
+                                   const float4 *pos, uint32_t j) {
+  if (d2f > q.f_rv_hi) return kNone;
+  if (d2f < q.f_rs_lo) return kSafe;
+  if (d2f > q.f_rs_hi && d2f < q.f_b_lo) return kPb;
+  if (d2f > q.f_b_hi && d2f < q.f_rv_lo) return kPc;
+  const double d2 = dist2_exact(pi, pos[j], q);
+  if (d2 > q.rv2) return kNone;
+  return d2 <= q.rs2 ? kSafe : (d2 <= q.b2 ? kPb : kPc);
+}
+
+// Box of a wave's home positions, and the test that drops a staged partner
+// no home of the box can reach.  Per axis the partner's float32 gap to the
+// box, fl(lo - ps) or fl(ps - hi), is at most |fl(h - ps)| for every home h
+// in the box (rounding is monotonic), and the fused sum of squares is
+// monotonic in each term, so a gap-distance above the r_v band's upper edge
+// means every home's dist2_staged lies above it too, i.e. every exact
+// distance exceeds r_v.  Only for jobs whose candidates are not wrapped.
+struct HomeBox {
+  float lo[3], hi[3];
+};
+__device__ inline HomeBox home_box(const float4 &pi, bool valid) {
+  const float inf = __builtin_huge_valf();
+  HomeBox b;
+  b.lo[0] = valid ? pi.x : inf;
+  b.lo[1] = valid ? pi.y : inf;
+  b.lo[2] = valid ? pi.z : inf;
+  b.hi[0] = valid ? pi.x : -inf;
+  b.hi[1] = valid ? pi.y : -inf;
+  b.hi[2] = valid ? pi.z : -inf;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      b.lo[a] = fminf(b.lo[a], __shfl_xor(b.lo[a], d, kWave));
+      b.hi[a] = fmaxf(b.hi[a], __shfl_xor(b.hi[a], d, kWave));
+    }
+  return b;
+}
+__device__ inline bool box_reaches(const JobPair &q, const HomeBox &b, const float4 &ps) {
+  const float ex = fmaxf(fmaxf(b.lo[0] - ps.x, ps.x - b.hi[0]), 0.f);
+  const float ey = fmaxf(fmaxf(b.lo[1] - ps.y, ps.y - b.hi[1]), 0.f);
+  const float ez = fmaxf(fmaxf(b.lo[2] - ps.z, ps.z - b.hi[2]), 0.f);
+  return __builtin_fmaf(ez, ez, __builtin_fmaf(ey, ey, ex * ex)) <= q.f_rv_hi;
+}
+
 // State of one home particle k during a pass.
 struct Home {
   uint32_t k;
@@ -306,9 +368,8 @@ __device__ inline uint64_t forest_key(const PairBufs &B, const JobPair &q, const
 // ever moves to an ancestor, so a stale value equal to the home's root guess
 // still means both are in one set, and any other value leads to a union.
 template <int PASS, bool STAGED>
-__device__ inline void visit(const PairBufs &B, const JobPair &q, Home &h, uint32_t j,
-                             const float4 &pj, const float3 &sh, uint32_t sj, uint32_t fj) {
-  const int cls = classify(q, h.pi, pj, sh);
+__device__ inline void visit_class(const PairBufs &B, const JobPair &q, Home &h, uint32_t j,
+                                   const float4 &pj, int cls, uint32_t sj, uint32_t fj) {
   if (cls == kNone) return;
   auto spar = [&]() { return STAGED ? sj : B.safe_par[j]; };
   auto fpar = [&]() { return STAGED ? fj : B.fof_par[j]; };
@@ -349,6 +410,12 @@ __device__ inline void visit(const PairBufs &B, const JobPair &q, Home &h, uint3
     B.f_v[h.wf] = spj;
     h.wf++;
   }
+}
+
+template <int PASS, bool STAGED>
+__device__ inline void visit(const PairBufs &B, const JobPair &q, Home &h, uint32_t j,
+                             const float4 &pj, const float3 &sh, uint32_t sj, uint32_t fj) {
+  visit_class<PASS, STAGED>(B, q, h, j, pj, classify(q, h.pi, pj, sh), sj, fj);
 }
 
 __device__ inline void pass1_counts(const Home &h, bool valid, unsigned long long (&cnt)[3]) {
@@ -431,6 +498,35 @@ __global__ void __launch_bounds__(kSparseThreads) k_pairs_sparse(PairBufs B, con
 
 constexpr int kPairWaves = 4;
 
+// Stages the partners t0 .. t0 + cnt - 1 of a dense unit in LDS, each lane
+// loading one: its position with the range's image shift added, both
+// parents and its index.  With `cull` (a neighbour range of a job whose
+// candidates are not wrapped), a partner that no home of the unit's box
+// can reach is left out; the others keep their order.  Returns how many
+// were staged.
+__device__ inline uint32_t stage_partners(const PairBufs &B, const JobPair &q, const HomeBox &box,
+                                          bool cull, uint32_t t0, uint32_t cnt, const float3 &sh,
+                                          int lane, uint64_t below, float4 *stage, uint32_t *ssp,
+                                          uint32_t *sfp, uint32_t *sidx) {
+  bool keep = false;
+  float4 ps = make_float4(0.f, 0.f, 0.f, 0.f);
+  if ((uint32_t)lane < cnt) {
+    const float4 p = B.pos[t0 + lane];
+    ps = make_float4(p.x + sh.x, p.y + sh.y, p.z + sh.z, p.w);
+    keep = !(cull && q.img) || box_reaches(q, box, ps);
+  }
+  const uint64_t km = __ballot(keep);
+  if (keep) {
+    const uint32_t d = (uint32_t)__popcll(km & below);
+    stage[d] = ps;
+    ssp[d] = B.safe_par[t0 + lane];
+    sfp[d] = B.fof_par[t0 + lane];
+    sidx[d] = t0 + lane;
+  }
+  wave_sync();
+  return (uint32_t)__popcll(km);
+}
+
 // Dense cells: one wave per 64 home particles of one cell.  Each neighbour
 // range (a run of forward cells with consecutive keys) is staged through
 // LDS 64 particles at a time with coalesced loads (positions and both
@@ -442,7 +538,7 @@ template <int PASS>
 __global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense(PairBufs B, const uint32_t *ucell,
                                                                  const uint32_t *uchunk, size_t m) {
   __shared__ float4 stage[kPairWaves][64];
-  __shared__ uint32_t ssp[kPairWaves][64], sfp[kPairWaves][64];
+  __shared__ uint32_t ssp[kPairWaves][64], sfp[kPairWaves][64], sidx[kPairWaves][64];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const size_t unit = (size_t)blockIdx.x * kPairWaves + w;
   if (unit >= m) return;  // the whole wave leaves together
@@ -456,6 +552,8 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense(PairBufs B, con
   const uint32_t edge = B.cell_edge[cell];
   Home h;
   home_begin<PASS>(B, h, valid ? k0 + lane : k0);
+  const HomeBox box = home_box(h.pi, valid);
+  const uint64_t below = (1ull << lane) - 1ull;
   for (int s = 0; s <= kNbrSlots; ++s) {
     uint32_t j0, j1;
     float3 sh = make_float3(0.f, 0.f, 0.f);
@@ -471,17 +569,22 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense(PairBufs B, con
     }
     for (uint32_t t0 = j0; t0 < j1; t0 += 64) {
       const uint32_t cnt_t = (j1 - t0) < 64u ? (j1 - t0) : 64u;
-      if ((uint32_t)lane < cnt_t) {
-        stage[w][lane] = B.pos[t0 + lane];
-        ssp[w][lane] = B.safe_par[t0 + lane];
-        sfp[w][lane] = B.fof_par[t0 + lane];
-      }
-      wave_sync();
+      const uint32_t nk = stage_partners(B, q, box, s > 0, t0, cnt_t, sh, lane, below, stage[w],
+                                         ssp[w], sfp[w], sidx[w]);
       if (valid) {
-        // in the home cell only the partners after k
-        const uint32_t tb = (s == 0 && h.k >= t0) ? (h.k + 1 - t0) : 0u;
-        for (uint32_t t = tb; t < cnt_t; ++t)
-          visit<PASS, true>(B, q, h, t0 + t, stage[w][t], sh, ssp[w][t], sfp[w][t]);
+        auto one = [&](uint32_t t) {
+          const float4 ps = stage[w][t];
+          const uint32_t j = sidx[w][t];
+          visit_class<PASS, true>(B, q, h, j, ps,
+                                  class_staged(q, dist2_staged(q, h.pi, ps), h.pi, B.pos, j),
+                                  ssp[w][t], sfp[w][t]);
+        };
+        if (s == 0) {
+          // the home cell is staged whole: only the partners after k
+          for (uint32_t t = h.k >= t0 ? h.k + 1 - t0 : 0u; t < nk; ++t) one(t);
+        } else {
+          for (uint32_t t = 0; t < nk; ++t) one(t);
+        }
       }
       wave_sync();
     }
@@ -505,7 +608,7 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense_write(PairBufs 
                                                                        const uint32_t *uchunk,
                                                                        size_t m) {
   __shared__ float4 stage[kPairWaves][64];
-  __shared__ uint32_t ssp[kPairWaves][64], sfp[kPairWaves][64];
+  __shared__ uint32_t ssp[kPairWaves][64], sfp[kPairWaves][64], sidx[kPairWaves][64];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const size_t unit = (size_t)blockIdx.x * kPairWaves + w;
   if (unit >= m) return;  // the whole wave leaves together
@@ -519,6 +622,7 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense_write(PairBufs 
   const uint32_t edge = B.cell_edge[cell];
   Home h;
   home_begin<3>(B, h, valid ? k0 + lane : k0);
+  const HomeBox box = home_box(h.pi, valid);
   const uint64_t a0 = B.off_a[k0], f0 = B.off_f[k0];
   uint64_t wa = a0, wf = f0;
   const uint64_t below = (1ull << lane) - 1ull;
@@ -537,19 +641,15 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense_write(PairBufs 
     }
     for (uint32_t t0 = j0; t0 < j1; t0 += 64) {
       const uint32_t cnt_t = (j1 - t0) < 64u ? (j1 - t0) : 64u;
-      if ((uint32_t)lane < cnt_t) {
-        stage[w][lane] = B.pos[t0 + lane];
-        ssp[w][lane] = B.safe_par[t0 + lane];
-        sfp[w][lane] = B.fof_par[t0 + lane];
-      }
-      wave_sync();
-      for (uint32_t t = 0; t < cnt_t; ++t) {
-        const uint32_t j = t0 + t;
+      const uint32_t nk = stage_partners(B, q, box, s > 0, t0, cnt_t, sh, lane, below, stage[w],
+                                         ssp[w], sfp[w], sidx[w]);
+      for (uint32_t t = 0; t < nk; ++t) {
+        const uint32_t j = sidx[w][t];
         const float4 pj = stage[w][t];
         int cls = kNone;
         bool ta = false, tf = false;
         if (valid && !(s == 0 && j <= h.k)) {
-          cls = classify(q, h.pi, pj, sh);
+          cls = class_staged(q, dist2_staged(q, h.pi, pj), h.pi, B.pos, j);
           mode_filter(q, h, cls, ssp[w][t], sfp[w][t], ta, tf);
         }
         const uint64_t ba = __ballot(ta), bf = __ballot(tf);

@@ -162,6 +162,24 @@ def test_pair_classes_at_the_thresholds(ctx, layout, mode):
     assert ref.stats["n_pb"] > 0 and ref.stats["n_pc"] > 0 and ref.stats["n_safe"] > 0
 
 
+@pytest.mark.parametrize("layout", ["box", "shifted", "open"])
+def test_pair_classes_at_the_thresholds_in_dense_units(ctx, layout):
+    """The same pairs with every cell taken as a dense unit: partners are
+    staged with their image shift added and culled against the box of the
+    unit's homes, so the pairs right at r_v test that no partner within r_v
+    of a home is dropped."""
+    old = ctx.get_option("dense_cell")
+    ctx.set_option("dense_cell", 1)
+    try:
+        w = _threshold_pairs(layout, seed=11)
+        for mode in ("vp", "hf"):
+            print("case thr dense", layout, mode, flush=True)
+            ref, stream, st = _compare(ctx, w, mode)
+            assert ref.stats["n_pc"] > 0
+    finally:
+        ctx.set_option("dense_cell", old)
+
+
 @pytest.mark.parametrize("m", [8, 32])
 def test_bit_depths(ctx, m):
     import paper_2604_18801_amd as pcc
