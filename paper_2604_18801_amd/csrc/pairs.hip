@@ -1051,6 +1051,167 @@ __global__ void k_bor_compact(const uint64_t *key, const uint32_t *ru, const uin
   }
 }
 
+// Chunk-local spanning forests.  An edge that is not in the minimum
+// spanning forest of some subset of the edges is the heaviest edge of a
+// cycle inside that subset, so (cycle property) it is not in the forest of
+// the whole graph either.  Each block takes kLocalEdges consecutive
+// candidates (neighbouring homes, whose links close many triangles), finds
+// their own minimum spanning forest by Boruvka rounds in LDS, and moves its
+// edges to the front of its chunk; only those enter the global rounds.
+// Within one job the keys of a component's edges are distinct (one key per
+// particle pair), so every round's minimum edges form a forest.  Endpoints
+// get local ids from an open-addressing table in LDS (at most
+// 2 kLocalEdges values in kLocalSlots slots, so an insert always succeeds).
+constexpr int kLocalEdges = 1024, kLocalThreads = 256, kLocalSlots = 2 * kLocalEdges;
+constexpr int kLocalPer = kLocalEdges / kLocalThreads;
+
+__device__ inline uint32_t lds_find(uint32_t *par, uint32_t x) {
+  for (;;) {
+    const uint32_t p = __hip_atomic_load(par + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (p == x) return x;
+    x = p;
+  }
+}
+// hook the larger root under the smaller one (parents only ever decrease)
+__device__ inline void lds_union(uint32_t *par, uint32_t a, uint32_t b) {
+  a = lds_find(par, a);
+  b = lds_find(par, b);
+  while (a != b) {
+    const uint32_t hi = a > b ? a : b, lo = a > b ? b : a;
+    uint32_t seen = hi;
+    if (__hip_atomic_compare_exchange_strong(par + hi, &seen, lo, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+      return;
+    a = lds_find(par, seen);
+    b = lds_find(par, lo);
+  }
+}
+// slot of value x in the table (inserted if absent)
+__device__ inline uint32_t lds_slot(uint32_t *tab, uint32_t x) {
+  uint32_t h = (x * 2654435761u) >> (32 - 11);
+  static_assert(kLocalSlots == 1 << 11, "hash width");
+  for (;;) {
+    uint32_t seen = 0xffffffffu;
+    if (__hip_atomic_compare_exchange_strong(tab + h, &seen, x, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) ||
+        seen == x)
+      return h;
+    h = (h + 1) & (kLocalSlots - 1);
+  }
+}
+
+__global__ void __launch_bounds__(kLocalThreads) k_forest_local(uint64_t *key, uint32_t *u,
+                                                                uint32_t *v, size_t m,
+                                                                uint32_t *nkept) {
+  __shared__ uint32_t tab[kLocalSlots];              // endpoint values
+  __shared__ uint32_t par[kLocalSlots];              // parents of the slots
+  __shared__ unsigned long long best[kLocalSlots];   // lightest edge of each component
+  __shared__ uint32_t wsum[kLocalThreads / kWave];
+  const int tid = threadIdx.x;
+  const size_t c0 = (size_t)blockIdx.x * kLocalEdges;
+  const uint32_t ne = (uint32_t)(m - c0 < (size_t)kLocalEdges ? m - c0 : (size_t)kLocalEdges);
+  uint32_t ea[kLocalPer], eb[kLocalPer], eu[kLocalPer], ev[kLocalPer];
+  unsigned long long ek[kLocalPer];
+  uint32_t live = 0, sel = 0;
+  for (uint32_t x = (uint32_t)tid; x < (uint32_t)kLocalSlots; x += kLocalThreads) {
+    tab[x] = 0xffffffffu;
+    par[x] = x;
+  }
+#pragma unroll
+  for (int r = 0; r < kLocalPer; ++r) {
+    const uint32_t i = (uint32_t)tid + (uint32_t)r * kLocalThreads;
+    ea[r] = eb[r] = 0u;
+    ek[r] = ~0ull;
+    if (i < ne) {
+      ea[r] = u[c0 + i];
+      eb[r] = v[c0 + i];
+      ek[r] = key[c0 + i];
+      if (ea[r] != eb[r]) live |= 1u << r;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kLocalPer; ++r) {
+    eu[r] = ev[r] = 0u;
+    if ((live >> r) & 1u) {
+      eu[r] = lds_slot(tab, ea[r]);
+      ev[r] = lds_slot(tab, eb[r]);
+    }
+  }
+  __syncthreads();
+  for (;;) {
+    for (uint32_t x = (uint32_t)tid; x < (uint32_t)kLocalSlots; x += kLocalThreads) best[x] = ~0ull;
+    __syncthreads();
+    uint32_t ru[kLocalPer], rv[kLocalPer];
+#pragma unroll
+    for (int r = 0; r < kLocalPer; ++r) {
+      ru[r] = par[eu[r]];  // flattened: the root
+      rv[r] = par[ev[r]];
+      if (!((live >> r) & 1u)) continue;
+      if (ru[r] == rv[r]) {
+        live &= ~(1u << r);
+        continue;
+      }
+      atomicMin(best + ru[r], ek[r]);
+      atomicMin(best + rv[r], ek[r]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kLocalPer; ++r) {
+      if (!((live >> r) & 1u)) continue;
+      if (best[ru[r]] == ek[r] || best[rv[r]] == ek[r]) {
+        sel |= 1u << r;
+        live &= ~(1u << r);
+        lds_union(par, ru[r], rv[r]);
+      }
+    }
+    __syncthreads();
+    for (uint32_t x = (uint32_t)tid; x < (uint32_t)kLocalSlots; x += kLocalThreads)
+      par[x] = lds_find(par, x);
+    if (!__syncthreads_or(live != 0)) break;
+  }
+  // the chunk's forest edges to the front of the chunk (every read of the
+  // chunk happened above), in thread order
+  const uint32_t mine = (uint32_t)__popc(sel);
+  uint32_t incl = mine;
+  const int lane = tid & 63, w = tid >> 6;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(incl, d, kWave);
+    if (lane >= d) incl += y;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  uint32_t base = 0, total = 0;
+  for (int q = 0; q < kLocalThreads / kWave; ++q) {
+    if (q < w) base += wsum[q];
+    total += wsum[q];
+  }
+  uint32_t at = base + incl - mine;
+#pragma unroll
+  for (int r = 0; r < kLocalPer; ++r)
+    if ((sel >> r) & 1u) {
+      key[c0 + at] = ek[r];
+      u[c0 + at] = ea[r];
+      v[c0 + at] = eb[r];
+      ++at;
+    }
+  if (tid == 0) nkept[blockIdx.x] = total;
+}
+
+// the kept fronts of the chunks, back to back
+__global__ void k_forest_gather(const uint64_t *key, const uint32_t *u, const uint32_t *v,
+                                const uint32_t *nkept, const uint32_t *off, uint64_t *nkey,
+                                uint32_t *nu, uint32_t *nv) {
+  const size_t c0 = (size_t)blockIdx.x * kLocalEdges;
+  const uint32_t k = nkept[blockIdx.x], o = off[blockIdx.x];
+  for (uint32_t i = threadIdx.x; i < k; i += blockDim.x) {
+    nkey[o + i] = key[c0 + i];
+    nu[o + i] = u[c0 + i];
+    nv[o + i] = v[c0 + i];
+  }
+}
+
 int64_t boruvka(uint64_t *key, uint32_t *u, uint32_t *v, size_t ncand, uint32_t *bpar, size_t n,
                 const uint32_t *inv_perm, const int64_t *p_off, int njobs, uint32_t *out_i,
                 uint32_t *out_j, uint8_t *out_t, Arena &ar, hipStream_t s) {
@@ -1070,6 +1231,22 @@ int64_t boruvka(uint64_t *key, uint32_t *u, uint32_t *v, size_t ncand, uint32_t 
   int64_t emitted = 0;
   size_t m = ncand;
   try {
+    {
+      // the chunk-local forests' edges only
+      const size_t nch = (m + kLocalEdges - 1) / kLocalEdges;
+      uint32_t *nkept = ar.get<uint32_t>(nch), *off = ar.get<uint32_t>(nch);
+      k_forest_local<<<(unsigned)nch, kLocalThreads, 0, s>>>(key, u, v, m, nkept);
+      scan_u32_u32(nkept, off, nch, cnt, ar, s);
+      k_forest_gather<<<(unsigned)nch, 128, 0, s>>>(key, u, v, nkept, off, key2, u2, v2);
+      PCC_HIP(hipMemcpyAsync(hcnt, cnt, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      PCC_HIP(hipStreamSynchronize(s));
+      if (getenv("PCC_VERBOSE"))
+        fprintf(stderr, "[pcc] forest: %zu candidates, %u in chunk-local forests\n", m, hcnt[0]);
+      m = hcnt[0];
+      std::swap(key, key2);
+      std::swap(u, u2);
+      std::swap(v, v2);
+    }
     while (m > 0) {
       const int nb = blocks_for(m, 256, 65536);
       fill_u64((uint64_t *)best, ~0ull, n, s);
