@@ -1065,11 +1065,16 @@ __global__ void k_bor_compact(const uint64_t *key, const uint32_t *ru, const uin
 constexpr int kLocalEdges = 1024, kLocalThreads = 256, kLocalSlots = 2 * kLocalEdges;
 constexpr int kLocalPer = kLocalEdges / kLocalThreads;
 
+// root of x, halving the path (a non-root's parent only ever moves to an
+// ancestor, so the store is safe beside concurrent hooks of roots)
 __device__ inline uint32_t lds_find(uint32_t *par, uint32_t x) {
   for (;;) {
     const uint32_t p = __hip_atomic_load(par + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (p == x) return x;
-    x = p;
+    const uint32_t g = __hip_atomic_load(par + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (g == p) return p;
+    __hip_atomic_store(par + x, g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    x = g;
   }
 }
 // hook the larger root under the smaller one (parents only ever decrease)
@@ -1103,10 +1108,12 @@ __device__ inline uint32_t lds_slot(uint32_t *tab, uint32_t x) {
 __global__ void __launch_bounds__(kLocalThreads) k_forest_local(uint64_t *key, uint32_t *u,
                                                                 uint32_t *v, size_t m,
                                                                 uint32_t *nkept) {
-  __shared__ uint32_t tab[kLocalSlots];              // endpoint values
-  __shared__ uint32_t par[kLocalSlots];              // parents of the slots
+  // the endpoint table is needed only until every end has its slot; the
+  // lightest edge per component takes its place afterwards
   __shared__ unsigned long long best[kLocalSlots];   // lightest edge of each component
+  __shared__ uint32_t par[kLocalSlots];              // parents of the slots
   __shared__ uint32_t wsum[kLocalThreads / kWave];
+  uint32_t *tab = reinterpret_cast<uint32_t *>(best);  // endpoint values
   const int tid = threadIdx.x;
   const size_t c0 = (size_t)blockIdx.x * kLocalEdges;
   const uint32_t ne = (uint32_t)(m - c0 < (size_t)kLocalEdges ? m - c0 : (size_t)kLocalEdges);
@@ -1140,21 +1147,28 @@ __global__ void __launch_bounds__(kLocalThreads) k_forest_local(uint64_t *key, u
   }
   __syncthreads();
   for (;;) {
-    for (uint32_t x = (uint32_t)tid; x < (uint32_t)kLocalSlots; x += kLocalThreads) best[x] = ~0ull;
-    __syncthreads();
+    // roots of the live edges' ends; their components' minima start empty
     uint32_t ru[kLocalPer], rv[kLocalPer];
 #pragma unroll
     for (int r = 0; r < kLocalPer; ++r) {
-      ru[r] = par[eu[r]];  // flattened: the root
-      rv[r] = par[ev[r]];
+      ru[r] = rv[r] = 0u;
       if (!((live >> r) & 1u)) continue;
+      ru[r] = lds_find(par, eu[r]);
+      rv[r] = lds_find(par, ev[r]);
       if (ru[r] == rv[r]) {
         live &= ~(1u << r);
         continue;
       }
-      atomicMin(best + ru[r], ek[r]);
-      atomicMin(best + rv[r], ek[r]);
+      best[ru[r]] = ~0ull;
+      best[rv[r]] = ~0ull;
     }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kLocalPer; ++r)
+      if ((live >> r) & 1u) {
+        atomicMin(best + ru[r], ek[r]);
+        atomicMin(best + rv[r], ek[r]);
+      }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kLocalPer; ++r) {
@@ -1165,9 +1179,6 @@ __global__ void __launch_bounds__(kLocalThreads) k_forest_local(uint64_t *key, u
         lds_union(par, ru[r], rv[r]);
       }
     }
-    __syncthreads();
-    for (uint32_t x = (uint32_t)tid; x < (uint32_t)kLocalSlots; x += kLocalThreads)
-      par[x] = lds_find(par, x);
     if (!__syncthreads_or(live != 0)) break;
   }
   // the chunk's forest edges to the front of the chunk (every read of the
