@@ -361,6 +361,19 @@ __device__ inline uint64_t forest_key(const PairBufs &B, const JobPair &q, const
   return (viol0 << 62) | (lo << 31) | hi;
 }
 
+// The same key from the home's reconstructed position and job-local index
+// (the write pass's queued candidates carry the home's lane, not its state).
+__device__ inline uint64_t forest_key_of(const PairBufs &B, const JobPair &q, const float4 &ri,
+                                         uint32_t li, uint32_t j, uint32_t lj) {
+  const float4 rj = B.rec[j];
+  const double ex = wrap_d((double)ri.x - (double)rj.x, q.L[0], q.hL[0]);
+  const double ey = wrap_d((double)ri.y - (double)rj.y, q.L[1], q.hL[1]);
+  const double ez = wrap_d((double)ri.z - (double)rj.z, q.L[2], q.hL[2]);
+  const uint64_t viol0 = ((ex * ex + ey * ey) + ez * ez) > q.bm2 ? 1ull : 0ull;
+  const uint64_t lo = li < lj ? li : lj, hi = li < lj ? lj : li;
+  return (viol0 << 62) | (lo << 31) | hi;
+}
+
 // One candidate partner j of the home particle: its class, then the work of
 // the pass.  With STAGED the partner's parents come from the caller (staged
 // with its position), else they are read when needed.  In pass 1 a parent
@@ -609,6 +622,12 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense_write(PairBufs 
                                                                        size_t m) {
   __shared__ float4 stage[kPairWaves][64];
   __shared__ uint32_t ssp[kPairWaves][64], sfp[kPairWaves][64], sidx[kPairWaves][64];
+  // forest candidates wait in a queue (home lane | staged index << 6, in
+  // the order partner, home lane) and are keyed and stored 64 at a time with
+  // every lane busy, instead of by the few lanes that find one per partner
+  __shared__ uint16_t fq[kPairWaves][128];
+  __shared__ float4 hri[kPairWaves][64];  // the homes' reconstructed positions
+  __shared__ uint32_t hsk[kPairWaves][64], hli[kPairWaves][64];  // safe roots, local ids
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const size_t unit = (size_t)blockIdx.x * kPairWaves + w;
   if (unit >= m) return;  // the whole wave leaves together
@@ -626,6 +645,22 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense_write(PairBufs 
   const uint64_t a0 = B.off_a[k0], f0 = B.off_f[k0];
   uint64_t wa = a0, wf = f0;
   const uint64_t below = (1ull << lane) - 1ull;
+  hri[w][lane] = h.ri;
+  hsk[w][lane] = h.sk;
+  hli[w][lane] = __float_as_uint(h.pi.w);
+  uint32_t qn = 0;  // queued forest candidates (wave-uniform)
+  // keys and stores the first cnt (<= 64) queued candidates
+  auto flush = [&](uint32_t cnt) {
+    if ((uint32_t)lane < cnt) {
+      const uint32_t e = fq[w][lane], hl = e & 63u, t = e >> 6;
+      const uint32_t j = sidx[w][t];
+      const uint64_t d = wf + (uint64_t)lane;
+      B.f_key[d] = forest_key_of(B, q, hri[w][hl], hli[w][hl], j, __float_as_uint(stage[w][t].w));
+      B.f_u[d] = hsk[w][hl];
+      B.f_v[d] = ssp[w][t];
+    }
+    wf += cnt;
+  };
   for (int s = 0; s <= kNbrSlots; ++s) {
     uint32_t j0, j1;
     float3 sh = make_float3(0.f, 0.f, 0.f);
@@ -659,15 +694,25 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense_write(PairBufs 
           B.a_j[d] = j;
           B.a_t[d] = (uint8_t)cls;
         }
-        if (tf) {
-          const uint64_t d = wf + (uint64_t)__popcll(bf & below);
-          B.f_key[d] = forest_key(B, q, h, j, pj);
-          B.f_u[d] = h.sk;
-          B.f_v[d] = ssp[w][t];
-        }
         wa += (uint64_t)__popcll(ba);
-        wf += (uint64_t)__popcll(bf);
+        if (bf) {
+          if (tf) fq[w][qn + (uint32_t)__popcll(bf & below)] = (uint16_t)((uint32_t)lane | (t << 6));
+          qn += (uint32_t)__popcll(bf);
+          if (qn >= 64) {
+            wave_sync();
+            flush(64);
+            const uint32_t rest = qn - 64;  // below 64
+            const uint16_t mv = (uint32_t)lane < rest ? fq[w][64 + lane] : (uint16_t)0;
+            wave_sync();
+            if ((uint32_t)lane < rest) fq[w][lane] = mv;
+            qn = rest;
+          }
+        }
       }
+      // the staged partners are replaced next: key the queue's rest now
+      wave_sync();
+      flush(qn);
+      qn = 0;
       wave_sync();
     }
   }
