@@ -375,17 +375,18 @@ __device__ inline uint64_t forest_key_of(const PairBufs &B, const JobPair &q, co
 }
 
 // One candidate partner j of the home particle: its class, then the work of
-// the pass.  With STAGED the partner's parents come from the caller (staged
-// with its position), else they are read when needed.  In pass 1 a parent
+// the pass.  STAGED says which of the partner's parents come from the caller
+// (bit 0 the safe parent, bit 1 the FoF parent: staged or loaded ahead with
+// its position); the others are read when needed.  In pass 1 a parent
 // only serves to skip a union that is already done: a node's parent only
 // ever moves to an ancestor, so a stale value equal to the home's root guess
 // still means both are in one set, and any other value leads to a union.
-template <int PASS, bool STAGED>
+template <int PASS, int STAGED>
 __device__ inline void visit_class(const PairBufs &B, const JobPair &q, Home &h, uint32_t j,
                                    const float4 &pj, int cls, uint32_t sj, uint32_t fj) {
   if (cls == kNone) return;
-  auto spar = [&]() { return STAGED ? sj : B.safe_par[j]; };
-  auto fpar = [&]() { return STAGED ? fj : B.fof_par[j]; };
+  auto spar = [&]() { return (STAGED & 1) ? sj : B.safe_par[j]; };
+  auto fpar = [&]() { return (STAGED & 2) ? fj : B.fof_par[j]; };
   if (PASS == 1) {
     // h.sk / h.fk hold an ancestor of k in each forest: a partner whose
     // parent is that node is already in k's set and needs no union
@@ -425,7 +426,7 @@ __device__ inline void visit_class(const PairBufs &B, const JobPair &q, Home &h,
   }
 }
 
-template <int PASS, bool STAGED>
+template <int PASS, int STAGED>
 __device__ inline void visit(const PairBufs &B, const JobPair &q, Home &h, uint32_t j,
                              const float4 &pj, const float3 &sh, uint32_t sj, uint32_t fj) {
   visit_class<PASS, STAGED>(B, q, h, j, pj, classify(q, h.pi, pj, sh), sj, fj);
@@ -489,19 +490,28 @@ __global__ void __launch_bounds__(kSparseThreads) k_pairs_sparse(PairBufs B, con
     float3 sh = make_float3(0.f, 0.f, 0.f);
     enter(0, j, e, sh);
     while (j >= e && ++r < kRanges) enter(r, j, e, sh);
-    float4 pj = B.pos[r < kRanges ? j : k];  // (index k: any valid load)
+    // the partner's position and parents are loaded one candidate ahead (the
+    // FoF parent in pass 1, where the safe one is rarely needed; both after)
+    constexpr int kAhead = PASS == 1 ? 2 : 3;
+    uint32_t ja = r < kRanges ? j : k;  // (index k: any valid load)
+    float4 pj = B.pos[ja];
+    uint32_t sj = (kAhead & 1) ? B.safe_par[ja] : 0u, fj = B.fof_par[ja];
     while (r < kRanges) {
       uint32_t jn = j + 1, en = e;
       int rn = r;
       float3 shn = sh;
       while (jn >= en && ++rn < kRanges) enter(rn, jn, en, shn);
-      const float4 pn = B.pos[rn < kRanges ? jn : k];
-      visit<PASS, false>(B, q, h, j, pj, sh, 0u, 0u);
+      ja = rn < kRanges ? jn : k;
+      const float4 pn = B.pos[ja];
+      const uint32_t sn = (kAhead & 1) ? B.safe_par[ja] : 0u, fn = B.fof_par[ja];
+      visit<PASS, kAhead>(B, q, h, j, pj, sh, sj, fj);
       j = jn;
       e = en;
       r = rn;
       sh = shn;
       pj = pn;
+      sj = sn;
+      fj = fn;
     }
     home_end<PASS>(B, h);
     if (PASS == 1) pass1_counts(h, true, cnt);
@@ -588,7 +598,7 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pairs_dense(PairBufs B, con
         auto one = [&](uint32_t t) {
           const float4 ps = stage[w][t];
           const uint32_t j = sidx[w][t];
-          visit_class<PASS, true>(B, q, h, j, ps,
+          visit_class<PASS, 3>(B, q, h, j, ps,
                                   class_staged(q, dist2_staged(q, h.pi, ps), h.pi, B.pos, j),
                                   ssp[w][t], sfp[w][t]);
         };
