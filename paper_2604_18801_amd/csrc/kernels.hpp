@@ -106,10 +106,10 @@ int64_t boruvka(uint64_t *key, uint32_t *u, uint32_t *v, size_t ncand, uint32_t 
 
 // pgd.hip
 // Iterates of the PGD loop: one record of x, y, z float64 per editable row.
-// A call whose rows hold few incidences (the chunked-only step kernel, which
-// streams rows) packs the records into 24 bytes; the others pad them to 32,
-// so a partner gather is one 16-byte and one 8-byte load inside one aligned
-// 32-byte sector.
+// A plain call (stepped by k_pgd_rows, which streams rows) packs the records
+// into 24 bytes; the served form's shared loop (k_pgd_step over a table of
+// groups) pads them to 32, so a partner gather is one 16-byte and one 8-byte
+// load inside one aligned 32-byte sector.
 constexpr int kPStrideRows = 3, kPStrideStep = 4;
 __device__ inline void load_p(const double *P, size_t i, int stride, double &x, double &y,
                               double &z) {
@@ -147,7 +147,7 @@ struct PgdBufs {
   const uint32_t *row_ptr, *col;
   size_t ninc;            // incidences: twice the active pairs
   double *P0, *P1;        // [ne][pstride]: x, y, z of each row
-  int pstride;            // kPStrideRows: the chunked-only kernel; kPStrideStep: the other
+  int pstride;            // kPStrideRows: a plain call's kernel; kPStrideStep: the shared loop's
   double *m, *v;          // [3][ne]
   const float4 *xo;       // original position of each row
   int32_t *n_active;      // device: jobs not done
@@ -222,9 +222,6 @@ void build_csr(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t, con
                hipStream_t s);
 void launch_pgd_init(const uint32_t *e_list, size_t ne, const float4 *pos, const float4 *rec,
                      double *P0, int stride, float4 *xo, double *m, double *v, hipStream_t s);
-// whether a call with ninc incidences over ne rows steps with the
-// chunked-only kernel (and packs its iterate records)
-bool pgd_rows_kernel(size_t ninc, size_t ne);
 // worklist of the first step: every row; no row hot yet
 void launch_hot_init(const PgdBufs &b, hipStream_t s);
 // After the first step: renumbers each job's rows so that its hot rows come

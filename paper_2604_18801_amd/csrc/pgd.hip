@@ -375,13 +375,6 @@ constexpr int kPgdBlocks = 256 * 4 * PCC_PGD_MIN_WAVES / kPgdWaves;
 int pgd_step_waves(size_t ne) { return blocks_for(ne, 64 * kPgdWaves, kPgdBlocks) * kPgdWaves; }
 int pgd_max_waves() { return kPgdBlocks * kPgdWaves; }
 
-// tiles with at most this many incidences per lane take the chunked
-// evaluation, the others the per-lane walk of whole rows
-constexpr uint32_t kChunkPerLane = 24;
-// calls with at most this many incidences per row on average take the
-// chunked-only kernel (k_pgd_rows)
-constexpr double kRowsKernelDegree = 12.0;
-bool pgd_rows_kernel(size_t ninc, size_t ne) { return (double)ninc <= kRowsKernelDegree * (double)ne; }
 
 // group of a tile (or of a finalize block): the last with base <= x
 template <typename T>
@@ -443,15 +436,17 @@ __device__ inline uint64_t dbits(double x) { return (uint64_t)__double_as_longlo
 // iterates, the violation counts and the loss are exactly those of
 // evaluating every row in every step.
 //
-// Evaluation.  The tile's incidences, row after row, are cut into 64 runs
+// Evaluation.  The tile's incidences, row after row, go to the lanes 64 at
+// a time (a chunk): each lane gathers one partner and evaluates one
+// constraint, and the row's own lane adds the violated terms of its row in
+// column order, so every gradient is summed in the oracle's order.  Two
+// chunks are in flight.  The gradients go through LDS to the Adam step and
+// the projection, where lane r takes row r (coalesced row reads and
+// writes).  Counts stay in registers until the wave moves to another job or
+// finishes.  The partners of the rows that turn hot are marked over 64 runs
 // of about equal length at row boundaries: lane L takes the rows whose
 // first incidence falls in [L T / 64, (L + 1) T / 64) (T incidences in the
-// tile), so every row is walked by one lane, in partner order, and its
-// gradient is summed in exactly that order.  Each lane keeps the column
-// entry two incidences ahead and the partner position one ahead in flight.
-// The gradients go through LDS to the Adam step and the projection, where
-// lane r takes row r (coalesced row reads and writes).  Counts stay in
-// registers until the wave moves to another job or finishes.
+// tile).
 __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES)
     k_pgd_step(const PgdGroups *__restrict__ G) {
   // LDS of one wave: one struct, so that every access is the wave's base
@@ -520,7 +515,8 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES)
     const double bm = J.bm, bp = J.bp, bm2 = J.bm2, bp2 = J.bp2;
     const bool multi = J.nthr > 1;
     // the row's position and incidence range go to LDS; its Adam state is
-    // loaded after the walk (fewer live registers, more waves in flight)
+    // loaded after the evaluation (fewer live registers, more waves in
+    // flight)
     uint32_t total;
     {
       size_t e = 0;
@@ -625,7 +621,8 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES)
     auto gather = [&](uint32_t col, double &x, double &y, double &z) {
       load_p(Pc, col & kColRow, kPStrideStep, x, y, z);
     };
-    // this lane's rows [r0, r1) in the balanced walk: those whose first
+    // this lane's rows [r0, r1) in the balanced split of the tile's
+    // incidences (the partner marking below walks them): those whose first
     // incidence lies in [ta, tb)
     const uint32_t ta = (uint32_t)(((uint64_t)lane * total + 63u) / 64u);
     const uint32_t tb = (uint32_t)(((uint64_t)(lane + 1) * total + 63u) / 64u);
@@ -642,12 +639,11 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES)
     };
     const int r0 = first_at(ta), r1 = first_at(tb);
     const uint32_t fA = S.vb[r0], fB = S.vb[r1];
-    if (total <= 64u * kChunkPerLane) {
-      // Few incidences per lane: they are spread over the lanes 64 at a
-      // time (one partner gather per lane, two chunks in flight), each
-      // lane leaves its term in LDS and the row's own lane adds the terms
-      // of its row in column order.  A long row then costs one lane a few
-      // LDS adds instead of a lane walking it while the others wait.
+    {
+      // The tile's incidences are spread over the lanes 64 at a time (one
+      // partner gather per lane, two chunks in flight), each lane leaves
+      // its term in LDS and the row's own lane adds the violated terms of
+      // its row in column order.
       double gx = 0.0, gy = 0.0, gz = 0.0;
       bool hrow = false;
       const uint32_t vb = S.vb[lane], vend = S.vb[lane < 63 ? lane + 1 : 64];
@@ -715,68 +711,6 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES)
         S.gz[lane] = gz;
         S.hit[lane] = hrow ? 1 : 0;
       }
-    } else if (fA < fB) {
-      // Many incidences per lane: each lane walks its run of whole rows,
-      // in partner order, the column entry two incidences ahead and the
-      // partner position one ahead in flight.
-      // row of incidence f (rows only move forward; empty rows are skipped)
-      auto row_of = [&](int r, uint32_t f) {
-        while (S.vb[r + 1] <= f) ++r;
-        return r;
-      };
-      // the row being summed and its own data
-      int rr = row_of(r0, fA);
-      uint32_t rend = S.vb[rr + 1];
-      uint32_t er = S.e[rr];
-      double rx = S.px[rr], ry = S.py[rr], rz = S.pz[rr];
-      double gx = 0.0, gy = 0.0, gz = 0.0;
-      bool hrow = false;
-      uint32_t col_a = B.col[S.base[rr] + fA];
-      double ax, ay, az;
-      gather(col_a, ax, ay, az);
-      int rb = rr;
-      uint32_t col_b = 0;
-      if (fA + 1 < fB) {
-        rb = row_of(rr, fA + 1);
-        col_b = B.col[S.base[rb] + fA + 1];
-      }
-      for (uint32_t f = fA; f < fB; ++f) {
-        const uint32_t col = col_a;
-        const double ox = ax, oy = ay, oz = az;
-        if (f + 1 < fB) {
-          col_a = col_b;
-          gather(col_a, ax, ay, az);
-        }
-        if (f + 2 < fB) {
-          rb = row_of(rb, f + 2);
-          col_b = B.col[S.base[rb] + f + 2];
-        }
-        double tx, ty, tz;
-        if (eval(col, ox, oy, oz, rx, ry, rz, er, tx, ty, tz)) {
-          gx += tx;
-          gy += ty;
-          gz += tz;
-          hrow = true;
-        }
-        if (f + 1 == rend) {
-          S.gx[rr] = gx;
-          S.gy[rr] = gy;
-          S.gz[rr] = gz;
-          S.hit[rr] = hrow ? 1 : 0;
-          if (f + 1 < fB) {
-            rr = row_of(rr + 1, f + 1);
-            rend = S.vb[rr + 1];
-            er = S.e[rr];
-            rx = S.px[rr];
-            ry = S.py[rr];
-            rz = S.pz[rr];
-            gx = 0.0;
-            gy = 0.0;
-            gz = 0.0;
-            hrow = false;
-          }
-        }
-      }
     }
     wave_sync();
     bool mark = false;
@@ -834,8 +768,8 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES)
     if (__ballot(mark)) {
       S.mk[lane] = mark ? 1 : 0;
       wave_sync();
-      // the same runs as the evaluation, walked in step by every lane (the
-      // appends below take a wave-wide ballot)
+      // the balanced runs, walked in step by every lane (the appends below
+      // take a wave-wide ballot)
       unsigned long long run = fB - fA;
 #pragma unroll
       for (int d = 32; d >= 1; d >>= 1) {
@@ -897,8 +831,8 @@ __device__ inline void flush_rows(const PgdBufs &B, int job, int lslot,
   loss = 0.0;
 }
 
-// The step of a call whose rows have few incidences (one group, passed by
-// value): the chunked evaluation alone.  Each wave walks tiles of up to 64
+// The step of a plain call (one group, passed by value, packed iterate
+// records).  Each wave walks tiles of up to 64
 // rows of one job's worklist (tiles never straddle two jobs, so the job and
 // its constants are wave-uniform).
 //
@@ -1446,9 +1380,8 @@ void launch_pgd_step(const PgdGroups *g, const PgdBufs &b, hipStream_t s) {
   if (b.ne) {
     // the loss slots were sized for this many waves
     if (b.nwaves != pgd_step_waves(b.ne)) throw Error(-3, "PGD step grid differs from its loss slots");
-    // few incidences per row on average (packed records): the chunked
-    // kernel with the buffers as its argument; else the kernel with both
-    // evaluations
+    // a plain call (packed records): the kernel with the buffers as its
+    // argument; a call in the shared loop: the kernel over the group table
     if (b.pstride == kPStrideRows)
       k_pgd_rows<<<b.nwaves / kPgdWaves, 64 * kPgdWaves, 0, s>>>(b);
     else if (b.pstride == kPStrideStep)

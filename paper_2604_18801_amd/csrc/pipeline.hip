@@ -999,10 +999,10 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   gb.row_ptr = row_ptr;
   gb.col = col;
   gb.ninc = 2 * na;
-  // the served form's shared loop runs only the kernel with both
-  // evaluations, which reads padded records
+  // the served form's shared loop runs the kernel over the group table,
+  // which reads padded records
   const bool engine_loop = C.engine && J <= kMaxGroupJobs;
-  gb.pstride = pgd_rows_kernel(gb.ninc, ne) && !engine_loop ? kPStrideRows : kPStrideStep;
+  gb.pstride = engine_loop ? kPStrideStep : kPStrideRows;
   gb.P0 = dev<double>(ar, (size_t)gb.pstride * ne);
   gb.P1 = dev<double>(ar, (size_t)gb.pstride * ne);
   gb.m = dev<double>(ar, 3 * (size_t)ne);
