@@ -11,7 +11,7 @@ namespace pcc {
 // final position of row e of job `job`
 __device__ inline double3 final_pos(const EncBufs &b, int job, size_t e) {
   double3 p;
-  load_p((b.loop[job].t & 1) ? b.P1 : b.P0, e, b.pstride, p.x, p.y, p.z);
+  load_p((b.loop[job].t & 1) ? b.P1 : b.P0, e, p.x, p.y, p.z);
   return p;
 }
 

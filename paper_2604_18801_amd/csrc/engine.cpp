@@ -46,7 +46,6 @@ class PgdEngine {
   }
 
   void run(const PgdBufs &gb, int32_t active) {
-    if (gb.pstride != kPStrideStep) throw Error(-3, "shared PGD loop: packed iterate records");
     Member m;
     m.b = gb;
     m.active = active;

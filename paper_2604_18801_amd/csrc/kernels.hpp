@@ -105,36 +105,21 @@ int64_t boruvka(uint64_t *key, uint32_t *u, uint32_t *v, size_t ncand, uint32_t 
                 uint32_t *out_i, uint32_t *out_j, uint8_t *out_t, Arena &ar, hipStream_t s);
 
 // pgd.hip
-// Iterates of the PGD loop: one record of x, y, z float64 per editable row.
-// A plain call (stepped by k_pgd_rows, which streams rows) packs the records
-// into 24 bytes; the served form's shared loop (k_pgd_step over a table of
-// groups) pads them to 32, so a partner gather is one 16-byte and one 8-byte
-// load inside one aligned 32-byte sector.
-constexpr int kPStrideRows = 3, kPStrideStep = 4;
-__device__ inline void load_p(const double *P, size_t i, int stride, double &x, double &y,
-                              double &z) {
-  if (stride == 4) {
-    const double2 a = reinterpret_cast<const double2 *>(P)[2 * i];
-    x = a.x;
-    y = a.y;
-    z = P[4 * i + 2];
-  } else {
-    const double *p = P + (size_t)stride * i;
-    x = p[0];
-    y = p[1];
-    z = p[2];
-  }
+// Iterates of the PGD loop: one packed record of x, y, z float64 per
+// editable row (24 bytes: the step streams rows, and a quarter less per row
+// beat the aligned 32-byte records on every workload measured).
+constexpr int kPStride = 3;
+__device__ inline void load_p(const double *P, size_t i, double &x, double &y, double &z) {
+  const double *p = P + (size_t)kPStride * i;
+  x = p[0];
+  y = p[1];
+  z = p[2];
 }
-__device__ inline void store_p(double *P, size_t i, int stride, double x, double y, double z) {
-  if (stride == 4) {
-    reinterpret_cast<double2 *>(P)[2 * i] = make_double2(x, y);
-    P[4 * i + 2] = z;
-  } else {
-    double *p = P + (size_t)stride * i;
-    p[0] = x;
-    p[1] = y;
-    p[2] = z;
-  }
+__device__ inline void store_p(double *P, size_t i, double x, double y, double z) {
+  double *p = P + (size_t)kPStride * i;
+  p[0] = x;
+  p[1] = y;
+  p[2] = z;
 }
 struct PgdBufs {
   const JobDev *jobs;
@@ -146,8 +131,7 @@ struct PgdBufs {
   size_t ne;
   const uint32_t *row_ptr, *col;
   size_t ninc;            // incidences: twice the active pairs
-  double *P0, *P1;        // [ne][pstride]: x, y, z of each row
-  int pstride;            // kPStrideRows: a plain call's kernel; kPStrideStep: the shared loop's
+  double *P0, *P1;        // [ne][kPStride]: x, y, z of each row
   double *m, *v;          // [3][ne]
   const float4 *xo;       // original position of each row
   int32_t *n_active;      // device: jobs not done
@@ -221,7 +205,7 @@ void build_csr(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t, con
                const float4 *pos, bool pairs_sorted, uint32_t *row_ptr, uint32_t *col, Arena &ar,
                hipStream_t s);
 void launch_pgd_init(const uint32_t *e_list, size_t ne, const float4 *pos, const float4 *rec,
-                     double *P0, int stride, float4 *xo, double *m, double *v, hipStream_t s);
+                     double *P0, float4 *xo, double *m, double *v, hipStream_t s);
 // worklist of the first step: every row; no row hot yet
 void launch_hot_init(const PgdBufs &b, hipStream_t s);
 // After the first step: renumbers each job's rows so that its hot rows come
@@ -249,8 +233,7 @@ struct EncBufs {
   size_t ne, n;
   const uint32_t *e_list;
   const float4 *pos, *rec;
-  const double *P0, *P1;   // [ne][pstride]
-  int pstride;
+  const double *P0, *P1;   // [ne][kPStride]
   uint8_t *flag8;          // [n] global original order
   uint32_t *fpos;          // exclusive scan of flag8
   uint16_t *sym;           // symbols

@@ -296,12 +296,12 @@ void build_csr(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t, con
 }
 
 __global__ void k_pgd_init(const uint32_t *e_list, size_t ne, const float4 *pos, const float4 *rec,
-                           double *P0, int stride, float4 *xo, double *m, double *v) {
+                           double *P0, float4 *xo, double *m, double *v) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne;
        e += (size_t)gridDim.x * blockDim.x) {
     const uint32_t k = e_list[e];
     const float4 r = rec[k];
-    store_p(P0, e, stride, (double)r.x, (double)r.y, (double)r.z);
+    store_p(P0, e, (double)r.x, (double)r.y, (double)r.z);
     xo[e] = pos[k];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -312,9 +312,8 @@ __global__ void k_pgd_init(const uint32_t *e_list, size_t ne, const float4 *pos,
 }
 
 void launch_pgd_init(const uint32_t *e_list, size_t ne, const float4 *pos, const float4 *rec,
-                     double *P0, int stride, float4 *xo, double *m, double *v, hipStream_t s) {
-  if (ne)
-    k_pgd_init<<<blocks_for(ne, 256, 65536), 256, 0, s>>>(e_list, ne, pos, rec, P0, stride, xo, m, v);
+                     double *P0, float4 *xo, double *m, double *v, hipStream_t s) {
+  if (ne) k_pgd_init<<<blocks_for(ne, 256, 65536), 256, 0, s>>>(e_list, ne, pos, rec, P0, xo, m, v);
 }
 
 __global__ void k_loop_init(const JobDev *jobs, JobLoop *loop, int njobs, int32_t *n_active) {
@@ -526,7 +525,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES)
         e = B.wl[eoff + w0 + lane];
         q0 = B.row_ptr[e];
         len = B.row_ptr[e + 1] - q0;
-        load_p(Pc, e, kPStrideStep, pex, pey, pez);
+        load_p(Pc, e, pex, pey, pez);
       }
       uint32_t incl = len;  // inclusive prefix sum of len over the wave
 #pragma unroll
@@ -619,7 +618,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES)
       return true;
     };
     auto gather = [&](uint32_t col, double &x, double &y, double &z) {
-      load_p(Pc, col & kColRow, kPStrideStep, x, y, z);
+      load_p(Pc, col & kColRow, x, y, z);
     };
     // this lane's rows [r0, r1) in the balanced split of the tile's
     // incidences (the partner marking below walks them): those whose first
@@ -760,7 +759,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES)
         // square-root sequences costs registers, hence occupancy
         __builtin_amdgcn_sched_barrier(0);
       }
-      store_p(Pn, e, kPStrideStep, np[0], np[1], np[2]);
+      store_p(Pn, e, np[0], np[1], np[2]);
       // a live row that has not yet done so marks itself and its partners hot
       mark = (moved || S.hit[lane] || state != 0) && hotv != 2;
       if (mark) B.hot[e] = 2;
@@ -831,8 +830,7 @@ __device__ inline void flush_rows(const PgdBufs &B, int job, int lslot,
   loss = 0.0;
 }
 
-// The step of a plain call (one group, passed by value, packed iterate
-// records).  Each wave walks tiles of up to 64
+// The step of a plain call (one group, passed by value).  Each wave walks tiles of up to 64
 // rows of one job's worklist (tiles never straddle two jobs, so the job and
 // its constants are wave-uniform).
 //
@@ -909,7 +907,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_rows(
       e = B.wl[eoff + w0 + lane];
       q0 = B.row_ptr[e];
       len = B.row_ptr[e + 1] - q0;
-      load_p(Pc, e, kPStrideRows, pe.x, pe.y, pe.z);
+      load_p(Pc, e, pe.x, pe.y, pe.z);
     }
     uint32_t incl = len;  // inclusive prefix sum of len over the wave
 #pragma unroll
@@ -960,7 +958,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_rows(
     // two-deep pipeline: while chunk c is evaluated, the partner gather of
     // chunk c + 1 and the column entries of chunk c + 2 are in flight
     auto gather = [&](uint32_t col) {
-      const double *pp = Pc + (size_t)kPStrideRows * (col & kColRow);
+      const double *pp = Pc + (size_t)kPStride * (col & kColRow);
       return make_double3(pp[0], pp[1], pp[2]);
     };
     int r_nx = 0, r_nx2 = 0;
@@ -1110,7 +1108,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_rows(
         // square-root sequences costs registers, hence occupancy
         __builtin_amdgcn_sched_barrier(0);
       }
-      store_p(Pn, e, kPStrideRows, np[0], np[1], np[2]);
+      store_p(Pn, e, np[0], np[1], np[2]);
       // a live row that has not yet done so marks itself and its partners hot
       mark = (moved || hrow || state != 0) && hotv != 2;
       if (mark) B.hot[e] = 2;
@@ -1215,17 +1213,16 @@ struct RowPerm {
   double *nm, *nv;
   float4 *nxo;
   uint32_t *nhot, *ne_list, *nlen, *wl;
-  int stride;  // of the iterate records
 };
 
 __global__ void k_permute_rows(RowPerm R, size_t ne) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne;
        e += (size_t)gridDim.x * blockDim.x) {
     const uint32_t r = R.new_id[e];
-    const size_t S = (size_t)R.stride;
-    for (size_t k = 0; k < S; ++k) {
-      R.nP0[S * r + k] = R.P0[S * e + k];
-      R.nP1[S * r + k] = R.P1[S * e + k];
+#pragma unroll
+    for (int k = 0; k < kPStride; ++k) {
+      R.nP0[(size_t)kPStride * r + k] = R.P0[(size_t)kPStride * e + k];
+      R.nP1[(size_t)kPStride * r + k] = R.P1[(size_t)kPStride * e + k];
     }
     R.nxo[r] = R.xo[e];
 #pragma unroll
@@ -1287,9 +1284,8 @@ void renumber_hot(PgdBufs &b, uint32_t *&e_list, Arena &ar, hipStream_t s) {
   R.hot = b.hot;
   R.e_list = e_list;
   R.row_ptr = b.row_ptr;
-  R.stride = b.pstride;
-  R.nP0 = ar.get<double>((size_t)b.pstride * ne);
-  R.nP1 = ar.get<double>((size_t)b.pstride * ne);
+  R.nP0 = ar.get<double>((size_t)kPStride * ne);
+  R.nP1 = ar.get<double>((size_t)kPStride * ne);
   R.nm = ar.get<double>(3 * ne);
   R.nv = ar.get<double>(3 * ne);
   R.nxo = ar.get<float4>(ne);
@@ -1380,14 +1376,10 @@ void launch_pgd_step(const PgdGroups *g, const PgdBufs &b, hipStream_t s) {
   if (b.ne) {
     // the loss slots were sized for this many waves
     if (b.nwaves != pgd_step_waves(b.ne)) throw Error(-3, "PGD step grid differs from its loss slots");
-    // a plain call (packed records): the kernel with the buffers as its
-    // argument; a call in the shared loop: the kernel over the group table
-    if (b.pstride == kPStrideRows)
-      k_pgd_rows<<<b.nwaves / kPgdWaves, 64 * kPgdWaves, 0, s>>>(b);
-    else if (b.pstride == kPStrideStep)
-      k_pgd_step<<<b.nwaves / kPgdWaves, 64 * kPgdWaves, 0, s>>>(g);
-    else
-      throw Error(-3, "PGD iterate records of an unknown size");
+    // one call: the kernel with the buffers as its argument (the shared
+    // loop launches the kernel over the group table instead)
+    (void)g;
+    k_pgd_rows<<<b.nwaves / kPgdWaves, 64 * kPgdWaves, 0, s>>>(b);
   }
 }
 void launch_pgd_finalize(const PgdGroups *g, const PgdBufs &b, hipStream_t s) {

@@ -999,12 +999,9 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   gb.row_ptr = row_ptr;
   gb.col = col;
   gb.ninc = 2 * na;
-  // the served form's shared loop runs the kernel over the group table,
-  // which reads padded records
   const bool engine_loop = C.engine && J <= kMaxGroupJobs;
-  gb.pstride = engine_loop ? kPStrideStep : kPStrideRows;
-  gb.P0 = dev<double>(ar, (size_t)gb.pstride * ne);
-  gb.P1 = dev<double>(ar, (size_t)gb.pstride * ne);
+  gb.P0 = dev<double>(ar, (size_t)kPStride * ne);
+  gb.P1 = dev<double>(ar, (size_t)kPStride * ne);
   gb.m = dev<double>(ar, 3 * (size_t)ne);
   gb.v = dev<double>(ar, 3 * (size_t)ne);
   float4 *xo = dev<float4>(ar, ne);
@@ -1030,7 +1027,7 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
     gb.lp_off = d_lo;
     gb.lossp = dev<double>(ar, (size_t)lo[J]);
   }
-  launch_pgd_init(e_list, ne, pos, rec, gb.P0, gb.pstride, xo, gb.m, gb.v, s);
+  launch_pgd_init(e_list, ne, pos, rec, gb.P0, xo, gb.m, gb.v, s);
   launch_hot_init(gb, s);
   launch_loop_init(d_jobs, gb.loop, J, gb.n_active, s);
   // the call's PGD state as the one group of the step's group table
@@ -1170,7 +1167,6 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   eb.rec = rec;
   eb.P0 = gb.P0;
   eb.P1 = gb.P1;
-  eb.pstride = gb.pstride;
   eb.flag8 = dev<uint8_t>(ar, n);
   eb.fpos = dev<uint32_t>(ar, n);
   uint32_t *nflag_dev = dev<uint32_t>(ar, 1);
