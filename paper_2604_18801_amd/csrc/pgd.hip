@@ -830,9 +830,9 @@ __device__ inline void flush_rows(const PgdBufs &B, int job, int lslot,
   loss = 0.0;
 }
 
-// The step of a plain call (one group, passed by value).  Each wave walks tiles of up to 64
-// rows of one job's worklist (tiles never straddle two jobs, so the job and
-// its constants are wave-uniform).
+// The step of a plain call (one group, passed by value).  Each wave walks
+// tiles of up to 64 rows of one job's worklist (tiles never straddle two
+// jobs, so the job and its constants are wave-uniform).
 //
 // Hot rows.  A row whose constraints are all satisfied, whose Adam moments
 // are zero and whose position lies in the box is a fixed point of the step
