@@ -133,7 +133,7 @@ struct PgdBufs {
   size_t ninc;            // incidences: twice the active pairs
   double *P0, *P1;        // [ne][kPStride]: x, y, z of each row
   double *m, *v;          // [3][ne]
-  const float4 *xo;       // original position of each row
+  const float *xo;        // [ne][3] original position of each row
   int32_t *n_active;      // device: jobs not done
   // Hot rows (the only rows evaluated after the first step), per job in
   // wl[e_off[j] .. e_off[j] + wl_n[j]); a step processes the first
@@ -143,6 +143,7 @@ struct PgdBufs {
   uint32_t *wl;       // [ne]
   uint32_t *wl_n;     // [njobs]
   uint32_t *wl_step;  // [njobs]
+  uint32_t *wl_id;    // [njobs] leading entries with wl[e_off[j] + i] = e_off[j] + i
   uint64_t *inc_n;    // [njobs] incidences of the rows in wl[0 .. wl_n)
   uint64_t *inc_step; // [njobs] incidences of the rows a step processes
   // violation count of one evaluation: per job, acc_slots partial sums,
@@ -205,7 +206,7 @@ void build_csr(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t, con
                const float4 *pos, bool pairs_sorted, uint32_t *row_ptr, uint32_t *col, Arena &ar,
                hipStream_t s);
 void launch_pgd_init(const uint32_t *e_list, size_t ne, const float4 *pos, const float4 *rec,
-                     double *P0, float4 *xo, double *m, double *v, hipStream_t s);
+                     double *P0, float *xo, double *m, double *v, hipStream_t s);
 // worklist of the first step: every row; no row hot yet
 void launch_hot_init(const PgdBufs &b, hipStream_t s);
 // After the first step: renumbers each job's rows so that its hot rows come

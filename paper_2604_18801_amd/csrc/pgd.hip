@@ -296,13 +296,16 @@ void build_csr(const uint32_t *a_i, const uint32_t *a_j, const uint8_t *a_t, con
 }
 
 __global__ void k_pgd_init(const uint32_t *e_list, size_t ne, const float4 *pos, const float4 *rec,
-                           double *P0, float4 *xo, double *m, double *v) {
+                           double *P0, float *xo, double *m, double *v) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne;
        e += (size_t)gridDim.x * blockDim.x) {
     const uint32_t k = e_list[e];
     const float4 r = rec[k];
     store_p(P0, e, (double)r.x, (double)r.y, (double)r.z);
-    xo[e] = pos[k];
+    const float4 x = pos[k];
+    xo[3 * e] = x.x;
+    xo[3 * e + 1] = x.y;
+    xo[3 * e + 2] = x.z;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       m[a * ne + e] = 0.0;
@@ -312,7 +315,7 @@ __global__ void k_pgd_init(const uint32_t *e_list, size_t ne, const float4 *pos,
 }
 
 void launch_pgd_init(const uint32_t *e_list, size_t ne, const float4 *pos, const float4 *rec,
-                     double *P0, float4 *xo, double *m, double *v, hipStream_t s) {
+                     double *P0, float *xo, double *m, double *v, hipStream_t s) {
   if (ne) k_pgd_init<<<blocks_for(ne, 256, 65536), 256, 0, s>>>(e_list, ne, pos, rec, P0, xo, m, v);
 }
 
@@ -598,10 +601,10 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES)
           uz = dz / d;
         } else {
           // coincident points: take the direction of the original pair
-          const float4 a = B.xo[er], b = B.xo[o];
-          const double ox2 = wrapd((double)a.x - (double)b.x, L0, h0);
-          const double oy2 = wrapd((double)a.y - (double)b.y, L1, h1);
-          const double oz2 = wrapd((double)a.z - (double)b.z, L2, h2);
+          const float *a = B.xo + 3 * (size_t)er, *b = B.xo + 3 * (size_t)o;
+          const double ox2 = wrapd((double)a[0] - (double)b[0], L0, h0);
+          const double oy2 = wrapd((double)a[1] - (double)b[1], L1, h1);
+          const double oz2 = wrapd((double)a[2] - (double)b[2], L2, h2);
           const double od = sqrt((ox2 * ox2 + oy2 * oy2) + oz2 * oz2);
           ux = ox2 / od;
           uy = oy2 / od;
@@ -716,7 +719,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES)
     if (valid) {
       const size_t e = S.e[lane];
       const uint32_t hotv = B.hot[e];
-      const float4 x = B.xo[e];
+      const float *x = B.xo + 3 * e;
       double mo[3], vo[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
@@ -733,7 +736,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES)
                    omb2 = J.one_m_beta2, aeps = J.adam_eps, xip = J.xi_p;
       const double g[3] = {S.gx[lane], S.gy[lane], S.gz[lane]};
       const double p[3] = {S.px[lane], S.py[lane], S.pz[lane]};
-      const double xs[3] = {(double)x.x, (double)x.y, (double)x.z};
+      const double xs[3] = {(double)x[0], (double)x[1], (double)x[2]};
       double np[3];
       uint64_t state = 0;
       bool moved = false;
@@ -883,6 +886,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_rows(
     const int64_t w0 = (tile - B.tile_off[job]) * 64;  // first worklist entry of the tile
     const int64_t left = (int64_t)B.wl_step[job] - w0;
     if (left <= 0) continue;
+    const uint32_t wl_ident = B.wl_id[job];
     if (job != cjob) {
       flush_rows(B, cjob, cslot, viol, loss);
       cjob = job;
@@ -904,7 +908,10 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_rows(
     uint32_t q0 = 0, len = 0;
     double4 pe = make_double4(0.0, 0.0, 0.0, 0.0);
     if (valid) {
-      e = B.wl[eoff + w0 + lane];
+      // the worklist's leading entries are the identity (every row before
+      // the first step, the renumbered hot rows after it): no read
+      const int64_t wi = w0 + lane;
+      e = wi < (int64_t)wl_ident ? (size_t)(eoff + wi) : (size_t)B.wl[eoff + wi];
       q0 = B.row_ptr[e];
       len = B.row_ptr[e + 1] - q0;
       load_p(Pc, e, pe.x, pe.y, pe.z);
@@ -1016,10 +1023,10 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_rows(
               uz = dz / d;
             } else {
               // coincident points: take the direction of the original pair
-              const float4 a = B.xo[er], b = B.xo[o];
-              const double ox = wrapd((double)a.x - (double)b.x, L0, h0);
-              const double oy = wrapd((double)a.y - (double)b.y, L1, h1);
-              const double oz = wrapd((double)a.z - (double)b.z, L2, h2);
+              const float *a = B.xo + 3 * (size_t)er, *b = B.xo + 3 * (size_t)o;
+              const double ox = wrapd((double)a[0] - (double)b[0], L0, h0);
+              const double oy = wrapd((double)a[1] - (double)b[1], L1, h1);
+              const double oz = wrapd((double)a[2] - (double)b[2], L2, h2);
               const double od = sqrt((ox * ox + oy * oy) + oz * oz);
               ux = ox / od;
               uy = oy / od;
@@ -1065,7 +1072,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_rows(
     bool mark = false;
     if (valid) {
       const uint32_t hotv = B.hot[e];
-      const float4 x = B.xo[e];
+      const float *x = B.xo + 3 * e;
       double mo[3], vo[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
@@ -1082,7 +1089,7 @@ __global__ void __launch_bounds__(64 * kPgdWaves, PCC_PGD_MIN_WAVES) k_pgd_rows(
                    omb2 = J.one_m_beta2, aeps = J.adam_eps, xip = J.xi_p;
       const double g[3] = {gx, gy, gz};
       const double p[3] = {s_px[w][lane], s_py[w][lane], s_pz[w][lane]};
-      const double xs[3] = {(double)x.x, (double)x.y, (double)x.z};
+      const double xs[3] = {(double)x[0], (double)x[1], (double)x[2]};
       double np[3];
       uint64_t state = 0;
       bool moved = false;
@@ -1171,6 +1178,7 @@ __global__ void k_hot_init(PgdBufs B, size_t n) {
     if (i < (size_t)B.njobs) {
       B.wl_n[i] = 0;
       B.wl_step[i] = (uint32_t)(B.e_off[i + 1] - B.e_off[i]);
+      B.wl_id[i] = B.wl_step[i];
       B.inc_n[i] = 0;
       B.inc_step[i] = B.ne ? (uint64_t)B.row_ptr[B.e_off[i + 1]] - B.row_ptr[B.e_off[i]] : 0;
     }
@@ -1207,11 +1215,11 @@ struct RowPerm {
   const uint32_t *new_id;
   const double *P0, *P1;
   const double *m, *v;
-  const float4 *xo;
+  const float *xo;
   const uint32_t *hot, *e_list, *row_ptr;
   double *nP0, *nP1;
   double *nm, *nv;
-  float4 *nxo;
+  float *nxo;
   uint32_t *nhot, *ne_list, *nlen, *wl;
 };
 
@@ -1224,7 +1232,8 @@ __global__ void k_permute_rows(RowPerm R, size_t ne) {
       R.nP0[(size_t)kPStride * r + k] = R.P0[(size_t)kPStride * e + k];
       R.nP1[(size_t)kPStride * r + k] = R.P1[(size_t)kPStride * e + k];
     }
-    R.nxo[r] = R.xo[e];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) R.nxo[3 * (size_t)r + k] = R.xo[3 * e + k];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       R.nm[(size_t)k * ne + r] = R.m[(size_t)k * ne + e];
@@ -1251,13 +1260,15 @@ __global__ void k_permute_cols(const uint32_t *new_id, const uint32_t *row_ptr, 
 
 __global__ void k_hot_counts(const uint32_t *pos, const uint32_t *total, const uint32_t *nrow_ptr,
                              const int64_t *e_off, int njobs, size_t ne, uint32_t *wl_n,
-                             uint32_t *wl_step, uint64_t *inc_n, uint64_t *inc_step) {
+                             uint32_t *wl_step, uint32_t *wl_id, uint64_t *inc_n,
+                             uint64_t *inc_step) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= njobs) return;
   const int64_t s = e_off[j], t = e_off[j + 1];
   const uint32_t a = s < (int64_t)ne ? pos[s] : *total, b = t < (int64_t)ne ? pos[t] : *total;
   wl_n[j] = b - a;
   wl_step[j] = b - a;
+  wl_id[j] = b - a;  // the renumbering leaves the worklist the identity
   // the hot rows are now e_off[j] .. e_off[j] + (b - a) - 1
   const uint64_t inc = (uint64_t)nrow_ptr[s + (b - a)] - nrow_ptr[s];
   inc_n[j] = inc;
@@ -1288,7 +1299,7 @@ void renumber_hot(PgdBufs &b, uint32_t *&e_list, Arena &ar, hipStream_t s) {
   R.nP1 = ar.get<double>((size_t)kPStride * ne);
   R.nm = ar.get<double>(3 * ne);
   R.nv = ar.get<double>(3 * ne);
-  R.nxo = ar.get<float4>(ne);
+  R.nxo = ar.get<float>(3 * ne);
   R.nhot = ar.get<uint32_t>(ne);
   R.ne_list = ar.get<uint32_t>(ne);
   R.nlen = ar.get<uint32_t>(ne);
@@ -1299,7 +1310,8 @@ void renumber_hot(PgdBufs &b, uint32_t *&e_list, Arena &ar, hipStream_t s) {
   uint32_t *ncol = ar.get<uint32_t>(b.ninc ? b.ninc : 1);
   k_permute_cols<<<nb, 256, 0, s>>>(new_id, b.row_ptr, b.col, nrow_ptr, ne, ncol);
   k_hot_counts<<<(b.njobs + 255) / 256, 256, 0, s>>>(pos, total, nrow_ptr, b.e_off, b.njobs, ne,
-                                                      b.wl_n, b.wl_step, b.inc_n, b.inc_step);
+                                                      b.wl_n, b.wl_step, b.wl_id, b.inc_n,
+                                                      b.inc_step);
   b.P0 = R.nP0;
   b.P1 = R.nP1;
   b.m = R.nm;

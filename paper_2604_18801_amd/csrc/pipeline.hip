@@ -1004,13 +1004,14 @@ pcc_status run_batch_impl(Context &C, const pcc_job *jobs, int njobs_in, pcc_job
   gb.P1 = dev<double>(ar, (size_t)kPStride * ne);
   gb.m = dev<double>(ar, 3 * (size_t)ne);
   gb.v = dev<double>(ar, 3 * (size_t)ne);
-  float4 *xo = dev<float4>(ar, ne);
+  float *xo = dev<float>(ar, 3 * (size_t)ne);
   gb.xo = xo;
   gb.n_active = dev<int32_t>(ar, 1);
   gb.hot = dev<uint32_t>(ar, ne);
   gb.wl = dev<uint32_t>(ar, ne);
   gb.wl_n = dev<uint32_t>(ar, J);
   gb.wl_step = dev<uint32_t>(ar, J);
+  gb.wl_id = dev<uint32_t>(ar, J);
   gb.inc_n = dev<uint64_t>(ar, J);
   gb.inc_step = dev<uint64_t>(ar, J);
   gb.acc_slots = 64;
