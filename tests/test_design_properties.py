@@ -142,3 +142,117 @@ def test_sum_of_violated_terms_equals_the_full_sum_bitwise():
         assert full.tobytes() == some.tobytes()
         # a running sum that starts at +0.0 never becomes -0.0
         assert not (some == 0.0 and np.signbit(some))
+
+
+# ---------------------------------------------------------------------------
+# Float32 classification of staged partners (dense pair units): the partner is
+# staged as ps = fl(pj + shift), the displacement is fl(pi - ps) per axis and
+# d^2 = fma(dz, dz, fma(dy, dy, fl(dx * dx))) in float32.  Outside the guard
+# bands [(sqrt T - e)^2 (1 - 2^-17), (sqrt T + e)^2 (1 + 2^-17)] with
+# e = 4 ulp_f32(max|x| + L + 1) the float32 class must be the exact float64
+# class; and the gap to the box of a unit's homes, computed the same way, is
+# never above any home's own float32 distance (no partner within r_v culled).
+# Float32 rounding and the fused multiply-add are emulated exactly with
+# rationals.
+# ---------------------------------------------------------------------------
+from fractions import Fraction
+
+
+def _round_f32(x):
+    """x (a Fraction) rounded to the nearest float32, ties to even."""
+    if x == 0:
+        return Fraction(0)
+    s = -1 if x < 0 else 1
+    a = abs(x)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    if Fraction(2) ** e > a:
+        e -= 1
+    e = max(e, -126)                    # subnormals share the smallest exponent
+    q = a / Fraction(2) ** (e - 23)     # 24-bit significand scale
+    n, r = divmod(q.numerator, q.denominator)
+    if 2 * r > q.denominator or (2 * r == q.denominator and n % 2 == 1):
+        n += 1
+    return s * Fraction(n) * Fraction(2) ** (e - 23)
+
+
+def _f32(x):
+    return Fraction(float(np.float32(x)))
+
+
+def _ulp_f32(x):
+    return 2.0 ** (np.floor(np.log2(x)) - 23)
+
+
+def _band(T, e):
+    r = np.sqrt(T)
+    lo = (r - e) ** 2 * (1 - 2.0 ** -17) if r > 2 * e else -1.0
+    hi = (r + e) ** 2 * (1 + 2.0 ** -17)
+    flo, fhi = np.float32(lo), np.float32(hi)
+    if float(flo) > lo:
+        flo = np.nextafter(flo, np.float32(-np.inf))
+    if float(fhi) < hi:
+        fhi = np.nextafter(fhi, np.float32(np.inf))
+    return Fraction(float(flo)), Fraction(float(fhi))
+
+
+def _d2_staged(pi, pj, sh):
+    d = [_round_f32(pi[a] - _round_f32(pj[a] + sh[a])) for a in range(3)]
+    return _round_f32(d[2] * d[2] + _round_f32(d[1] * d[1] + _round_f32(d[0] * d[0])))
+
+
+def test_staged_float32_classes_match_the_exact_ones_outside_the_bands():
+    rng = np.random.default_rng(11)
+    L, b, xi = 512.0, 0.2, 0.05
+    rs, rv = b - 2 * np.sqrt(3) * xi, b + 2 * np.sqrt(3) * xi
+    e = 4 * _ulp_f32(L + L + 1)
+    bands = [_band(T * T, e) for T in (rs, b, rv)]
+    (rs_lo, rs_hi), (b_lo, b_hi), (rv_lo, rv_hi) = bands
+    outside = 0
+    for trial in range(3000):
+        T = (rs, b, rv)[trial % 3]
+        d = T * (1 + rng.normal() * 1e-4 * 10 ** rng.integers(0, 3))
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        # the home near a periodic face on x, so that some partners lie across it
+        pi = np.array([np.float32(rng.uniform(0, L)) for _ in range(3)], np.float32)
+        pi[0] = np.float32(L - 0.05) if trial % 2 else np.float32(0.05)
+        q = pi.astype(np.float64) + d * u
+        sh = np.where(q >= L, L, np.where(q < 0, -L, 0.0))
+        pj = (q - sh).astype(np.float32)                # the partner inside [0, L)
+        pj = np.where(pj >= np.float32(L), np.float32(0.0), pj)
+        # the exact predicate: float64 minimum image of the float32 coordinates
+        dx = pi.astype(np.float64) - pj.astype(np.float64)
+        dx -= L * np.round(dx / L)
+        exact = Fraction(float((dx[0] * dx[0] + dx[1] * dx[1]) + dx[2] * dx[2]))
+        d2f = _d2_staged([_f32(x) for x in pi], [_f32(x) for x in pj], [Fraction(s) for s in sh])
+        R2 = [Fraction(float(r * r)) for r in (rs, b, rv)]
+        if d2f > rv_hi:
+            assert exact > R2[2]
+        elif d2f < rs_lo:
+            assert exact <= R2[0]
+        elif rs_hi < d2f < b_lo:
+            assert R2[0] < exact <= R2[1]
+        elif b_hi < d2f < rv_lo:
+            assert R2[1] < exact <= R2[2]
+        else:
+            continue
+        outside += 1
+    assert outside > 100
+
+
+def test_box_gap_never_exceeds_a_homes_distance():
+    rng = np.random.default_rng(12)
+    for trial in range(400):
+        homes = rng.uniform(100, 100.5, size=(int(rng.integers(1, 9)), 3)).astype(np.float32)
+        ps = (homes[0] + rng.normal(size=3).astype(np.float32) * np.float32(0.4)).astype(np.float32)
+        lo, hi = homes.min(0), homes.max(0)
+        gap = []
+        for a in range(3):
+            g1 = _round_f32(_f32(lo[a]) - _f32(ps[a]))
+            g2 = _round_f32(_f32(ps[a]) - _f32(hi[a]))
+            gap.append(max(g1, g2, Fraction(0)))
+        bd2 = _round_f32(gap[2] * gap[2] + _round_f32(gap[1] * gap[1] + _round_f32(gap[0] * gap[0])))
+        for h in homes:
+            d = [_round_f32(_f32(h[a]) - _f32(ps[a])) for a in range(3)]
+            d2 = _round_f32(d[2] * d[2] + _round_f32(d[1] * d[1] + _round_f32(d[0] * d[0])))
+            assert bd2 <= d2
